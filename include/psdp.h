@@ -1,0 +1,247 @@
+/*
+ * psdp.h - C ABI of the MI355X (gfx950) vectorized-PSDP library.
+ *
+ * Problem (Huo and Gu, "A Vectorized Positive Semidefinite Penalty Method for
+ * Unconstrained Binary Quadratic Programming", Section 2, eq. (bqp)):
+ *     minimize f(x) = x^T Q x + b^T x  over x in {0,1}^n,  Q real symmetric.
+ * The method replaces the binary constraint by the box 0 <= x <= 1 and the
+ * penalty h(x, p) = f(x) + sum_i p_i (x_i - x_i^2) (eq. (p1)), solves the
+ * box-constrained subproblem with projected alternating Barzilai-Borwein
+ * steps (Algorithm 2) or a diagonal proximal-point step (Algorithm 1), and
+ * raises p by alpha * z with alpha = eta * lambda_min(Z^-1/2 Qbar_II Z^-1/2)
+ * (eqs. (pp1), (alpha1)) until x is binary (Algorithm 3).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns psdp_status; 0 is success, negatives are errors.
+ *    psdp_last_error() returns a thread-local message for the last failure.
+ *  - Pointers marked "device" are device memory owned by the caller; the
+ *    library never frees or retains them after the call returns. Pointers
+ *    marked "host" are host memory.
+ *  - Matrices are dense. Q is row-major n x n with leading dimension ldq (for
+ *    a symmetric Q row- and column-major coincide). Batches of vectors
+ *    ("X", n x B) are column-major with leading dimension n: column c is the
+ *    contiguous vector x_c (a torch tensor of shape (B, n)).
+ *  - Work is enqueued on `stream` (0 = the null stream). The solve entry
+ *    points block until their result is on the host side of their outputs'
+ *    stream order (they synchronize `stream` before returning); the
+ *    evaluation, adjoint and objective entry points are stream-ordered and
+ *    return without synchronizing.
+ *  - No C++ exception crosses this boundary and nothing aborts. Argument
+ *    validation happens before any device work. Reaching an iteration cap is
+ *    not an error: the status is PSDP_OK and psdp_stats.exit_reason says why
+ *    the solve stopped.
+ *  - Calls are serialized per process by an internal lock (the solve
+ *    workspace is cached per device and reused across calls).
+ */
+#ifndef PSDP_H
+#define PSDP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSDP_OK = 0,
+    PSDP_E_INVALID = -1,        /* bad size, null pointer, bad enum, bad params */
+    PSDP_E_NOT_SYMMETRIC = -2,  /* Q is not exactly symmetric */
+    PSDP_E_NONFINITE = -3,      /* NaN/Inf in an input, or x0 outside [0,1] */
+    PSDP_E_OVERFLOW = -4,       /* exact int64 objective bound would overflow */
+    PSDP_E_DEVICE = -5,         /* HIP runtime error (detail in psdp_last_error) */
+    PSDP_E_NOMEM = -6,          /* device allocation failed */
+    PSDP_E_UNSUPPORTED = -7     /* valid but unsupported combination */
+} psdp_status;
+
+/* Subproblem solver: Algorithm 2 (projected alternating BB) or Algorithm 1
+ * (proximal point with the diagonal H_p of Section 3.1). */
+typedef enum { PSDP_INNER_PABB = 0, PSDP_INNER_PPA = 1 } psdp_inner;
+
+/* Storage/arithmetic type of the Q.X product operands. F64 runs FP64 MFMA /
+ * FP64 FMA; F32 runs FP32 MFMA with FP32 accumulation (batched) or FP32
+ * storage with FP64 accumulation (single instance); BF16 stores Q in bfloat16
+ * and accumulates in FP32/FP64. All other solver state is FP64. */
+typedef enum { PSDP_F64 = 0, PSDP_F32 = 1, PSDP_BF16 = 2 } psdp_dtype;
+
+/* Random symmetric perturbation of Q before the reformation (Section 3.5,
+ * "Random Perturbation"): none, every entry (i <= j, mirrored), or the
+ * diagonal only. */
+typedef enum { PSDP_PERTURB_NONE = 0, PSDP_PERTURB_FULL = 1, PSDP_PERTURB_DIAG = 2 } psdp_perturb;
+
+/* Why a solve stopped. */
+typedef enum {
+    PSDP_EXIT_CONVERGED = 0,   /* max_i min(x_i, 1 - x_i) <= tol_binary (Algorithm 3) */
+    PSDP_EXIT_OUTER_CAP = 1,   /* max_outer penalty updates reached */
+    PSDP_EXIT_STALL = 2        /* stall_outer consecutive subproblems did not move x,
+                                  or the cap was hit with a component at 1/2 */
+} psdp_exit;
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(psdp_params); set by psdp_params_default */
+    int32_t inner;             /* psdp_inner */
+    int32_t qx_dtype;          /* psdp_dtype of the Q.X operands */
+    int32_t perturb;           /* psdp_perturb */
+    int32_t max_inner;         /* subproblem iteration cap (10000, Section 5) */
+    int32_t max_outer;         /* penalty update cap (1000, Section 5) */
+    int32_t stall_outer;       /* no-progress exit after this many non-moving subproblems (2) */
+    int32_t eig_maxit;         /* lambda_min iteration cap (LOBPCG) (500) */
+    int32_t cg_maxit;          /* x^0 linear solve iteration cap (500) */
+    int32_t timing;            /* 1: time every Q.X launch with HIP events (psdp_stats.qx_*) */
+    int32_t poll_sweeps;       /* sweeps enqueued between host polls of the done count (16) */
+    int32_t gemm_variant;      /* batched Q.X tile choice; -1 = autotune (cached per shape) */
+    double tol_kkt;            /* delta of eq. (cret) (1e-5) */
+    double tol_binary;         /* Algorithm 3 loop tolerance (1e-5) */
+    double eta;                /* eq. (alpha1) scaling, 0 < eta < 1 (0.999) */
+    double eps_hp;             /* epsilon in H_p (1e-8) */
+    double lambda_floor_rel;   /* alpha uses max(lambda, lambda_floor_rel * rho) (1e-8) */
+    double alpha_min, alpha_max; /* BB step clamp (1e-30, 1e30) */
+    double sigma;              /* perturbation standard deviation (absolute) (0) */
+    double eig_tol;            /* LOBPCG relative residual tolerance (1e-9) */
+    double cg_tol;             /* x^0 relative residual tolerance (1e-12) */
+    uint64_t seed;             /* perturbation seed */
+} psdp_params;
+
+typedef struct {
+    int32_t exit_reason;       /* psdp_exit */
+    int32_t outer_iters;       /* penalty updates performed */
+    int64_t inner_iters;       /* penalty-gradient evaluations in subproblems */
+    int64_t aux_matvecs;       /* Q products spent on lambda_min and x^0 */
+    double final_cret_rel;     /* cret/rho at the last evaluation */
+    double final_binary_gap;   /* max_i min(x_i, 1 - x_i) of the final iterate */
+    int64_t sweeps;            /* Q.X sweeps of the whole launch (same for every column) */
+    double qx_seconds;         /* summed Q.X kernel time (timing = 1), whole launch */
+    double qx_flops;           /* algorithmic flops of those Q.X launches (2 n^2 per column) */
+    int64_t qx_launches;       /* number of Q.X launches timed */
+} psdp_stats;
+
+/* Fills *p with the defaults listed above. */
+void psdp_params_default(psdp_params *p);
+
+/* Static description of a status code. */
+const char *psdp_status_string(psdp_status s);
+
+/* Thread-local detail of the last error (empty string if none). */
+const char *psdp_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t psdp_version(void);
+
+/*
+ * psdp_solve_i32 - Algorithm 3 on B independent starts of one integer instance.
+ *
+ * Q       device, int32, n x n row-major (ldq = n), exactly symmetric.
+ * b       device, int32, length n.
+ * X0      device, double, n x B column-major, entries in [0,1]; NULL means
+ *         every column starts from x^0 of eq. (gamma) (then B must be 1).
+ * p0      device, double, length n, initial penalty of the reformulated
+ *         problem (Algorithm 3 line 3 sets 0); NULL means 0.
+ * B       number of starts (>= 1). B = 1 runs the single-instance path
+ *         (GEMV Q.x); B > 1 runs all starts together (MFMA Q.X per sweep).
+ * prm     host, parameters (psdp_params_default then edit; NULL = defaults).
+ * xhat    device, uint8, n x B: rounded solutions, x_i = 1 iff x_i > 1/2.
+ * obj     device, int64, length B: f(xhat) on the original Q and b, exact.
+ * X_out   device, double, n x B, nullable: final continuous iterates.
+ * best    host, nullable: index of the smallest objective (lowest index on ties).
+ * stats   host, nullable: array of B psdp_stats.
+ * Errors: PSDP_E_INVALID (n < 1, B < 1, null required pointer, bad params),
+ *         PSDP_E_NOT_SYMMETRIC, PSDP_E_NONFINITE (X0 outside [0,1]),
+ *         PSDP_E_OVERFLOW (n^2 max|Q| + n max|b| >= 2^62),
+ *         PSDP_E_UNSUPPORTED (FULL perturbation with BF16 operands),
+ *         PSDP_E_DEVICE / PSDP_E_NOMEM.
+ * Validation reads Q, b and X0 back to the host once.
+ */
+psdp_status psdp_solve_i32(const int32_t *Q, const int32_t *b, int64_t n,
+                           const double *X0, const double *p0, int32_t B,
+                           const psdp_params *prm, uint8_t *xhat, int64_t *obj,
+                           double *X_out, int32_t *best, psdp_stats *stats,
+                           hipStream_t stream);
+
+/*
+ * psdp_solve_group_i32 - Algorithm 3 on `count` independent instances of
+ * different sizes, all advanced together (one column per instance).
+ *
+ * n       host, int64[count], sizes (>= 1).
+ * Q       host array of `count` device pointers, int32 n_i x n_i row-major.
+ * b       host array of `count` device pointers, int32 length n_i.
+ * seeds   host, uint64[count], nullable: per-instance perturbation seeds
+ *         (NULL uses prm->seed for every instance).
+ * xhat    host array of `count` device pointers, uint8 length n_i.
+ * obj     device, int64[count].
+ * stats   host, nullable: array of `count` psdp_stats.
+ * Every instance starts from its own x^0 (eq. (gamma)) with p^0 = 0.
+ * Errors as psdp_solve_i32.
+ */
+psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n,
+                                 const int32_t *const *Q, const int32_t *const *b,
+                                 const uint64_t *seeds, const psdp_params *prm,
+                                 uint8_t *const *xhat, int64_t *obj,
+                                 psdp_stats *stats, hipStream_t stream);
+
+/*
+ * psdp_eval_penalty_grad - h(x_c, p) and grad h(x_c, p) for B points (eq. (p1)
+ * and the gradient 2 (Q - Diag p) x + (b + p) of eq. (kkt1)), exactly as
+ * written, with the given p (no reformation, no perturbation).
+ *
+ * dtype   psdp_dtype of Q and X (F64, F32 or BF16).
+ * vtype   psdp_dtype of b, p, h and G (F64 or F32).
+ * Q       device, n x n, leading dimension ldq >= n, symmetric (not checked).
+ * b, p    device, length n.
+ * X       device, n x B column-major.
+ * h       device, length B.
+ * G       device, n x B column-major, nullable.
+ * Stream-ordered; no host synchronization. Errors: PSDP_E_INVALID.
+ */
+psdp_status psdp_eval_penalty_grad(int32_t dtype, int32_t vtype, const void *Q, int64_t ldq,
+                                   const void *b, const void *p, const void *X,
+                                   int64_t n, int64_t B, void *h, void *G,
+                                   hipStream_t stream);
+
+/*
+ * psdp_penalty_adjoint - gradients of L = sum_c w_c h(x_c, p) (h of eq. (p1),
+ * linear in Q, b and p):
+ *   dX[:, c] = w_c G[:, c]             (G = grad h from psdp_eval_penalty_grad)
+ *   dQ       = X Diag(w) X^T           (n x n, entries of Q taken as independent)
+ *   db       = X w,   dp = (X - X o X) w.
+ * dtype   psdp_dtype of X and dQ (F32 or F64); vtype of G, w, dX, db, dp.
+ * X, G    device, n x B column-major. w: device, length B.
+ * dX, dQ (ld n), db, dp: device outputs, each nullable (skipped when NULL).
+ * Stream-ordered. Errors: PSDP_E_INVALID, PSDP_E_UNSUPPORTED (BF16).
+ */
+psdp_status psdp_penalty_adjoint(int32_t dtype, int32_t vtype, const void *X, const void *G,
+                                 const void *w, int64_t n, int64_t B,
+                                 void *dX, void *dQ, void *db, void *dp,
+                                 hipStream_t stream);
+
+/*
+ * psdp_round_objective_i32 - the final step of the solve on given iterates:
+ * xhat_ic = 1 iff X_ic > 1/2 and obj_c = xhat_c^T Q xhat_c + b^T xhat_c, in
+ * exact int64 arithmetic on the original integer data.
+ * Q device int32 n x n; b device int32; X device double n x B;
+ * xhat device uint8 n x B; obj device int64[B]. Stream-ordered.
+ * Errors: PSDP_E_INVALID.
+ */
+psdp_status psdp_round_objective_i32(const int32_t *Q, const int32_t *b, int64_t n,
+                                     const double *X, int64_t B, uint8_t *xhat,
+                                     int64_t *obj, hipStream_t stream);
+
+/*
+ * psdp_perturbation - the symmetric perturbation mu of Section 3.5 as this
+ * library draws it: for i <= j and t = 0..3, c = (i n + j) 4 + t,
+ * key = SplitMix64(seed), u_t = SplitMix64(key XOR c) >> 11;
+ * S = sum u_t (exact integer);
+ * N = (double(S) 2^-53 - 2) sqrt(3); mu_ij = mu_ji = rint(N sigma 2^16) 2^-16.
+ * mode FULL fills all entries, DIAG only the diagonal, NONE writes zeros.
+ * mu: device, double, n x n. Stream-ordered. Errors: PSDP_E_INVALID.
+ */
+psdp_status psdp_perturbation(int64_t n, double sigma, uint64_t seed, int32_t mode,
+                              double *mu, hipStream_t stream);
+
+/* Releases the cached device workspace of every device (optional). */
+void psdp_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSDP_H */

@@ -1,0 +1,406 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of the paper (or the mathematical fact) that
+fixes the expected value: exhaustive enumeration, central differences of a
+quadratic, the paper's identities and lemmas, a textbook box-QP solver and a
+third-party implementation of SplitMix64.
+"""
+import itertools
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.optimize
+
+from oracle import psdp as O
+from oracle.bruteforce import brute_force
+from workloads import gen
+
+
+def _rand_sym(n, seed, scale=10.0):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) * scale
+    return (A + A.T) / 2.0, rng.standard_normal(n) * scale
+
+
+# --- objective f and exhaustive search (Section 2, eq. (bqp)) ---------------
+
+def test_bruteforce_matches_direct_enumeration():
+    for seed in range(6):
+        n = 6 + seed
+        Q, b = gen.dense_int(n, 1000 + seed)
+        best = None
+        for bits in itertools.product([0, 1], repeat=n):
+            x = np.array(bits, dtype=np.int64)
+            f = int(x @ Q.astype(np.int64) @ x + b.astype(np.int64) @ x)
+            if best is None or f < best:
+                best = f
+        obj, xh = brute_force(Q, b)
+        assert obj == best
+        assert O.objective_exact(Q, b, xh) == best
+
+
+def test_objective_exact_vs_float_on_random_binaries():
+    Q, b = gen.dense_int(40, 7)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        x = (rng.random(40) < 0.5).astype(np.uint8)
+        assert O.objective_exact(Q, b, x) == int(round(O.objective(Q, b, x)))
+
+
+def test_reformation_preserves_objective_on_vertices():
+    # Section 3.5: x^T (Q + Diag g) x + (b - g)^T x = f(x) for binary x, any g
+    Q, b = gen.dense_int(30, 3)
+    gam = O.reformation_gamma(Q, b)
+    Qr = Q + np.diag(gam)
+    br = b - gam
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        x = (rng.random(30) < 0.5).astype(np.float64)
+        assert O.objective(Qr, br, x) == O.objective(Q, b, x)
+
+
+# --- penalty h and its gradient (eq. (p1), eq. (kkt1)) -----------------------
+
+def test_gradient_central_differences_exact_for_quadratic():
+    Q, b = _rand_sym(25, 11)
+    p = np.random.default_rng(2).uniform(-5, 5, 25)
+    rng = np.random.default_rng(3)
+    for _ in range(8):
+        x = rng.random(25)
+        d = rng.standard_normal(25)
+        for t in (1e-3, 0.5):
+            fd = (O.penalty(Q, b, p, x + t * d) - O.penalty(Q, b, p, x - t * d)) / (2 * t)
+            an = float(O.penalty_grad(Q, b, p, x) @ d)
+            assert abs(fd - an) <= 1e-9 * (1 + abs(an))
+
+
+def test_penalty_equals_objective_at_vertices():
+    # h(x, p) = f(x) for x in {0,1}^n and any p (Section 4.1, proof of Lemma 1)
+    Q, b = gen.dense_int(20, 5)
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        x = (rng.random(20) < 0.5).astype(np.float64)
+        p = rng.uniform(-100, 100, 20)
+        assert O.penalty(Q, b, p, x) == O.objective(Q, b, x)
+
+
+def test_proximal_identity_section_3_1():
+    # h(x+d) + d^T (H_p - Q + P*) d = h(x) + grad h(x)^T d + d^T H_p d
+    Q, b = _rand_sym(15, 21)
+    rng = np.random.default_rng(5)
+    p = rng.uniform(-3, 3, 15)
+    hp = O.proximal_diagonal(Q, p, 1e-8)
+    for _ in range(5):
+        x = rng.random(15)
+        d = rng.standard_normal(15) * 0.3
+        Hmat = np.diag(hp) - Q + np.diag(p)
+        lhs = O.penalty(Q, b, p, x + d) + d @ Hmat @ d
+        rhs = O.penalty(Q, b, p, x) + O.penalty_grad(Q, b, p, x) @ d + d @ (hp * d)
+        assert abs(lhs - rhs) <= 1e-10 * (1 + abs(lhs))
+
+
+def test_lemma1_monotone_in_p():
+    # Lemma 1: h(x, p1) <= h(x, p2) for p1 <= p2 on the box
+    Q, b = _rand_sym(20, 8)
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        x = rng.random(20)
+        p1 = rng.uniform(-5, 5, 20)
+        p2 = p1 + rng.uniform(0, 5, 20)
+        assert O.penalty(Q, b, p1, x) <= O.penalty(Q, b, p2, x) + 1e-12
+
+
+def test_adjoint_by_finite_differences():
+    # h is linear in Q, b and p: central differences in those directions are exact
+    Q, b = _rand_sym(12, 31)
+    rng = np.random.default_rng(7)
+    p = rng.uniform(0, 2, 12)
+    X = rng.uniform(0.05, 0.95, (3, 12))
+    w = rng.standard_normal(3)
+    dX, dQ, db, dp = O.penalty_adjoint(Q, b, p, X, w)
+    L = lambda Q_, b_, p_, X_: float(w @ np.array([O.penalty(Q_, b_, p_, x) for x in X_]))
+    t = 1e-3
+    E = rng.standard_normal((12, 12)); E = (E + E.T) / 2
+    fd = (L(Q + t * E, b, p, X) - L(Q - t * E, b, p, X)) / (2 * t)
+    assert abs(fd - np.sum(dQ * E)) <= 1e-9 * (1 + abs(fd))
+    e = rng.standard_normal(12)
+    fd = (L(Q, b + t * e, p, X) - L(Q, b - t * e, p, X)) / (2 * t)
+    assert abs(fd - db @ e) <= 1e-9 * (1 + abs(fd))
+    fd = (L(Q, b, p + t * e, X) - L(Q, b, p - t * e, X)) / (2 * t)
+    assert abs(fd - dp @ e) <= 1e-9 * (1 + abs(fd))
+    D = rng.standard_normal((3, 12))
+    fd = (L(Q, b, p, X + t * D) - L(Q, b, p, X - t * D)) / (2 * t)
+    assert abs(fd - np.sum(dX * D)) <= 1e-8 * (1 + abs(fd))
+
+
+# --- KKT measure, rho, BB step (Sections 3.2-3.3) ----------------------------
+
+def test_kkt_violation_hand_example():
+    x = np.array([0.0, 1.0, 0.5, 0.0, 1.0])
+    g = np.array([-1.0, 2.0, 0.3, 4.0, -7.0])
+    # J: |min(-1,0)| = 1, |min(4,0)| = 0; K: max(2,0) = 2, max(-7,0) = 0; I: 0.3
+    assert O.kkt_violation(x, g) == 2.0
+    assert O.kkt_violation(np.array([0.2]), np.array([-0.25])) == 0.25
+    assert O.kkt_violation(np.array([1.0, 0.0]), np.array([-1.0, 1.0])) == 0.0
+
+
+def test_rho_hand_example():
+    Qr = np.array([[3.0, -1.0], [-1.0, 2.0]])
+    br = np.array([-5.0, 1.0])
+    p = np.array([1.0, 0.0])
+    # 2(Qr - Diag p) = [[4,-2],[-2,4]] -> row sums 6, 6; b_r + p = [-4, 1]
+    assert O.rho_scale(Qr, br, p) == 6.0
+    assert O.rho_scale(np.zeros((1, 1)), np.zeros(1), np.zeros(1)) == 1.0
+
+
+def test_bb_steps_hand_example():
+    prm = O.Params()
+    s = np.array([1.0, 2.0]); y = np.array([2.0, 1.0])
+    assert O._bb_step(1, s, y, 10.0, prm) == 5.0 / 4.0      # BB1 = s's / s'y
+    assert O._bb_step(2, s, y, 10.0, prm) == 4.0 / 5.0      # BB2 = s'y / y'y
+    assert O._bb_step(0, None, None, 10.0, prm) == 0.1
+    assert O._bb_step(3, s, -y, 10.0, prm) == prm.alpha_max  # non-positive curvature
+
+
+# --- initialization (Section 3.5) --------------------------------------------
+
+def test_gamma_strict_and_x0_interior():
+    for seed in range(3):
+        Q, b = gen.dense_int(50, 40 + seed)
+        gam = O.reformation_gamma(Q, b)
+        assert np.all(gam > 2 * np.abs(Q).sum(1) + np.abs(b))
+        Qr = Q + np.diag(gam); br = b - gam
+        x0 = O.initial_point(Qr, br)
+        assert np.all((x0 > 0) & (x0 < 1))
+        res = 2 * Qr @ x0 + br
+        assert np.abs(res).max() <= 1e-10 * np.abs(br).max()
+
+
+def test_x0_is_half_for_maxcut_encoding():
+    # Q = W (zero diagonal), b = -W e: 2 (W + Diag g) e/2 = W e + g = g - b
+    W = gen.maxcut_graph(40, 9, 0.3)
+    b = -W.astype(np.int64).sum(1)
+    gam = O.reformation_gamma(W, b)
+    x0 = O.initial_point(W + np.diag(gam), b - gam)
+    assert np.abs(x0 - 0.5).max() <= 1e-13
+
+
+def test_maxcut_encoding_by_enumeration():
+    # max cut of W equals -min x^T W x - (W e)^T x over {0,1}^n
+    W = gen.maxcut_graph(11, 3, 0.5)
+    best_cut = 0
+    for bits in itertools.product([0, 1], repeat=11):
+        s = np.array(bits)
+        cut = sum(W[i, j] for i in range(11) for j in range(i + 1, 11) if s[i] != s[j])
+        best_cut = max(best_cut, cut)
+    obj, _ = brute_force(W, -W.astype(np.int64).sum(1))
+    assert -obj == best_cut
+
+
+# --- H_p (Section 3.1) and PPA (Lemma 3, Theorem 2) ------------------------------
+
+def test_hp_makes_proximal_term_psd():
+    Q, b = gen.dense_int(30, 12)
+    gam = O.reformation_gamma(Q, b)
+    Qr = Q + np.diag(gam)
+    rng = np.random.default_rng(8)
+    for scale in (0.0, 1.0, 3.0):
+        p = rng.uniform(0, scale * gam.max() + 1, 30)
+        hp = O.proximal_diagonal(Qr, p, 1e-8)
+        lam = np.linalg.eigvalsh(np.diag(hp) - Qr + np.diag(p)).min()
+        assert lam >= -1e-9 * np.abs(Qr).sum(1).max()
+
+
+def test_ppa_descent_lemma3():
+    Q, b = gen.dense_int(24, 13)
+    gam = O.reformation_gamma(Q, b)
+    Qr = Q + np.diag(gam); br = b - gam
+    p = 0.8 * gam
+    hp = O.proximal_diagonal(Qr, p, 1e-8)
+    Hm = np.diag(hp) - Qr + np.diag(p)
+    xs = []
+    O.solve_subproblem_ppa(Qr, br, p, np.full(24, 0.5), O.Params(max_inner=300),
+                           callback=lambda k, x, g: xs.append(x.copy()))
+    assert len(xs) > 3
+    for a, c in zip(xs[:-1], xs[1:]):
+        d = c - a
+        lhs = O.penalty(Qr, br, p, c)
+        rhs = O.penalty(Qr, br, p, a) - d @ Hm @ d
+        assert lhs <= rhs + 1e-9 * (1 + abs(rhs))
+
+
+def _convex_box_qp(n, seed):
+    # strictly convex h: Qbar = Q_r - Diag p positive definite; b pushes some
+    # components onto the bounds
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    Qr = A @ A.T + n * np.eye(n)
+    br = rng.standard_normal(n) * 3 * n
+    return Qr, br, np.zeros(n)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_convex_subproblem_pabb_ppa_and_lbfgsb_agree(seed):
+    n = 30
+    Qr, br, p = _convex_box_qp(n, seed)
+    prm = O.Params(max_inner=20000, tol_kkt=1e-12)
+    xa, _, rel_a, _ = O.solve_subproblem_pabb(Qr, br, p, np.full(n, 0.5), prm)
+    xb, _, rel_b, _ = O.solve_subproblem_ppa(Qr, br, p, np.full(n, 0.5), prm)
+    fun = lambda x: O.penalty(Qr, br, p, x)
+    jac = lambda x: O.penalty_grad(Qr, br, p, x)
+    ref = scipy.optimize.minimize(fun, np.full(n, 0.5), jac=jac, method="L-BFGS-B",
+                                  bounds=[(0, 1)] * n, options=dict(ftol=1e-15, gtol=1e-12, maxiter=5000))
+    at_bound = np.sum((ref.x <= 1e-9) | (ref.x >= 1 - 1e-9))
+    assert 0 < at_bound < n
+    assert np.abs(xa - ref.x).max() <= 1e-6
+    assert np.abs(xb - ref.x).max() <= 1e-6
+
+
+def test_pabb_stop_rule_holds_at_return():
+    Q, b = gen.dense_int(40, 14)
+    gam = O.reformation_gamma(Q, b)
+    Qr = Q + np.diag(gam); br = b - gam
+    p = 0.9 * gam
+    prm = O.Params()
+    x, it, rel, _ = O.solve_subproblem_pabb(Qr, br, p, np.full(40, 0.5), prm)
+    rho = O.rho_scale(Qr, br, p)
+    assert it < prm.max_inner
+    assert O.kkt_violation(x, O.penalty_grad(Qr, br, p, x)) / rho < prm.tol_kkt
+
+
+# --- penalty update (Section 3.4) --------------------------------------------
+
+def test_lambda_shift_law_and_generalized_eig():
+    Q, b = gen.dense_int(30, 15)
+    gam = O.reformation_gamma(Q, b)
+    Qr = Q + np.diag(gam)
+    rng = np.random.default_rng(9)
+    x = rng.uniform(0.05, 0.95, 30); x[:3] = [0.0, 1.0, 0.0]
+    p = rng.uniform(0, gam.min(), 30)
+    lam, I, z = O.lambda_min_scaled(Qr, p, x)
+    # independent route: smallest eigenvalue of the pencil (Qbar_II, Z_II)
+    A = (Qr - np.diag(p))[np.ix_(I, I)]
+    lam2 = scipy.linalg.eigh(A, np.diag(z), eigvals_only=True)[0]
+    assert abs(lam - lam2) <= 1e-9 * abs(lam)
+    # eq. (pp1) with the same I and z shifts the scaled matrix by -alpha
+    alpha = 0.37 * lam
+    p2 = p.copy(); p2[I] += alpha * z
+    lam_after, I2, _ = O.lambda_min_scaled(Qr, p2, x)
+    assert (I2 == I).all()
+    assert abs(lam_after - (lam - alpha)) <= 1e-9 * abs(lam)
+
+
+def test_theorem3_large_penalty_gives_binary_local_minima():
+    # Lemma 2 / Theorem 3: for p_i > (Q_r)_ii every local minimum is binary and
+    # the global box minimum equals the binary optimum
+    for seed in range(3):
+        Q, b = gen.dense_int(12, 200 + seed)
+        gam = O.reformation_gamma(Q, b)
+        Qr = Q + np.diag(gam); br = b - gam
+        p = np.diag(Qr) + 1.0
+        rng = np.random.default_rng(seed)
+        best = None
+        prm = O.Params(max_inner=5000)
+        for _ in range(60):
+            x, it, rel, _ = O.solve_subproblem_pabb(Qr, br, p, rng.random(12), prm)
+            if O.binary_gap(x) <= 1e-6:
+                v = O.objective_exact(Q, b, O.round_binary(x))
+                best = v if best is None else min(best, v)
+        assert best is not None
+        assert best == brute_force(Q, b)[0]
+
+
+# --- perturbation (Section 3.5) ------------------------------------------------
+
+def _compile_mix64_pin():
+    inc = os.path.join(os.path.dirname(__import__("pybind11").__file__), "include")
+    src = (
+        "#include <pybind11/detail/internals.h>\n#include <cstdio>\n#include <cstdlib>\n"
+        "int main(int c,char**v){for(int i=1;i<c;i++)"
+        "printf(\"%llu\\n\",(unsigned long long)pybind11::detail::mix64(strtoull(v[i],0,10)));}\n")
+    d = tempfile.mkdtemp()
+    with open(os.path.join(d, "pin.cpp"), "w") as f:
+        f.write(src)
+    exe = os.path.join(d, "pin")
+    pyinc = subprocess.check_output(["python3-config", "--includes"]).decode().split()
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-w", "-I" + inc, *pyinc,
+                           os.path.join(d, "pin.cpp"), "-o", exe],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return exe
+
+
+def test_splitmix64_against_third_party_finalizer():
+    # SplitMix64 output = finalizer(state + golden gamma); pybind11 ships the finalizer
+    try:
+        exe = _compile_mix64_pin()
+    except Exception as e:  # pragma: no cover - toolchain missing
+        pytest.skip(f"cannot build the pybind11 pin: {e}")
+    states = [0, 1, 2, 12345678901234567, 2**63, 2**64 - 1, 0x9E3779B97F4A7C15]
+    rng = np.random.default_rng(10)
+    states += [int(v) for v in rng.integers(0, 2**63 - 1, 20, dtype=np.int64)]
+    args = [str((s + 0x9E3779B97F4A7C15) % 2**64) for s in states]
+    out = subprocess.check_output([exe, *args]).decode().split()
+    shutil.rmtree(os.path.dirname(exe), ignore_errors=True)
+    assert [int(v) for v in out] == [O.splitmix64(s) for s in states]
+
+
+def test_perturbation_structure_and_moments():
+    mu = O.perturbation(60, 1.0, 123, "full")
+    assert (mu == mu.T).all()
+    assert (mu * 65536.0 == np.rint(mu * 65536.0)).all()      # dyadic grid
+    iu = np.triu_indices(60)
+    v = mu[iu]
+    assert abs(v.mean()) < 0.05 and abs(v.var() - 1.0) < 0.06  # Irwin-Hall(4) rescaled
+    assert np.abs(v).max() <= 2 * math.sqrt(3) + 1e-12         # support of Irwin-Hall(4)
+    md = O.perturbation(60, 1.0, 123, "diag")
+    assert (md == np.diag(np.diag(mu))).all()
+    assert (O.perturbation(10, 1.0, 1, "none") == 0).all()
+    assert not (O.perturbation(10, 1.0, 2, "full") == O.perturbation(10, 1.0, 3, "full")).all()
+
+
+# --- the whole method (Algorithm 3) ---------------------------------------------
+
+def test_solve_quality_band_on_bruteforce_set():
+    # quality band only: the paper reports mean PABB GAP 0.06% at n = 20 (Table 2)
+    gaps, reasons = [], []
+    for seed, Q, b in gen.bruteforce_set()[::2]:
+        r = O.solve(Q, b)
+        opt, _ = brute_force(Q, b)
+        assert O.binary_gap(r.x) <= 1e-5 or r.exit_reason != O.CONVERGED
+        assert r.obj == O.objective_exact(Q, b, r.xhat)
+        assert r.obj >= opt
+        gaps.append(abs((r.obj - opt) / opt) * 100)
+        reasons.append(r.exit_reason)
+    assert all(rr == O.CONVERGED for rr in reasons)
+    assert np.mean(gaps) < 1.0
+    assert np.mean(np.array(gaps) == 0) >= 0.6
+
+
+def test_solve_resume_is_bit_identical():
+    Q, b = gen.small_dense(0)
+    full = O.solve(Q, b)
+    assert full.outer_iters > 6
+    part = O.solve(Q, b, O.Params(max_outer=5))
+    assert part.exit_reason == O.OUTER_CAP
+    rest = O.solve(Q, b, x0=part.x, p0=part.p)
+    assert rest.obj == full.obj
+    assert (rest.x == full.x).all()
+    assert part.outer_iters + rest.outer_iters == full.outer_iters
+
+
+def test_no_progress_exit_matches_shift_law():
+    # after a non-moving subproblem, I and z are unchanged and lambda shrinks by (1 - eta)
+    Q, b = gen.small_dense(0)
+    prm = O.Params(eta=0.9, stall_outer=3)
+    r = O.solve(Q, b, prm)
+    assert r.exit_reason == O.STALL
+    tail = r.trace[-3:]
+    assert all(t["inner"] == 1 for t in tail)
+    for prev, nxt in zip(tail[:-1], tail[1:]):
+        assert abs(nxt["lam"] - (1 - prm.eta) * prev["lam"]) <= 1e-6 * abs(prev["lam"])
