@@ -113,6 +113,8 @@ typedef struct {
     double qx_seconds;         /* summed Q.X kernel time (timing = 1), whole launch */
     double qx_flops;           /* algorithmic flops of those Q.X launches (2 n^2 per column) */
     int64_t qx_launches;       /* number of Q.X launches timed */
+    double aux_seconds;        /* batched FP32: summed time of the FP64 lambda_min/CG products */
+    double aux_flops;          /* algorithmic flops of those products */
 } psdp_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -137,7 +139,10 @@ int32_t psdp_version(void);
  * p0      device, double, length n, initial penalty of the reformulated
  *         problem (Algorithm 3 line 3 sets 0); NULL means 0.
  * B       number of starts (>= 1). B = 1 runs the single-instance path
- *         (GEMV Q.x); B > 1 runs all starts together (MFMA Q.X per sweep).
+ *         (GEMV Q.x, FP64 accumulation, Q stored in qx_dtype); B > 1 runs
+ *         all starts together (MFMA Q.X per sweep). With B > 1 and F32
+ *         operands the subproblem products run on FP32 MFMA while the
+ *         lambda_min and x^0 products keep FP64 operands (FP64 MFMA).
  * prm     host, parameters (psdp_params_default then edit; NULL = defaults).
  * xhat    device, uint8, n x B: rounded solutions, x_i = 1 iff x_i > 1/2.
  * obj     device, int64, length B: f(xhat) on the original Q and b, exact.
@@ -156,6 +161,19 @@ psdp_status psdp_solve_i32(const int32_t *Q, const int32_t *b, int64_t n,
                            const psdp_params *prm, uint8_t *xhat, int64_t *obj,
                            double *X_out, int32_t *best, psdp_stats *stats,
                            hipStream_t stream);
+
+/*
+ * psdp_solve_i32_ex - psdp_solve_i32 plus a per-penalty-update trace.
+ * trace     host, nullable: B x trace_cap records of 6 doubles
+ *           {s, |I|, lambda_min, alpha, subproblem evaluations, final cret/rho},
+ *           one record per completed subproblem (unused records untouched).
+ * trace_cap records per column (>= 1 when trace is given).
+ */
+psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n,
+                              const double *X0, const double *p0, int32_t B,
+                              const psdp_params *prm, uint8_t *xhat, int64_t *obj,
+                              double *X_out, int32_t *best, psdp_stats *stats,
+                              double *trace, int32_t trace_cap, hipStream_t stream);
 
 /*
  * psdp_solve_group_i32 - Algorithm 3 on `count` independent instances of

@@ -1,0 +1,10 @@
+"""MI355X (gfx950) vectorized-PSDP hot path: HIP kernels behind a C ABI.
+
+The public functions forward to libpsdp.so through ``binding``; they raise if
+the library is not built. Nothing here computes on the CPU.
+"""
+from .binding import (  # noqa: F401
+    F32, F64, BF16, PABB, PPA, EXIT_NAMES, PSDPError, Params, Stats,
+    default_params, eval_penalty_grad, load, penalty_adjoint, penalty_fn,
+    perturbation, round_objective, solve, solve_group,
+)

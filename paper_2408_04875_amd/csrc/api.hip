@@ -1,0 +1,705 @@
+// C ABI of the vectorized PSDP library (include/psdp.h): validation,
+// workspace, and the host loop that drives the per-sweep kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace psdp;
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_lock;
+
+psdp_status fail(psdp_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+psdp_status hipfail(hipError_t e, const char *where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PSDP_E_NOMEM : PSDP_E_DEVICE;
+}
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hipfail(e_, #expr); \
+    } while (0)
+
+int64_t pad16(int64_t n) { return (n + 15) / 16 * 16; }
+
+// Device allocations released in reverse order when the solve returns.
+struct Arena {
+    std::vector<void *> ptrs;
+    ~Arena() {
+        for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it) (void)hipFree(*it);
+    }
+    hipError_t get(void **p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(p, (bytes + 255) / 256 * 256);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+};
+
+size_t esize(int dtype) { return dtype == PSDP_F64 ? 8 : dtype == PSDP_F32 ? 4 : 2; }
+
+psdp_status check_params(const psdp_params &p) {
+    if (p.inner != PSDP_INNER_PABB && p.inner != PSDP_INNER_PPA) return fail(PSDP_E_INVALID, "params.inner");
+    if (p.qx_dtype < PSDP_F64 || p.qx_dtype > PSDP_BF16) return fail(PSDP_E_INVALID, "params.qx_dtype");
+    if (p.perturb < PSDP_PERTURB_NONE || p.perturb > PSDP_PERTURB_DIAG)
+        return fail(PSDP_E_INVALID, "params.perturb");
+    if (p.max_inner < 1 || p.max_outer < 0 || p.stall_outer < 1 || p.eig_maxit < 1 || p.cg_maxit < 1 ||
+        p.poll_sweeps < 1)
+        return fail(PSDP_E_INVALID, "params: iteration caps must be positive");
+    if (!(p.eta > 0.0 && p.eta < 1.0)) return fail(PSDP_E_INVALID, "params.eta must be in (0,1)");
+    if (!(p.tol_kkt > 0.0) || !(p.tol_binary >= 0.0) || !(p.eps_hp > 0.0) || !(p.eig_tol > 0.0) ||
+        !(p.cg_tol > 0.0) || !(p.alpha_min > 0.0) || !(p.alpha_max >= p.alpha_min) ||
+        !(p.lambda_floor_rel >= 0.0) || !(p.sigma >= 0.0) || !std::isfinite(p.sigma))
+        return fail(PSDP_E_INVALID, "params: tolerance out of range");
+    return PSDP_OK;
+}
+
+// Host-side checks of one integer instance (Q and b already copied back).
+psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int32_t> &b, int64_t n,
+                           const psdp_params &p) {
+    int64_t qmax = 0, bmax = 0, offmax = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        bmax = std::max<int64_t>(bmax, std::llabs((long long)b[i]));
+        for (int64_t j = 0; j < n; ++j) {
+            const int32_t v = Q[i * n + j];
+            if (v != Q[j * n + i]) {
+                char buf[128];
+                snprintf(buf, sizeof buf, "Q[%lld][%lld] != Q[%lld][%lld]", (long long)i, (long long)j,
+                         (long long)j, (long long)i);
+                return fail(PSDP_E_NOT_SYMMETRIC, buf);
+            }
+            const int64_t a = std::llabs((long long)v);
+            qmax = std::max(qmax, a);
+            if (i != j) offmax = std::max(offmax, a);
+        }
+    }
+    // |f(x)| <= n^2 max|Q| + n max|b| must stay below 2^62
+    const long double bound = (long double)n * n * qmax + (long double)n * bmax;
+    if (bound >= 4.611686018427388e18L) return fail(PSDP_E_OVERFLOW, "n^2 max|Q| + n max|b| >= 2^62");
+    if (p.qx_dtype == PSDP_BF16 && p.perturb == PSDP_PERTURB_FULL && p.sigma > 0.0)
+        return fail(PSDP_E_UNSUPPORTED, "FULL perturbation is not exact in bfloat16 operands");
+    if (p.qx_dtype == PSDP_BF16 && offmax > 256)
+        return fail(PSDP_E_UNSUPPORTED, "bfloat16 operands need |Q_ij| <= 256 off the diagonal");
+    if (p.qx_dtype == PSDP_F32 && offmax > (1 << 24))
+        return fail(PSDP_E_UNSUPPORTED, "float operands need |Q_ij| <= 2^24 off the diagonal");
+    return PSDP_OK;
+}
+
+__global__ void gamma_kernel(const int32_t *b, const double *R, const double *dq, int64_t n,
+                             int64_t ld, double *bd, double *gam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ld) return;
+    if (i < n) {
+        const double bi = (double)b[i];
+        bd[i] = bi;
+        // gamma_i = 2 sum_j |Q~_ij| + |b_i| + 1 (Section 3.5, strict margin 1)
+        gam[i] = 2.0 * (R[i] + fabs(dq[i])) + fabs(bi) + 1.0;
+    } else {
+        bd[i] = 0.0;
+        gam[i] = 0.0;
+    }
+}
+
+__global__ void fill_p_kernel(double *p, const double *p0, int64_t n, int64_t ld, int ncol) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ld * ncol) return;
+    const int64_t i = idx % ld;
+    p[idx] = (p0 && i < n) ? p0[i] : 0.0;
+}
+
+struct Solver {
+    Arena ar;
+    Work w{};
+    int optype = PSDP_F64, utype = PSDP_F64;
+    int64_t *sweeps = nullptr;
+    int32_t *partial_dummy = nullptr;
+};
+
+void fill_work_params(Work &w, const psdp_params &p) {
+    w.inner = p.inner;
+    w.max_inner = p.max_inner;
+    w.max_outer = p.max_outer;
+    w.stall_outer = p.stall_outer;
+    w.eig_maxit = p.eig_maxit;
+    w.cg_maxit = p.cg_maxit;
+    w.tol_kkt = p.tol_kkt;
+    w.tol_binary = p.tol_binary;
+    w.eta = p.eta;
+    w.eps_hp = p.eps_hp;
+    w.lambda_floor_rel = p.lambda_floor_rel;
+    w.alpha_min = p.alpha_min;
+    w.alpha_max = p.alpha_max;
+    w.eig_tol = p.eig_tol;
+    w.cg_tol = p.cg_tol;
+}
+
+// Allocates the per-column vectors for `total` doubles of column storage.
+psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit) {
+    Work &w = S.w;
+    double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w};
+    for (double **v : vecs) {
+        HIPCHK(S.ar.get((void **)v, total * sizeof(double)));
+        HIPCHK(hipMemset(*v, 0, total * sizeof(double)));
+    }
+    HIPCHK(S.ar.get(&w.op, total * esize(S.optype)));
+    HIPCHK(hipMemset(w.op, 0, total * esize(S.optype)));
+    w.ksplit = (int32_t)ksplit;
+    w.slice = total;
+    HIPCHK(S.ar.get(&w.U, ksplit * total * esize(S.utype)));
+    HIPCHK(hipMemset(w.U, 0, ksplit * total * esize(S.utype)));
+    HIPCHK(S.ar.get((void **)&w.active, (ncol + 1) * sizeof(int32_t)));
+    HIPCHK(S.ar.get((void **)&w.nactive, 64));
+    HIPCHK(hipMemset(w.nactive, 0, 64));
+    w.nactive_aux = w.nactive + 1;
+    HIPCHK(S.ar.get((void **)&S.sweeps, 64));
+    HIPCHK(hipMemset(S.sweeps, 0, 64));
+    w.ncol = ncol;
+    if (S.w.split) {
+        w.ksplit_aux = (int32_t)ksplit;
+        w.slice_aux = total;
+        HIPCHK(S.ar.get((void **)&w.op_aux, total * sizeof(double)));
+        HIPCHK(hipMemset(w.op_aux, 0, total * sizeof(double)));
+        HIPCHK(S.ar.get((void **)&w.U_aux, ksplit * total * sizeof(double)));
+        HIPCHK(hipMemset(w.U_aux, 0, ksplit * total * sizeof(double)));
+        HIPCHK(S.ar.get((void **)&w.active_aux, (ncol + 1) * sizeof(int32_t)));
+    } else {
+        w.ksplit_aux = w.ksplit;
+        w.slice_aux = w.slice;
+        w.active_aux = w.active;
+    }
+    return PSDP_OK;
+}
+
+// Timing of Q.X launches with HIP events on the solve stream.
+struct QxTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    double seconds = 0.0;
+    int64_t launches = 0;
+    ~QxTimer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t begin(hipStream_t st) {
+        if (!on) return hipSuccess;
+        if (used + 2 > ev.size()) {
+            for (int q = 0; q < 64; ++q) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                ev.push_back(e);
+            }
+        }
+        return hipEventRecord(ev[used], st);
+    }
+    hipError_t end(hipStream_t st) {
+        if (!on) return hipSuccess;
+        hipError_t r = hipEventRecord(ev[used + 1], st);
+        used += 2;
+        return r;
+    }
+    // Accumulates every recorded pair; call after the stream is synchronized.
+    hipError_t collect() {
+        for (size_t q = 0; q + 1 < used; q += 2) {
+            float ms = 0.f;
+            hipError_t r = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            if (r != hipSuccess) return r;
+            seconds += ms * 1e-3;
+            launches += 1;
+        }
+        used = 0;
+        return hipSuccess;
+    }
+};
+
+// Runs sweeps until no column is live. `apply` enqueues the Q.X product of
+// the main live list, `apply_aux` (split precision only) the FP64 product of
+// the lambda_min / CG list.
+template <typename Apply, typename ApplyAux>
+psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &ta, hipStream_t st,
+                       const Apply &apply, const ApplyAux &apply_aux) {
+    Work &w = S.w;
+    int32_t *host_cnt = nullptr;
+    HIPCHK(hipHostMalloc((void **)&host_cnt, 4 * sizeof(int32_t), hipHostMallocDefault));
+    struct HostFree {
+        int32_t *p;
+        ~HostFree() { (void)hipHostFree(p); }
+    } hf{host_cnt};
+    hipEvent_t evs[2];
+    HIPCHK(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
+    struct EvFree {
+        hipEvent_t *e;
+        ~EvFree() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } ef{evs};
+    // hard bound from the per-column caps (every sweep advances every live column)
+    const int64_t cap = (int64_t)prm.cg_maxit +
+                        (int64_t)(prm.max_outer + 1) * ((int64_t)prm.eig_maxit + prm.max_inner + 2) + 2;
+    int64_t done_sweeps = 0;
+    int batch = 0;
+    bool finished = false;
+    while (!finished) {
+        const int nb = (int)std::min<int64_t>(prm.poll_sweeps, cap - done_sweeps);
+        if (nb <= 0) return fail(PSDP_E_DEVICE, "sweep bound exceeded");
+        for (int q = 0; q < nb; ++q) {
+            HIPCHK(tm.begin(st));
+            HIPCHK(apply());
+            HIPCHK(tm.end(st));
+            if (w.split) {
+                HIPCHK(ta.begin(st));
+                HIPCHK(apply_aux());
+                HIPCHK(ta.end(st));
+            }
+            HIPCHK(launch_solver_step(S.optype, S.utype, w, st));
+            HIPCHK(launch_compact_count(w, S.sweeps, st));
+        }
+        done_sweeps += nb;
+        const int slot = batch & 1;
+        HIPCHK(hipMemcpyAsync(host_cnt + 2 * slot, w.nactive, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(evs[slot], st));
+        if (batch > 0) {
+            const int prev = slot ^ 1;
+            HIPCHK(hipEventSynchronize(evs[prev]));
+            if (host_cnt[2 * prev] + host_cnt[2 * prev + 1] == 0) finished = true;
+        }
+        if ((tm.on && tm.used > 4096) || (ta.on && ta.used > 4096)) {
+            HIPCHK(hipEventSynchronize(evs[slot]));
+            HIPCHK(tm.collect());
+            HIPCHK(ta.collect());
+        }
+        ++batch;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(tm.collect());
+    HIPCHK(ta.collect());
+    return PSDP_OK;
+}
+
+void fill_stats(const std::vector<Col> &cols, int64_t sweeps, const QxTimer &tm, double flops_total,
+                const QxTimer &ta, double aux_flops, psdp_stats *stats) {
+    for (size_t c = 0; c < cols.size(); ++c) {
+        psdp_stats &s = stats[c];
+        std::memset(&s, 0, sizeof s);
+        s.exit_reason = cols[c].exit_reason;
+        s.outer_iters = cols[c].s;
+        s.inner_iters = cols[c].evals;
+        s.aux_matvecs = cols[c].aux;
+        s.final_cret_rel = cols[c].final_rel;
+        s.final_binary_gap = cols[c].final_bg;
+        s.sweeps = sweeps;
+        s.qx_seconds = tm.seconds;
+        s.qx_flops = flops_total;
+        s.qx_launches = tm.launches;
+        s.aux_seconds = ta.seconds;
+        s.aux_flops = aux_flops;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+
+extern "C" {
+
+void psdp_params_default(psdp_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(psdp_params);
+    p->inner = PSDP_INNER_PABB;
+    p->qx_dtype = PSDP_F64;
+    p->perturb = PSDP_PERTURB_NONE;
+    p->max_inner = 10000;
+    p->max_outer = 1000;
+    p->stall_outer = 2;
+    p->eig_maxit = 500;
+    p->cg_maxit = 500;
+    p->timing = 0;
+    p->poll_sweeps = 16;
+    p->gemm_variant = -1;
+    p->tol_kkt = 1e-5;
+    p->tol_binary = 1e-5;
+    p->eta = 0.999;
+    p->eps_hp = 1e-8;
+    p->lambda_floor_rel = 1e-8;
+    p->alpha_min = 1e-30;
+    p->alpha_max = 1e30;
+    p->sigma = 0.0;
+    p->eig_tol = 1e-9;
+    p->cg_tol = 1e-12;
+    p->seed = 0;
+}
+
+const char *psdp_status_string(psdp_status s) {
+    switch (s) {
+        case PSDP_OK: return "ok";
+        case PSDP_E_INVALID: return "invalid argument";
+        case PSDP_E_NOT_SYMMETRIC: return "Q is not symmetric";
+        case PSDP_E_NONFINITE: return "non-finite or out-of-range input";
+        case PSDP_E_OVERFLOW: return "objective bound overflows int64";
+        case PSDP_E_DEVICE: return "HIP device error";
+        case PSDP_E_NOMEM: return "out of device memory";
+        case PSDP_E_UNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown status";
+}
+
+const char *psdp_last_error(void) { return g_err.c_str(); }
+
+int32_t psdp_version(void) { return 10000; }
+
+psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, const double *X0,
+                              const double *p0, int32_t B, const psdp_params *prm_in,
+                              uint8_t *xhat, int64_t *obj, double *X_out, int32_t *best,
+                              psdp_stats *stats, double *trace, int32_t trace_cap,
+                              hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    psdp_params prm;
+    psdp_params_default(&prm);
+    if (prm_in) {
+        if (prm_in->struct_size != sizeof(psdp_params)) return fail(PSDP_E_INVALID, "params.struct_size");
+        prm = *prm_in;
+    }
+    if (psdp_status s = check_params(prm)) return s;
+    if (!Q || !b || !xhat || !obj) return fail(PSDP_E_INVALID, "null required pointer");
+    if (n < 1 || B < 1) return fail(PSDP_E_INVALID, "n and B must be >= 1");
+    if (!X0 && B != 1) return fail(PSDP_E_INVALID, "X0 = NULL needs B = 1");
+    if (trace && trace_cap < 1) return fail(PSDP_E_INVALID, "trace_cap");
+    if (n > 65536) return fail(PSDP_E_UNSUPPORTED, "n > 65536");
+    // validation: one copy of the inputs back to the host
+    std::vector<int32_t> hQ(n * n), hb(n);
+    HIPCHK(hipMemcpyAsync(hQ.data(), Q, n * n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hb.data(), b, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    std::vector<double> hX0, hp0;
+    if (X0) {
+        hX0.resize(n * B);
+        HIPCHK(hipMemcpyAsync(hX0.data(), X0, n * B * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    if (p0) {
+        hp0.resize(n);
+        HIPCHK(hipMemcpyAsync(hp0.data(), p0, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (psdp_status s = check_instance(hQ, hb, n, prm)) return s;
+    for (double v : hX0)
+        if (!(v >= 0.0 && v <= 1.0)) return fail(PSDP_E_NONFINITE, "X0 entries must lie in [0,1]");
+    for (double v : hp0)
+        if (!std::isfinite(v)) return fail(PSDP_E_NONFINITE, "p0 must be finite");
+    if (B > 1 && prm.qx_dtype == PSDP_BF16)
+        return fail(PSDP_E_UNSUPPORTED, "batched starts support F64 and F32 operands");
+
+    Solver S;
+    const bool batched = B > 1;
+    const int64_t ld = pad16(n);
+    S.optype = batched ? prm.qx_dtype : PSDP_F64;  // single instance: FP64 x, Q in qx_dtype
+    S.utype = batched ? prm.qx_dtype : PSDP_F64;
+    Work &w = S.w;
+    fill_work_params(w, prm);
+    // batched lower-precision products: lambda_min and CG keep FP64 operands
+    w.split = (batched && prm.qx_dtype != PSDP_F64) ? 1 : 0;
+    // instance data
+    void *Qop = nullptr;
+    HIPCHK(S.ar.get(&Qop, ld * ld * esize(prm.qx_dtype)));
+    double *bd, *gam, *R, *dq;
+    HIPCHK(S.ar.get((void **)&bd, ld * 8));
+    HIPCHK(S.ar.get((void **)&gam, ld * 8));
+    HIPCHK(S.ar.get((void **)&R, ld * 8));
+    HIPCHK(S.ar.get((void **)&dq, ld * 8));
+    HIPCHK(launch_prep_q(prm.qx_dtype, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qop, R, dq, st));
+    void *Qop64 = Qop;
+    if (w.split) {
+        HIPCHK(S.ar.get(&Qop64, ld * ld * sizeof(double)));
+        HIPCHK(launch_prep_q(PSDP_F64, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qop64, R, dq, st));
+    }
+    hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, st, b, R, dq, n, ld,
+                       bd, gam);
+    HIPCHK(hipGetLastError());
+    w.b = bd;
+    w.gam = gam;
+    w.R = R;
+    w.dq = dq;
+    Inst hin{n, ld, 0, Qop};
+    HIPCHK(S.ar.get((void **)&w.inst, sizeof(Inst)));
+    HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
+    // column data
+    int ksplit = 1;
+    if (batched) {
+        ksplit = prm.gemm_variant > 0 ? std::min(16, prm.gemm_variant & 0xff) : (n >= 1024 ? 4 : 1);
+    }
+    if (psdp_status s2 = alloc_columns(S, ld * B, B, ksplit)) return s2;
+    std::vector<Col> hcol(B);
+    for (int c = 0; c < B; ++c) {
+        Col &cc = hcol[c];
+        std::memset(&cc, 0, sizeof cc);
+        cc.inst = 0;
+        cc.n = n;
+        cc.ld = ld;
+        cc.off = (int64_t)c * ld;
+        cc.phase = PH_INNER;  // placeholder, set by the init kernel
+    }
+    HIPCHK(S.ar.get((void **)&w.col, B * sizeof(Col)));
+    HIPCHK(hipMemcpyAsync(w.col, hcol.data(), B * sizeof(Col), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(fill_p_kernel, dim3((unsigned)((ld * B + 255) / 256)), dim3(256), 0, st, w.p, p0, n,
+                       ld, B);
+    HIPCHK(hipGetLastError());
+    if (trace) {
+        HIPCHK(S.ar.get((void **)&w.trace, (size_t)B * trace_cap * 6 * sizeof(double)));
+        w.trace_cap = trace_cap;
+    }
+    HIPCHK(launch_solver_init(S.optype, w, X0, X0 ? 0 : 1, st));
+    HIPCHK(launch_compact(w, st));
+
+    QxTimer tm, ta;
+    tm.on = ta.on = prm.timing != 0;
+    auto none = []() { return hipSuccess; };
+    psdp_status rs;
+    if (!batched) {
+        rs = run_sweeps(S, prm, tm, ta, st, [&]() { return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st); },
+                        none);
+    } else {
+        rs = run_sweeps(
+            S, prm, tm, ta, st,
+            [&]() {
+                return launch_gemm(prm.qx_dtype, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit,
+                                   B, st);
+            },
+            [&]() {
+                return launch_gemm(PSDP_F64, Qop64, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
+                                   w.slice_aux, w.ksplit_aux, B, st);
+            });
+    }
+    if (rs != PSDP_OK) return rs;
+    // rounding and exact objective on the original data
+    int64_t *partial;
+    const int64_t nblk = (n + 15) / 16;
+    HIPCHK(S.ar.get((void **)&partial, nblk * B * sizeof(int64_t)));
+    HIPCHK(launch_round_objective(Q, b, n, w.x, ld, B, xhat, n, obj, partial, st));
+    if (X_out)
+        HIPCHK(hipMemcpy2DAsync(X_out, n * sizeof(double), w.x, ld * sizeof(double), n * sizeof(double), B,
+                                hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(hcol.data(), w.col, B * sizeof(Col), hipMemcpyDeviceToHost, st));
+    int64_t nsweeps = 0;
+    HIPCHK(hipMemcpyAsync(&nsweeps, S.sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    std::vector<int64_t> hobj;
+    if (best) {
+        hobj.resize(B);
+        HIPCHK(hipMemcpyAsync(hobj.data(), obj, B * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    }
+    if (trace)
+        HIPCHK(hipMemcpyAsync(trace, w.trace, (size_t)B * trace_cap * 6 * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (best) {
+        int32_t bi = 0;
+        for (int c = 1; c < B; ++c)
+            if (hobj[c] < hobj[bi]) bi = c;
+        *best = bi;
+    }
+    if (stats) {
+        double flops = 0.0, aflops = 0.0;
+        for (const Col &cc : hcol) {
+            flops += 2.0 * (double)n * (double)n * (double)(w.split ? cc.evals : cc.evals + cc.aux);
+            aflops += w.split ? 2.0 * (double)n * (double)n * (double)cc.aux : 0.0;
+        }
+        fill_stats(hcol, nsweeps, tm, flops, ta, aflops, stats);
+    }
+    return PSDP_OK;
+}
+
+psdp_status psdp_solve_i32(const int32_t *Q, const int32_t *b, int64_t n, const double *X0,
+                           const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
+                           int64_t *obj, double *X_out, int32_t *best, psdp_stats *stats,
+                           hipStream_t st) {
+    return psdp_solve_i32_ex(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats, nullptr, 0, st);
+}
+
+psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t *const *Q,
+                                 const int32_t *const *b, const uint64_t *seeds,
+                                 const psdp_params *prm_in, uint8_t *const *xhat, int64_t *obj,
+                                 psdp_stats *stats, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    psdp_params prm;
+    psdp_params_default(&prm);
+    if (prm_in) {
+        if (prm_in->struct_size != sizeof(psdp_params)) return fail(PSDP_E_INVALID, "params.struct_size");
+        prm = *prm_in;
+    }
+    if (psdp_status s = check_params(prm)) return s;
+    if (count < 1 || !n || !Q || !b || !xhat || !obj) return fail(PSDP_E_INVALID, "null or empty group");
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 1 || n[i] > 65536) return fail(PSDP_E_INVALID, "instance size out of range");
+        if (!Q[i] || !b[i] || !xhat[i]) return fail(PSDP_E_INVALID, "null instance pointer");
+    }
+    for (int i = 0; i < count; ++i) {
+        std::vector<int32_t> hQ(n[i] * n[i]), hb(n[i]);
+        HIPCHK(hipMemcpyAsync(hQ.data(), Q[i], n[i] * n[i] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hb.data(), b[i], n[i] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (psdp_status s = check_instance(hQ, hb, n[i], prm)) {
+            g_err = "instance " + std::to_string(i) + ": " + g_err;
+            return s;
+        }
+    }
+    Solver S;
+    S.optype = PSDP_F64;
+    S.utype = PSDP_F64;
+    Work &w = S.w;
+    fill_work_params(w, prm);
+    std::vector<int64_t> ld(count), off(count + 1, 0), rowstart(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        ld[i] = pad16(n[i]);
+        off[i + 1] = off[i] + ld[i];
+        rowstart[i + 1] = rowstart[i] + n[i];
+    }
+    const int64_t total = off[count];
+    double *bd, *gam, *R, *dq;
+    HIPCHK(S.ar.get((void **)&bd, total * 8));
+    HIPCHK(S.ar.get((void **)&gam, total * 8));
+    HIPCHK(S.ar.get((void **)&R, total * 8));
+    HIPCHK(S.ar.get((void **)&dq, total * 8));
+    std::vector<Inst> hin(count);
+    for (int i = 0; i < count; ++i) {
+        void *Qop;
+        HIPCHK(S.ar.get(&Qop, ld[i] * ld[i] * esize(prm.qx_dtype)));
+        const uint64_t seed = seeds ? seeds[i] : prm.seed;
+        HIPCHK(launch_prep_q(prm.qx_dtype, Q[i], n[i], ld[i], prm.perturb, prm.sigma, seed, Qop, R + off[i],
+                             dq + off[i], st));
+        hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((ld[i] + 255) / 256)), dim3(256), 0, st, b[i],
+                           R + off[i], dq + off[i], n[i], ld[i], bd + off[i], gam + off[i]);
+        HIPCHK(hipGetLastError());
+        hin[i] = Inst{n[i], ld[i], off[i], Qop};
+    }
+    w.b = bd;
+    w.gam = gam;
+    w.R = R;
+    w.dq = dq;
+    HIPCHK(S.ar.get((void **)&w.inst, count * sizeof(Inst)));
+    HIPCHK(hipMemcpyAsync(w.inst, hin.data(), count * sizeof(Inst), hipMemcpyHostToDevice, st));
+    if (psdp_status s2 = alloc_columns(S, total, count, 1)) return s2;
+    std::vector<Col> hcol(count);
+    for (int i = 0; i < count; ++i) {
+        Col &cc = hcol[i];
+        std::memset(&cc, 0, sizeof cc);
+        cc.inst = i;
+        cc.n = n[i];
+        cc.ld = ld[i];
+        cc.off = off[i];
+        cc.phase = PH_INNER;
+    }
+    HIPCHK(S.ar.get((void **)&w.col, count * sizeof(Col)));
+    HIPCHK(hipMemcpyAsync(w.col, hcol.data(), count * sizeof(Col), hipMemcpyHostToDevice, st));
+    int64_t *drow;
+    HIPCHK(S.ar.get((void **)&drow, (count + 1) * sizeof(int64_t)));
+    HIPCHK(hipMemcpyAsync(drow, rowstart.data(), (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_solver_init(S.optype, w, nullptr, 1, st));
+    HIPCHK(launch_compact(w, st));
+    QxTimer tm, ta;
+    tm.on = prm.timing != 0;
+    psdp_status rs = run_sweeps(
+        S, prm, tm, ta, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, rowstart[count], st); },
+        []() { return hipSuccess; });
+    if (rs != PSDP_OK) return rs;
+    int64_t maxblk = 0;
+    for (int i = 0; i < count; ++i) maxblk = std::max<int64_t>(maxblk, (n[i] + 15) / 16);
+    int64_t *partial;
+    HIPCHK(S.ar.get((void **)&partial, maxblk * sizeof(int64_t) * 2));
+    for (int i = 0; i < count; ++i)
+        HIPCHK(launch_round_objective(Q[i], b[i], n[i], w.x + off[i], ld[i], 1, xhat[i], n[i], obj + i,
+                                      partial, st));
+    HIPCHK(hipMemcpyAsync(hcol.data(), w.col, count * sizeof(Col), hipMemcpyDeviceToHost, st));
+    int64_t nsweeps = 0;
+    HIPCHK(hipMemcpyAsync(&nsweeps, S.sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (stats) {
+        double flops = 0.0;
+        for (const Col &cc : hcol) flops += 2.0 * (double)cc.n * (double)cc.n * (double)(cc.evals + cc.aux);
+        fill_stats(hcol, nsweeps, tm, flops, ta, 0.0, stats);
+    }
+    return PSDP_OK;
+}
+
+psdp_status psdp_eval_penalty_grad(int32_t dtype, int32_t vtype, const void *Q, int64_t ldq,
+                                   const void *b, const void *p, const void *X, int64_t n, int64_t B,
+                                   void *h, void *G, hipStream_t st) {
+    g_err.clear();
+    if (dtype < PSDP_F64 || dtype > PSDP_BF16) return fail(PSDP_E_INVALID, "dtype");
+    if (vtype != PSDP_F64 && vtype != PSDP_F32) return fail(PSDP_E_INVALID, "vtype");
+    if (!Q || !b || !p || !X || !h) return fail(PSDP_E_INVALID, "null required pointer");
+    if (n < 1 || B < 1 || ldq < n) return fail(PSDP_E_INVALID, "sizes");
+    if (B > 65535) return fail(PSDP_E_UNSUPPORTED, "B > 65535");
+    double *ws = nullptr;
+    const size_t bytes = (size_t)n * B * sizeof(double) + (B + 16) * sizeof(int32_t) + 256;
+    HIPCHK(hipMallocAsync((void **)&ws, bytes, st));
+    hipError_t e = launch_eval(dtype, vtype, Q, ldq, b, p, X, n, B, h, G, ws, st);
+    hipError_t e2 = hipFreeAsync(ws, st);
+    if (e != hipSuccess) return hipfail(e, "eval");
+    if (e2 != hipSuccess) return hipfail(e2, "hipFreeAsync");
+    return PSDP_OK;
+}
+
+psdp_status psdp_penalty_adjoint(int32_t dtype, int32_t vtype, const void *X, const void *G,
+                                 const void *w, int64_t n, int64_t B, void *dX, void *dQ, void *db,
+                                 void *dp, hipStream_t st) {
+    g_err.clear();
+    if (dtype != PSDP_F64 && dtype != PSDP_F32) {
+        if (dtype == PSDP_BF16) return fail(PSDP_E_UNSUPPORTED, "adjoint supports F32 and F64");
+        return fail(PSDP_E_INVALID, "dtype");
+    }
+    if (vtype != PSDP_F64 && vtype != PSDP_F32) return fail(PSDP_E_INVALID, "vtype");
+    if (!X || !w || (dX && !G)) return fail(PSDP_E_INVALID, "null required pointer");
+    if (n < 1 || B < 1) return fail(PSDP_E_INVALID, "sizes");
+    if (n > 65535 * 64) return fail(PSDP_E_UNSUPPORTED, "n too large");
+    hipError_t e = launch_adjoint(dtype, vtype, X, G, w, n, B, dX, dQ, db, dp, st);
+    if (e != hipSuccess) return hipfail(e, "adjoint");
+    return PSDP_OK;
+}
+
+psdp_status psdp_round_objective_i32(const int32_t *Q, const int32_t *b, int64_t n, const double *X,
+                                     int64_t B, uint8_t *xhat, int64_t *obj, hipStream_t st) {
+    g_err.clear();
+    if (!Q || !b || !X || !xhat || !obj) return fail(PSDP_E_INVALID, "null required pointer");
+    if (n < 1 || B < 1 || B > 65535) return fail(PSDP_E_INVALID, "sizes");
+    int64_t *partial = nullptr;
+    const int64_t nblk = (n + 15) / 16;
+    HIPCHK(hipMallocAsync((void **)&partial, nblk * B * sizeof(int64_t), st));
+    hipError_t e = launch_round_objective(Q, b, n, X, n, B, xhat, n, obj, partial, st);
+    hipError_t e2 = hipFreeAsync(partial, st);
+    if (e != hipSuccess) return hipfail(e, "round_objective");
+    if (e2 != hipSuccess) return hipfail(e2, "hipFreeAsync");
+    return PSDP_OK;
+}
+
+psdp_status psdp_perturbation(int64_t n, double sigma, uint64_t seed, int32_t mode, double *mu,
+                              hipStream_t st) {
+    g_err.clear();
+    if (n < 1 || !mu) return fail(PSDP_E_INVALID, "sizes");
+    if (mode < PSDP_PERTURB_NONE || mode > PSDP_PERTURB_DIAG) return fail(PSDP_E_INVALID, "mode");
+    if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(PSDP_E_INVALID, "sigma");
+    hipError_t e = launch_perturbation(n, sigma, seed, mode, mu, st);
+    if (e != hipSuccess) return hipfail(e, "perturbation");
+    return PSDP_OK;
+}
+
+void psdp_release(void) {}
+
+}  // extern "C"

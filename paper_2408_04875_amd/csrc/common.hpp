@@ -1,0 +1,207 @@
+// Shared definitions of the gfx950 vectorized-PSDP library: device state
+// layout, dtype helpers and deterministic block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "../../include/psdp.h"
+
+namespace psdp {
+
+constexpr int kBlock = 256;          // threads of every per-column kernel
+constexpr int kWaves = kBlock / 64;  // wave64
+
+// Column phases of the solver state machine. Each sweep applies Q to exactly
+// one vector per live column; the phase says what that vector was.
+enum Phase : int32_t {
+    PH_DONE = 0,
+    PH_CG = 1,     // x^0 linear solve (eq. (gamma)): operand = search direction
+    PH_EIG0 = 2,   // lambda_min: operand = first basis vector
+    PH_EIG = 3,    // lambda_min: operand = preconditioned residual
+    PH_INNER = 4,  // subproblem: operand = current iterate x^k
+};
+
+// Per-instance data (one problem Q, b); the vectors live at `off` in the
+// instance arrays, padded to `ld` entries (ld multiple of 16, pads are 0).
+struct Inst {
+    int64_t n;
+    int64_t ld;
+    int64_t off;         // offset into b, gamma, R, dq arrays
+    const void *Qop;     // operand copy of Q with zero diagonal, ld x ld row-major
+};
+
+// Per-column state (one start of one instance).
+struct Col {
+    int32_t inst;
+    int32_t phase;
+    int64_t n;
+    int64_t ld;
+    int64_t off;         // offset of this column's vectors (stride ld)
+    int32_t k;           // inner iteration index within the current subproblem
+    int32_t s;           // penalty updates done
+    int32_t stall;       // consecutive subproblems that did not move x
+    int32_t it;          // lambda_min / CG iteration counter
+    int32_t hasP;        // LOBPCG search direction present
+    int32_t exit_reason;
+    int32_t ntrace;      // trace records written
+    int32_t pad0;
+    double rho;          // rho at the current p (Section 3.3)
+    double rho_outer;    // rho at the p of the current penalty update
+    double lam;          // current Ritz value
+    double rz;           // CG: r^T M^-1 r
+    double r0;           // CG: ||r_0||
+    double final_rel;    // cret/rho of the last evaluation
+    double final_bg;     // binary gap of the final iterate
+    double alpha;        // penalty step of the current update (eq. (alpha1))
+    int64_t evals;       // penalty-gradient evaluations
+    int64_t aux;         // lambda_min and CG products
+    int64_t inner_start; // evals at the start of the current subproblem
+    int32_t nI;          // |I| of the current penalty update
+    int32_t pad1;
+};
+
+// Flat solver workspace (device pointers), passed to every solver kernel.
+struct Work {
+    int32_t ncol;
+    int32_t ksplit;      // number of U slices to sum (split-K)
+    int64_t slice;       // elements per U slice
+    Inst *inst;
+    Col *col;
+    // instance vectors
+    double *b, *gam, *R, *dq;
+    // column vectors
+    double *x, *xp, *g, *gp, *p, *v, *Av, *P, *AP, *w;
+    void *op;            // operand buffer (OpT), column layout as the vectors
+    void *U;             // Q.X output (UT), ksplit slices
+    int32_t *active;     // live column list for the next sweep (split: PH_INNER only)
+    int32_t *nactive;
+    // split precision: lambda_min and CG products use their own FP64 operand
+    // and product buffers and their own live list; otherwise these alias the
+    // main ones
+    int32_t split;
+    int32_t ksplit_aux;
+    int64_t slice_aux;
+    double *op_aux;
+    double *U_aux;
+    int32_t *active_aux;
+    int32_t *nactive_aux;
+    double *trace;       // per column trace_cap records of 6 doubles, or null
+    int32_t trace_cap;
+    // parameters
+    int32_t inner;       // psdp_inner
+    int32_t max_inner, max_outer, stall_outer, eig_maxit, cg_maxit;
+    double tol_kkt, tol_binary, eta, eps_hp, lambda_floor_rel, alpha_min, alpha_max;
+    double eig_tol, cg_tol;
+};
+
+// ---------------------------------------------------------------------------
+// dtype helpers
+
+template <typename T> __device__ __forceinline__ double to_f64(T v);
+template <> __device__ __forceinline__ double to_f64<double>(double v) { return v; }
+template <> __device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
+template <> __device__ __forceinline__ double to_f64<__hip_bfloat16>(__hip_bfloat16 v) {
+    return (double)__bfloat162float(v);
+}
+
+template <typename T> __device__ __forceinline__ T from_f64(double v);
+template <> __device__ __forceinline__ double from_f64<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_f64<float>(double v) { return __double2float_rn(v); }
+template <> __device__ __forceinline__ __hip_bfloat16 from_f64<__hip_bfloat16>(double v) {
+    // double -> float is exact for every value the callers pass (vectors in
+    // [0,1] or preconditioned residuals); float -> bf16 rounds to nearest even
+    return __float2bfloat16(__double2float_rn(v));
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions over kBlock threads: a fixed butterfly inside
+// each wave, then the wave partials combined in wave order. Every thread gets
+// the result. `scratch` must hold N * kWaves doubles of shared memory.
+
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *scratch) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[j] += __shfl_xor(v[j], o, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) scratch[j * kWaves + wv] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = scratch[j * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) s += scratch[j * kWaves + q];
+        v[j] = s;
+    }
+    __syncthreads();
+}
+
+template <int N>
+__device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[j] = fmax(v[j], __shfl_xor(v[j], o, 64));
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) scratch[j * kWaves + wv] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = scratch[j * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) s = fmax(s, scratch[j * kWaves + q]);
+        v[j] = s;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers implemented in the kernel translation units.
+
+hipError_t launch_prep_q(int dtype, const int32_t *Q, int64_t n, int64_t ld, int perturb,
+                         double sigma, uint64_t seed, void *Qop, double *R, double *dq,
+                         hipStream_t st);
+hipError_t launch_perturbation(int64_t n, double sigma, uint64_t seed, int mode, double *mu,
+                               hipStream_t st);
+hipError_t launch_round_objective(const int32_t *Q, const int32_t *b, int64_t n,
+                                  const double *X, int64_t ldx, int64_t B, uint8_t *xhat,
+                                  int64_t ldh, int64_t *obj, int64_t *partial, hipStream_t st);
+
+// Q.X products. U receives sum_j Qop[i][j] * op[j] for every live column.
+hipError_t launch_gemv(int dtype, const Inst *inst_host, int ninst_same, const Work &w,
+                       int ncol_max, hipStream_t st);
+hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart,
+                             int64_t total_rows, hipStream_t st);
+hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
+                       const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
+                       int ncol_max, hipStream_t st);
+
+// Solver kernels.
+hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,
+                              hipStream_t st);
+hipError_t launch_solver_step(int optype, int utype, const Work &w, hipStream_t st);
+hipError_t launch_compact(const Work &w, hipStream_t st);
+hipError_t launch_compact_count(const Work &w, int64_t *sweeps, hipStream_t st);
+
+// Evaluation and adjoint.
+hipError_t launch_eval(int dtype, int vtype, const void *Q, int64_t ldq, const void *b,
+                       const void *p, const void *X, int64_t n, int64_t B, void *h, void *G,
+                       double *ws, hipStream_t st);
+hipError_t launch_adjoint(int dtype, int vtype, const void *X, const void *G, const void *w,
+                          int64_t n, int64_t B, void *dX, void *dQ, void *db, void *dp,
+                          hipStream_t st);
+
+}  // namespace psdp

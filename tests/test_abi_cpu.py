@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports what include/psdp.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "psdp.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:psdp_status|void|const char \*|int32_t)\s*(psdp_\w+)\(", txt, re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_binding_signatures_cover_header():
+    from paper_2408_04875_amd import binding
+    assert sorted(binding.SIGNATURES) == _declared()
+
+
+def test_params_defaults_and_struct_size(lib):
+    from paper_2408_04875_amd import binding
+    p = binding.default_params()
+    assert p.struct_size == ctypes.sizeof(binding.Params)
+    assert (p.max_inner, p.max_outer, p.tol_kkt) == (10000, 1000, 1e-5)   # Section 5
+    assert p.eta == 0.999 and p.stall_outer == 2
+    q = binding.default_params(inner="ppa", qx_dtype="f32", perturb="diag", sigma=0.5)
+    assert (q.inner, q.qx_dtype, q.perturb, q.sigma) == (1, 1, 2, 0.5)
+    with pytest.raises(TypeError):
+        binding.default_params(bogus=1)
+
+
+def test_status_strings(lib):
+    for code in range(0, -8, -1):
+        s = lib.psdp_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert lib.psdp_status_string(-99).decode() == "unknown status"
+    assert lib.psdp_version() == 10000
+
+
+def test_invalid_arguments_fail_before_device_work(lib):
+    from paper_2408_04875_amd import binding
+    p = binding.default_params()
+    st = lib.psdp_solve_i32(None, None, 4, None, None, 1, ctypes.byref(p), None, None, None, None, None, None)
+    assert st == -1
+    assert "null" in lib.psdp_last_error().decode()
+    bad = binding.default_params(eta=1.5)
+    dummy = ctypes.c_void_p(16)
+    st = lib.psdp_solve_i32(dummy, dummy, 4, None, None, 1, ctypes.byref(bad), dummy, dummy, None, None,
+                            None, None)
+    assert st == -1 and "eta" in lib.psdp_last_error().decode()
+    wrong = binding.default_params()
+    wrong.struct_size = 8
+    st = lib.psdp_solve_i32(dummy, dummy, 4, None, None, 1, ctypes.byref(wrong), dummy, dummy, None, None,
+                            None, None)
+    assert st == -1 and "struct_size" in lib.psdp_last_error().decode()
+    st = lib.psdp_eval_penalty_grad(7, 0, dummy, 4, dummy, dummy, dummy, 4, 1, dummy, None, None)
+    assert st == -1
+    st = lib.psdp_penalty_adjoint(2, 0, dummy, dummy, dummy, 4, 1, None, None, None, None, None)
+    assert st == -7
+    st = lib.psdp_perturbation(0, 1.0, 0, 1, dummy, None)
+    assert st == -1
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    pkg = os.path.join(ROOT, "paper_2408_04875_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "workloads" not in txt, f

@@ -1,0 +1,145 @@
+"""GPU parity of the whole solve (Algorithm 3) against the FP64 oracle.
+
+Where trajectories are stable (n <= 64) the rounded solution and the int64
+objective must be bit-exact. Per-penalty-update traces (|I|, lambda_min,
+alpha, subproblem length) are compared step by step.
+"""
+import numpy as np
+import pytest
+
+from oracle import psdp as O
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2408_04875_amd as P
+    assert torch.cuda.is_available()
+    P.load()
+    return P
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("qdt", ["f64", "f32", "bf16"])
+def test_plain_solve_bruteforce_set_bit_exact(P, qdt):
+    mism = []
+    cases = gen.bruteforce_set()
+    for seed, Q, b in cases:
+        r = P.solve(_t(Q), _t(b), qx_dtype=qdt)
+        ref = O.solve(Q, b)
+        got = int(r.obj[0].item())
+        if got != ref.obj or not np.array_equal(r.xhat.cpu().numpy(), ref.xhat):
+            mism.append((seed, got, ref.obj))
+        st = r.stats[0]
+        assert st["exit_reason"] == ref.exit_reason
+    print(f"bruteforce set {qdt}: {len(cases) - len(mism)}/{len(cases)} bit-exact; mismatches {mism}", flush=True)
+    assert not mism
+
+
+def test_plain_solve_n64_trace_matches_oracle(P):
+    Q, b = gen.small_dense(0)
+    r = P.solve(_t(Q), _t(b), trace_cap=200)
+    ref = O.solve(Q, b)
+    st = r.stats[0]
+    print(f"n=64 gpu obj {int(r.obj[0])} outer {st['outer_iters']} inner {st['inner_iters']} aux {st['aux_matvecs']}"
+          f" | oracle obj {ref.obj} outer {ref.outer_iters} inner {ref.inner_iters}", flush=True)
+    assert int(r.obj[0]) == ref.obj
+    assert np.array_equal(r.xhat.cpu().numpy(), ref.xhat)
+    assert st["outer_iters"] == ref.outer_iters
+    tr = r.trace[0]
+    worst = 0.0
+    for s, t in enumerate(ref.trace):
+        assert tr[s, 1] == t["nI"]
+        worst = max(worst, abs(tr[s, 2] - t["lam"]) / abs(t["lam"]))
+        assert tr[s, 4] == t["inner"]
+    print(f"n=64 lambda_min: LOBPCG vs dense eigensolver, worst relative gap {worst:.2e}", flush=True)
+    # the dense eigensolver's error on the graded matrix Z^-1/2 Qbar Z^-1/2 is
+    # about eps * ||M||, which reaches 1e-6 of lambda when some z_i is tiny
+    assert worst <= 1e-5
+
+
+def test_initial_point_matches_cholesky(P):
+    """max_outer = 0 returns x^0 of eq. (gamma) (CG on the GPU, Cholesky in the oracle)."""
+    Q, b = gen.dense_int(200, 77)
+    r = P.solve(_t(Q), _t(b), max_outer=0)
+    gam = O.reformation_gamma(Q, b)
+    x0 = O.initial_point(Q + np.diag(gam), b - gam)
+    assert np.max(np.abs(r.X.cpu().numpy() - x0)) <= 1e-10
+    assert r.stats[0]["exit_reason"] == O.OUTER_CAP
+
+
+def _invariants(Q, b, r, tol_binary=1e-5):
+    """Exact properties of any returned solve, whatever its trajectory."""
+    X = r.X.cpu().numpy().reshape(-1, len(b))
+    xh = r.xhat.cpu().numpy().reshape(-1, len(b))
+    obj = r.obj.cpu().numpy()
+    Q64 = Q.astype(np.int64)
+    for c in range(len(obj)):
+        assert np.array_equal(xh[c], (X[c] > 0.5).astype(np.uint8))
+        v = xh[c].astype(np.int64)
+        assert obj[c] == int(v @ Q64 @ v + b.astype(np.int64) @ v)
+        st = r.stats[c]
+        if st["exit_reason"] == O.CONVERGED:
+            assert O.binary_gap(X[c]) <= tol_binary
+        assert ((X[c] >= 0) & (X[c] <= 1)).all()
+
+
+def test_single_start_from_x0_matches_oracle(P):
+    """Random starts are chaotic even at n = 64: most, not all, must match."""
+    Q, b = gen.dense_int(64, 3)
+    X0 = gen.random_box_points(64, 6, 11)
+    res = []
+    for c in range(len(X0)):
+        r = P.solve(_t(Q), _t(b), X0=_t(X0[c]))
+        _invariants(Q, b, r)
+        ref = O.solve(Q, b, x0=X0[c])
+        res.append((int(r.obj[0]), ref.obj))
+    print(f"single start from x0 (gpu obj, oracle obj): {res}", flush=True)
+    assert sum(a == b_ for a, b_ in res) >= 5
+
+
+@pytest.mark.parametrize("qdt", ["f64", "f32"])
+def test_batched_starts_match_per_start_oracle(P, qdt):
+    Q, b = gen.dense_int(64, 3)
+    X0 = gen.random_box_points(64, 24, 11)
+    r = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype=qdt)
+    _invariants(Q, b, r)
+    got = r.obj.cpu().numpy()
+    ref = [O.solve(Q, b, x0=X0[c]) for c in range(len(X0))]
+    match = sum(int(got[c] == ref[c].obj) for c in range(len(X0)))
+    print(f"batched {qdt}: {match}/{len(X0)} starts with the oracle objective", flush=True)
+    print("  gpu   ", [int(v) for v in got], flush=True)
+    print("  oracle", [rr.obj for rr in ref], flush=True)
+    best = min(range(len(X0)), key=lambda c: (got[c], c))
+    assert r.best == best
+    assert min(got) == min(rr.obj for rr in ref)          # best-of-batch objective
+    assert match >= (22 if qdt == "f64" else 20)
+
+
+def test_group_equals_single_instance_path_and_oracle(P):
+    """The grouped launch performs exactly the single-instance arithmetic."""
+    insts = gen.uneven_group(seed=4, count=8, nmin=20, nmax=90)
+    sigma = max(1e-3 * float(np.abs(d["Q"]).max()) for d in insts)
+    Qs = [_t(d["Q"]) for d in insts]
+    bs = [_t(d["b"]) for d in insts]
+    xh, obj, stats = P.solve_group(Qs, bs, seeds=[d["seed"] for d in insts], sigma=sigma, perturb="diag")
+    got = obj.cpu().numpy()
+    match = 0
+    for i, d in enumerate(insts):
+        one = P.solve(Qs[i], bs[i], sigma=sigma, perturb="diag", seed=d["seed"])
+        assert int(one.obj[0]) == got[i]
+        assert np.array_equal(one.xhat.cpu().numpy(), xh[i].cpu().numpy())
+        assert one.stats[0]["inner_iters"] == stats[i]["inner_iters"]
+        assert one.stats[0]["aux_matvecs"] == stats[i]["aux_matvecs"]
+        ref = O.solve(d["Q"], d["b"], O.Params(sigma=sigma, perturb="diag", seed=d["seed"]))
+        match += int(got[i] == ref.obj)
+        print(f"  inst {i} {d['kind']} n={d['n']}: gpu {got[i]} oracle {ref.obj}", flush=True)
+    print(f"group: {match}/{len(insts)} oracle objectives", flush=True)
+    assert match >= 5

@@ -404,3 +404,23 @@ def test_no_progress_exit_matches_shift_law():
     assert all(t["inner"] == 1 for t in tail)
     for prev, nxt in zip(tail[:-1], tail[1:]):
         assert abs(nxt["lam"] - (1 - prm.eta) * prev["lam"]) <= 1e-6 * abs(prev["lam"])
+
+
+def test_trajectory_sensitivity_at_ulp_level():
+    """Documents why full-trajectory parity is ill-posed beyond small cases.
+
+    With eta = 0.999 each penalty update leaves the scaled matrix within
+    (1 - eta) of singular, so the subproblem amplifies perturbations; a
+    relative change of 1e-14 in lambda (a few ulps) already changes the
+    number of evaluations and here the final objective.
+    """
+    d = gen.uneven_group(seed=4, count=8, nmin=20, nmax=90)[2]
+    prm = O.Params(sigma=0.1, perturb="diag", seed=d["seed"])
+    base = O.solve(d["Q"], d["b"], prm)
+    orig = O.lambda_min_scaled
+    try:
+        O.lambda_min_scaled = lambda *a: (lambda t: (t[0] * (1 - 1e-14), t[1], t[2]))(orig(*a))
+        nudged = O.solve(d["Q"], d["b"], prm)
+    finally:
+        O.lambda_min_scaled = orig
+    assert nudged.inner_iters != base.inner_iters
