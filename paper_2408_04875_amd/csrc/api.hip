@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -35,7 +36,9 @@ psdp_status hipfail(hipError_t e, const char *where) {
         if (e_ != hipSuccess) return hipfail(e_, #expr); \
     } while (0)
 
-int64_t pad16(int64_t n) { return (n + 15) / 16 * 16; }
+// Leading dimension of every operand copy: a multiple of the GEMM K chunk
+// (32), zero padded, so that 16-byte loads of whole chunks stay in bounds.
+int64_t padld(int64_t n) { return (n + 31) / 32 * 32; }
 
 // Device allocations released in reverse order when the solve returns.
 struct Arena {
@@ -72,7 +75,7 @@ psdp_status check_params(const psdp_params &p) {
 
 // Host-side checks of one integer instance (Q and b already copied back).
 psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int32_t> &b, int64_t n,
-                           const psdp_params &p) {
+                           const psdp_params &p, int64_t *offmax_out = nullptr) {
     int64_t qmax = 0, bmax = 0, offmax = 0;
     for (int64_t i = 0; i < n; ++i) {
         bmax = std::max<int64_t>(bmax, std::llabs((long long)b[i]));
@@ -98,6 +101,7 @@ psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int3
         return fail(PSDP_E_UNSUPPORTED, "bfloat16 operands need |Q_ij| <= 256 off the diagonal");
     if (p.qx_dtype == PSDP_F32 && offmax > (1 << 24))
         return fail(PSDP_E_UNSUPPORTED, "float operands need |Q_ij| <= 2^24 off the diagonal");
+    if (offmax_out) *offmax_out = offmax;
     return PSDP_OK;
 }
 
@@ -123,12 +127,15 @@ __global__ void fill_p_kernel(double *p, const double *p0, int64_t n, int64_t ld
     p[idx] = (p0 && i < n) ? p0[i] : 0.0;
 }
 
+constexpr int kMaxSplit = 8;
+
 struct Solver {
     Arena ar;
     Work w{};
+    std::function<void(int, int)> repick;  // adapts split-K to the live counts
     int optype = PSDP_F64, utype = PSDP_F64;
     int64_t *sweeps = nullptr;
-    int32_t *partial_dummy = nullptr;
+    int64_t nmax = 0;  // largest column length (selects the per-thread unroll)
 };
 
 void fill_work_params(Work &w, const psdp_params &p) {
@@ -159,7 +166,7 @@ psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit) {
     }
     HIPCHK(S.ar.get(&w.op, total * esize(S.optype)));
     HIPCHK(hipMemset(w.op, 0, total * esize(S.optype)));
-    w.ksplit = (int32_t)ksplit;
+    w.ksplit = 1;
     w.slice = total;
     HIPCHK(S.ar.get(&w.U, ksplit * total * esize(S.utype)));
     HIPCHK(hipMemset(w.U, 0, ksplit * total * esize(S.utype)));
@@ -169,9 +176,12 @@ psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit) {
     w.nactive_aux = w.nactive + 1;
     HIPCHK(S.ar.get((void **)&S.sweeps, 64));
     HIPCHK(hipMemset(S.sweeps, 0, 64));
+    w.sweeps = S.sweeps;
+    HIPCHK(S.ar.get((void **)&w.done_count, 64));
+    HIPCHK(hipMemset(w.done_count, 0, 64));
     w.ncol = ncol;
     if (S.w.split) {
-        w.ksplit_aux = (int32_t)ksplit;
+        w.ksplit_aux = 1;
         w.slice_aux = total;
         HIPCHK(S.ar.get((void **)&w.op_aux, total * sizeof(double)));
         HIPCHK(hipMemset(w.op_aux, 0, total * sizeof(double)));
@@ -269,8 +279,7 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
                 HIPCHK(apply_aux());
                 HIPCHK(ta.end(st));
             }
-            HIPCHK(launch_solver_step(S.optype, S.utype, w, st));
-            HIPCHK(launch_compact_count(w, S.sweeps, st));
+            HIPCHK(launch_solver_step(S.optype, S.utype, w, S.nmax, st));
         }
         done_sweeps += nb;
         const int slot = batch & 1;
@@ -280,6 +289,7 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
             const int prev = slot ^ 1;
             HIPCHK(hipEventSynchronize(evs[prev]));
             if (host_cnt[2 * prev] + host_cnt[2 * prev + 1] == 0) finished = true;
+            else if (S.repick) S.repick(host_cnt[2 * prev], host_cnt[2 * prev + 1]);
         }
         if ((tm.on && tm.used > 4096) || (ta.on && ta.used > 4096)) {
             HIPCHK(hipEventSynchronize(evs[slot]));
@@ -399,7 +409,8 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         HIPCHK(hipMemcpyAsync(hp0.data(), p0, n * sizeof(double), hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
-    if (psdp_status s = check_instance(hQ, hb, n, prm)) return s;
+    int64_t offmax = 0;
+    if (psdp_status s = check_instance(hQ, hb, n, prm, &offmax)) return s;
     for (double v : hX0)
         if (!(v >= 0.0 && v <= 1.0)) return fail(PSDP_E_NONFINITE, "X0 entries must lie in [0,1]");
     for (double v : hp0)
@@ -409,26 +420,39 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
 
     Solver S;
     const bool batched = B > 1;
-    const int64_t ld = pad16(n);
+    const int64_t ld = padld(n);
     S.optype = batched ? prm.qx_dtype : PSDP_F64;  // single instance: FP64 x, Q in qx_dtype
     S.utype = batched ? prm.qx_dtype : PSDP_F64;
     Work &w = S.w;
+    S.nmax = n;
     fill_work_params(w, prm);
     // batched lower-precision products: lambda_min and CG keep FP64 operands
     w.split = (batched && prm.qx_dtype != PSDP_F64) ? 1 : 0;
-    // instance data
+    // Q~ off the diagonal is exact in FP32 for integers up to 2^24 unless a
+    // FULL perturbation adds 2^-16-grid values to entries of 2^8 or more
+    const bool q32_exact = offmax <= (1 << 24) &&
+                           (prm.perturb != PSDP_PERTURB_FULL || prm.sigma == 0.0 ||
+                            (double)offmax + 3.5 * prm.sigma < 256.0);
+    // Qop: operand of the main product; Qaux: operand of the FP64 products
+    // (the exact FP32 copy widened in the kernel, or an FP64 copy)
+    const int qtype = batched ? ((prm.qx_dtype == PSDP_F32 || q32_exact) ? PSDP_F32 : PSDP_F64) : prm.qx_dtype;
+    int main_gemm = PSDP_F64, aux_gemm = PSDP_F64;
+    if (batched) {
+        main_gemm = prm.qx_dtype == PSDP_F32 ? PSDP_F32 : (q32_exact ? kGemmF32QF64 : PSDP_F64);
+        aux_gemm = q32_exact ? kGemmF32QF64 : PSDP_F64;
+    }
     void *Qop = nullptr;
-    HIPCHK(S.ar.get(&Qop, ld * ld * esize(prm.qx_dtype)));
+    HIPCHK(S.ar.get(&Qop, ld * ld * esize(qtype)));
     double *bd, *gam, *R, *dq;
     HIPCHK(S.ar.get((void **)&bd, ld * 8));
     HIPCHK(S.ar.get((void **)&gam, ld * 8));
     HIPCHK(S.ar.get((void **)&R, ld * 8));
     HIPCHK(S.ar.get((void **)&dq, ld * 8));
-    HIPCHK(launch_prep_q(prm.qx_dtype, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qop, R, dq, st));
-    void *Qop64 = Qop;
-    if (w.split) {
-        HIPCHK(S.ar.get(&Qop64, ld * ld * sizeof(double)));
-        HIPCHK(launch_prep_q(PSDP_F64, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qop64, R, dq, st));
+    HIPCHK(launch_prep_q(qtype, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qop, R, dq, st));
+    void *Qaux = Qop;
+    if (w.split && aux_gemm == PSDP_F64) {
+        HIPCHK(S.ar.get(&Qaux, ld * ld * sizeof(double)));
+        HIPCHK(launch_prep_q(PSDP_F64, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qaux, R, dq, st));
     }
     hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, st, b, R, dq, n, ld,
                        bd, gam);
@@ -441,11 +465,36 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(S.ar.get((void **)&w.inst, sizeof(Inst)));
     HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
     // column data
-    int ksplit = 1;
-    if (batched) {
-        ksplit = prm.gemm_variant > 0 ? std::min(16, prm.gemm_variant & 0xff) : (n >= 1024 ? 4 : 1);
-    }
-    if (psdp_status s2 = alloc_columns(S, ld * B, B, ksplit)) return s2;
+    const int kmax = batched ? kMaxSplit : 1;
+    if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax)) return s2;
+    const int MT = (int)((ld + 63) / 64);
+    // Product kernel per live count (the count comes from the last host poll,
+    // so it is an estimate; every kernel covers all B columns regardless):
+    // up to 64 live columns the wave-streaming kernel (needs the FP32 copy of
+    // Q), above that the LDS-tiled GEMM with enough split-K for ~512 tiles.
+    struct Pick { bool stream; int nt; int ks; };
+    auto pick = [&](int ncols, int gemm_dtype) {
+        Pick pk{false, 4, 1};
+        if (!batched) return pk;
+        if (prm.gemm_variant > 0) {
+            pk.ks = std::min(kMaxSplit, prm.gemm_variant & 0xff);
+            pk.stream = (prm.gemm_variant & 0x100) != 0 && gemm_dtype != PSDP_F64;
+            pk.nt = 4;
+            return pk;
+        }
+        if (ncols <= 64 && gemm_dtype != PSDP_F64) {
+            pk.stream = true;
+            pk.nt = ncols <= 16 ? 1 : (ncols <= 32 ? 2 : 4);
+            pk.ks = 4;
+            return pk;
+        }
+        const int tiles = MT * std::max(1, (ncols + 63) / 64);
+        pk.ks = std::max(1, std::min(kMaxSplit, (512 + tiles - 1) / tiles));
+        return pk;
+    };
+    Pick pm = pick(B, main_gemm), pa = pick(B, aux_gemm);
+    w.ksplit = pm.ks;
+    w.ksplit_aux = w.split ? pa.ks : w.ksplit;
     std::vector<Col> hcol(B);
     for (int c = 0; c < B; ++c) {
         Col &cc = hcol[c];
@@ -476,14 +525,25 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         rs = run_sweeps(S, prm, tm, ta, st, [&]() { return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st); },
                         none);
     } else {
+        S.repick = [&](int cm, int ca) {
+            pm = pick(cm, main_gemm);
+            pa = pick(ca, aux_gemm);
+            w.ksplit = pm.ks;
+            w.ksplit_aux = w.split ? pa.ks : w.ksplit;
+        };
         rs = run_sweeps(
             S, prm, tm, ta, st,
             [&]() {
-                return launch_gemm(prm.qx_dtype, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit,
-                                   B, st);
+                if (pm.stream)
+                    return launch_stream(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit, B,
+                                         pm.nt, st);
+                return launch_gemm(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit, B, st);
             },
             [&]() {
-                return launch_gemm(PSDP_F64, Qop64, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
+                if (pa.stream)
+                    return launch_stream(aux_gemm, Qaux, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
+                                         w.slice_aux, w.ksplit_aux, B, pa.nt, st);
+                return launch_gemm(aux_gemm, Qaux, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
                                    w.slice_aux, w.ksplit_aux, B, st);
             });
     }
@@ -565,9 +625,10 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     S.utype = PSDP_F64;
     Work &w = S.w;
     fill_work_params(w, prm);
+    for (int i = 0; i < count; ++i) S.nmax = std::max<int64_t>(S.nmax, n[i]);
     std::vector<int64_t> ld(count), off(count + 1, 0), rowstart(count + 1, 0);
     for (int i = 0; i < count; ++i) {
-        ld[i] = pad16(n[i]);
+        ld[i] = padld(n[i]);
         off[i + 1] = off[i] + ld[i];
         rowstart[i + 1] = rowstart[i] + n[i];
     }

@@ -10,8 +10,10 @@
 
 namespace psdp {
 
-constexpr int kBlock = 256;          // threads of every per-column kernel
+constexpr int kBlock = 256;          // threads of the generic kernels
 constexpr int kWaves = kBlock / 64;  // wave64
+constexpr int kSB = 512;             // threads of the per-column solver kernel
+constexpr int kSWaves = kSB / 64;
 
 // Column phases of the solver state machine. Each sweep applies Q to exactly
 // one vector per live column; the phase says what that vector was.
@@ -87,6 +89,8 @@ struct Work {
     double *U_aux;
     int32_t *active_aux;
     int32_t *nactive_aux;
+    int32_t *done_count;  // blocks finished in the current sweep (last one compacts)
+    int64_t *sweeps;      // sweep counter (nullable)
     double *trace;       // per column trace_cap records of 6 doubles, or null
     int32_t trace_cap;
     // parameters
@@ -120,8 +124,9 @@ template <> __device__ __forceinline__ __hip_bfloat16 from_f64<__hip_bfloat16>(d
 // each wave, then the wave partials combined in wave order. Every thread gets
 // the result. `scratch` must hold N * kWaves doubles of shared memory.
 
-template <int N>
+template <int N, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[N], double *scratch) {
+    constexpr int kWaves = NT / 64;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
 #pragma unroll
@@ -144,8 +149,9 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *scratch) {
     __syncthreads();
 }
 
-template <int N>
+template <int N, int NT = kBlock>
 __device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
+    constexpr int kWaves = NT / 64;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
 #pragma unroll
@@ -180,11 +186,17 @@ hipError_t launch_round_objective(const int32_t *Q, const int32_t *b, int64_t n,
                                   const double *X, int64_t ldx, int64_t B, uint8_t *xhat,
                                   int64_t ldh, int64_t *obj, int64_t *partial, hipStream_t st);
 
+// GEMM operand mode: FP32-stored Q (exact) widened to FP64, FP64 operands.
+constexpr int kGemmF32QF64 = 16;
+
 // Q.X products. U receives sum_j Qop[i][j] * op[j] for every live column.
 hipError_t launch_gemv(int dtype, const Inst *inst_host, int ninst_same, const Work &w,
                        int ncol_max, hipStream_t st);
 hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart,
                              int64_t total_rows, hipStream_t st);
+hipError_t launch_stream(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
+                         const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
+                         int ncol_max, int nt, hipStream_t st);
 hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
                        const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
                        int ncol_max, hipStream_t st);
@@ -192,9 +204,8 @@ hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, v
 // Solver kernels.
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,
                               hipStream_t st);
-hipError_t launch_solver_step(int optype, int utype, const Work &w, hipStream_t st);
+hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax, hipStream_t st);
 hipError_t launch_compact(const Work &w, hipStream_t st);
-hipError_t launch_compact_count(const Work &w, int64_t *sweeps, hipStream_t st);
 
 // Evaluation and adjoint.
 hipError_t launch_eval(int dtype, int vtype, const void *Q, int64_t ldq, const void *b,

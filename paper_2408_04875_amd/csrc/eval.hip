@@ -199,7 +199,7 @@ static hipError_t eval_mfma(const T *Q, int64_t n, const VT *b, const VT *p, con
 hipError_t launch_eval(int dtype, int vtype, const void *Q, int64_t ldq, const void *b,
                        const void *p, const void *X, int64_t n, int64_t B, void *h, void *G,
                        double *ws, hipStream_t st) {
-    const bool aligned = (n % 16 == 0) && (ldq == n) && ((uintptr_t)Q % 16 == 0) &&
+    const bool aligned = (n % 32 == 0) && (ldq == n) && ((uintptr_t)Q % 16 == 0) &&
                          ((uintptr_t)X % 16 == 0);
 #define EVAL_V(QT, VT)                                                                          \
     return (aligned && dtype != PSDP_BF16)                                                      \

@@ -94,10 +94,23 @@ __global__ void __launch_bounds__(kBlock) gemv_group_kernel(const Col *col, cons
 }
 
 // ---------------------------------------------------------------------------
-// MFMA GEMM: block tile BM x BN (BM = BN = 64), 4 waves each 32 x 32 made of
-// 2 x 2 MFMA 16x16 tiles. MFMA 16x16x4 operand layout (wave64): lane l holds
-// A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator rows differ
-// between the FP32 and FP64 instructions (Mfma<T>::row, measured on gfx950).
+// MFMA GEMM, U[:, c] = Q X[:, c] for the live columns c (block tile 64 x 64,
+// 4 waves of 32 x 32, each 2 x 2 MFMA 16x16x4 tiles).
+//
+// LDS holds the Q tile row-major (row m, contiguous k) and the X tile column
+// by column (column n, contiguous k): both are straight copies of global
+// memory. The MFMA 16x16x4 operand layout gives lane l the entries
+// A[l % 16][k] and B[k][l % 16] with k = l / 16; over four instructions the
+// lane group g = l / 16 instead reads the 16-byte run k = 4 g .. 4 g + 3 of
+// its row once and feeds one element to each instruction, so the four
+// instructions together cover 16 consecutive k (the sum is the same set of
+// products in another order). The accumulator rows differ between the FP32
+// and FP64 instructions (Mfma<T>::row, measured on gfx950).
+//
+// TA is the storage type of Q (float or double), T the MFMA type (float, or
+// double with Q widened exactly while staging). The K range is split into
+// ksplit slices written to separate outputs; blocks are ordered so that the
+// column tiles sharing one Q block run on the same XCD (same L2).
 
 template <typename T> struct Mfma;
 template <> struct Mfma<float> {
@@ -117,73 +130,139 @@ template <> struct Mfma<double> {
     static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-template <typename T, int BK>
-__global__ void __launch_bounds__(kBlock) gemm_kernel(const T *Q, int64_t ld, const T *X,
+constexpr int kGM = 64, kGN = 64, kGK = 32;
+
+template <typename T> struct GemmLds {
+    static constexpr int PAD = sizeof(T) == 4 ? 4 : 2;  // conflict-free 16-byte row reads
+    static constexpr int LDK = kGK + PAD;
+};
+
+// Loads one 64 x 32 tile row-slice per thread group: thread t covers row
+// t / 4 and k = (t % 4) * 8 .. + 7 (8 elements).
+template <typename TA>
+__device__ __forceinline__ void load8(const TA *src, bool ok, TA (&v)[8]) {
+    if (!ok) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (TA)0;
+        return;
+    }
+    if constexpr (sizeof(TA) == 4) {
+        const float4 a = *(const float4 *)src, b = *(const float4 *)(src + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 a = *(const double2 *)(src + 2 * q);
+            v[2 * q] = a.x;
+            v[2 * q + 1] = a.y;
+        }
+    }
+}
+
+template <typename T, typename TA>
+__device__ __forceinline__ void store8(T *dst, const TA (&v)[8]) {
+    if constexpr (sizeof(T) == 4) {
+        *(float4 *)dst = make_float4(v[0], v[1], v[2], v[3]);
+        *(float4 *)(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(double2 *)(dst + 2 * q) = make_double2((double)v[2 * q], (double)v[2 * q + 1]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void lds4(const T *src, T (&v)[4]) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = *(const float4 *)src;
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else {
+        const double2 a = *(const double2 *)src, b = *(const double2 *)(src + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+}
+
+template <typename T, typename TA>
+__global__ void __launch_bounds__(kBlock) gemm_kernel(const TA *Q, int64_t ld, const T *X,
                                                       const int32_t *active,
                                                       const int32_t *nactive, T *U,
-                                                      int64_t slice, int64_t kchunk) {
-    constexpr int BM = 64, BN = 64, PAD = 16;
-    constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte load
-    constexpr int LOADS = BK / 4 / VEC;           // 16-byte loads per thread per tile row quarter
+                                                      int64_t slice, int64_t kchunk, int MT,
+                                                      int NT, int KS) {
     typedef typename Mfma<T>::acc_t acc_t;
+    constexpr int LDK = GemmLds<T>::LDK;
+    __shared__ __attribute__((aligned(16))) T As[2][kGM * LDK];
+    __shared__ __attribute__((aligned(16))) T Bs[2][kGN * LDK];
+    // XCD-aware order: consecutive tile ids (same Q block, different column
+    // tiles) go to blocks dispatched on the same XCD
+    const int total = MT * NT * KS;
+    const int per = (total + 7) / 8;
+    const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (L >= total) return;
+    const int nt = L % NT, mt = (L / NT) % MT, kz = L / (NT * MT);
     const int nact = *nactive;
-    const int n0 = blockIdx.y * BN;
+    const int n0 = nt * kGN;
     if (n0 >= nact) return;
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t m0 = (int64_t)mt * kGM;
+    const int64_t kbeg = (int64_t)kz * kchunk;
     const int64_t kend = min(ld, kbeg + kchunk);
-    __shared__ T As[BK][BM + PAD];
-    __shared__ T Bs[BK][BN + PAD];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    const int lrow = t >> 2, lk = (t & 3) * 8;
+    const int64_t grow = m0 + lrow;
+    const bool arow_ok = grow < ld;
+    const TA *Ap = Q + (arow_ok ? grow : 0) * ld + lk;
+    const int bslot = n0 + lrow;
+    const bool bcol_ok = bslot < nact;
+    const T *Bp = X + (bcol_ok ? (int64_t)active[bslot] : 0) * ld + lk;
     acc_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-    // each thread stages BK/4 consecutive k of one A row and one B column
-    const int lrow = t >> 2, lk = (t & 3) * (BK / 4);
-    const int64_t grow = m0 + lrow;
-    const bool arow_ok = grow < ld;
-    const T *Ap = Q + (arow_ok ? grow : 0) * ld;
-    const int bslot = n0 + lrow;
-    const bool bcol_ok = bslot < nact;
-    const T *Bp = X + (bcol_ok ? (int64_t)active[bslot] : 0) * ld;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-        T av[BK / 4], bv[BK / 4];
+    TA ra[8];
+    T rb[8];
+    int buf = 0;
+    if (kbeg < kend) {
+        load8<TA>(Ap + kbeg, arow_ok, ra);
+        load8<T>(Bp + kbeg, bcol_ok, rb);
+        store8<T, TA>(&As[0][lrow * LDK + lk], ra);
+        store8<T, T>(&Bs[0][lrow * LDK + lk], rb);
+    }
+    __syncthreads();
+    const int cc = lane & 15, g = lane >> 4;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+        const bool more = k0 + kGK < kend;
+        if (more) {  // prefetch the next chunk into registers
+            load8<TA>(Ap + k0 + kGK, arow_ok, ra);
+            load8<T>(Bp + k0 + kGK, bcol_ok, rb);
+        }
+        const T *as = As[buf], *bs = Bs[buf];
 #pragma unroll
-        for (int q = 0; q < LOADS; ++q) {
-            typedef T vec_t __attribute__((ext_vector_type(VEC)));
-            vec_t a = arow_ok ? *(const vec_t *)(Ap + k0 + lk + q * VEC) : vec_t{};
-            vec_t b = bcol_ok ? *(const vec_t *)(Bp + k0 + lk + q * VEC) : vec_t{};
+        for (int sc = 0; sc < kGK; sc += 16) {
+            T a0[4], a1[4], b0[4], b1[4];
+            lds4<T>(as + (wm + cc) * LDK + sc + 4 * g, a0);
+            lds4<T>(as + (wm + 16 + cc) * LDK + sc + 4 * g, a1);
+            lds4<T>(bs + (wn + cc) * LDK + sc + 4 * g, b0);
+            lds4<T>(bs + (wn + 16 + cc) * LDK + sc + 4 * g, b1);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                av[q * VEC + e] = a[e];
-                bv[q * VEC + e] = b[e];
+            for (int e = 0; e < 4; ++e) {
+                acc[0][0] = Mfma<T>::run(a0[e], b0[e], acc[0][0]);
+                acc[0][1] = Mfma<T>::run(a0[e], b1[e], acc[0][1]);
+                acc[1][0] = Mfma<T>::run(a1[e], b0[e], acc[1][0]);
+                acc[1][1] = Mfma<T>::run(a1[e], b1[e], acc[1][1]);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < BK / 4; ++e) {
-            As[lk + e][lrow] = av[e];
-            Bs[lk + e][lrow] = bv[e];
+        if (more) {
+            store8<T, TA>(&As[buf ^ 1][lrow * LDK + lk], ra);
+            store8<T, T>(&Bs[buf ^ 1][lrow * LDK + lk], rb);
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            const int kr = kk + (lane >> 4), cc = lane & 15;
-            const T a0 = As[kr][wm + cc], a1 = As[kr][wm + 16 + cc];
-            const T b0 = Bs[kr][wn + cc], b1 = Bs[kr][wn + 16 + cc];
-            acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
-            acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
-            acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
-            acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
-        }
+        buf ^= 1;
     }
-    T *Us = U + (int64_t)blockIdx.z * slice;
+    T *Us = U + (int64_t)kz * slice;
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) {
-        const int slot = n0 + wn + ni * 16 + (lane & 15);
+        const int slot = n0 + wn + ni * 16 + cc;
         if (slot >= nact) continue;
         const int64_t c = active[slot];
 #pragma unroll
@@ -195,6 +274,153 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(const T *Q, int64_t ld, co
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-streaming MFMA product for few columns (the common case of the sweep
+// loop): no LDS and no barriers. Each wave owns 16 rows of Q, one K range and
+// one group of up to 64 live columns (NT tiles of 16). Lane l = m + 16 g
+// loads the 16-byte run k = k0 + 4 g .. + 3 of Q row m and of live column
+// 16 t + m, and feeds one element to each of four MFMA 16x16x4 (the same
+// K permutation as the tiled kernel). The K loop is unrolled UNR times so
+// that several chunks of Q are in flight per wave.
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+    static __device__ __forceinline__ void load(const float *p, float (&v)[4]) {
+        const float4 a = *(const float4 *)p;
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    }
+};
+template <> struct Vec4<double> {
+    static __device__ __forceinline__ void load(const double *p, double (&v)[4]) {
+        const double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+};
+
+template <typename T, int NT, int UNR>
+__global__ void __launch_bounds__(kBlock) stream_kernel(const float *Q, int64_t ld, const T *X,
+                                                        const int32_t *active,
+                                                        const int32_t *nactive, T *U,
+                                                        int64_t slice, int64_t kchunk, int MT, int KS,
+                                                        int NG) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    __shared__ acc_t part[kWaves - 1][NT][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gb = blockIdx.x;
+    if (gb >= MT * KS * NG) return;
+    const int mt = gb % MT, kz = (gb / MT) % KS, ng = gb / (MT * KS);
+    const int nact = *nactive;
+    const int c0 = ng * 16 * NT;
+    if (c0 >= nact) return;  // uniform over the block
+    const int m = lane & 15, g = lane >> 4;
+    const int64_t m0 = (int64_t)mt * 16;
+    // the block's K range, split into kWaves contiguous parts (multiples of 16)
+    const int64_t kb = (int64_t)kz * kchunk;
+    const int64_t ke = min(ld, kb + kchunk);
+    const int64_t nchunks = ke > kb ? (ke - kb) / 16 : 0;
+    const int64_t per = (nchunks + kWaves - 1) / kWaves;
+    const int64_t kbeg = kb + 16 * min(nchunks, per * wv);
+    const int64_t kend = kb + 16 * min(nchunks, per * (wv + 1));
+    const float *qrow = Q + (m0 + m) * ld + 4 * g;
+    const T *xcol[NT];
+    bool ok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int slot = c0 + 16 * t + m;
+        ok[t] = slot < nact;
+        xcol[t] = X + (ok[t] ? (int64_t)active[slot] : 0) * ld + 4 * g;
+    }
+    acc_t acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    int64_t k0 = kbeg;
+    for (; k0 + 16 * UNR <= kend; k0 += 16 * UNR) {
+        float a[UNR][4];
+        T b[UNR][NT][4];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            Vec4<float>::load(qrow + k0 + 16 * u, a[u]);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (ok[t]) Vec4<T>::load(xcol[t] + k0 + 16 * u, b[u][t]);
+                else b[u][t][0] = b[u][t][1] = b[u][t][2] = b[u][t][3] = (T)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::run((T)a[u][e], b[u][t][e], acc[t]);
+    }
+    for (; k0 < kend; k0 += 16) {
+        float a[4];
+        Vec4<float>::load(qrow + k0, a);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            T b[4] = {(T)0, (T)0, (T)0, (T)0};
+            if (ok[t]) Vec4<T>::load(xcol[t] + k0, b);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[t] = Mfma<T>::run((T)a[e], b[e], acc[t]);
+        }
+    }
+    // deterministic reduction of the four K parts: wave 0 adds waves 1..3 in order
+    if (wv > 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) part[wv - 1][t][lane] = acc[t];
+    }
+    __syncthreads();
+    if (wv != 0) return;
+#pragma unroll
+    for (int q = 0; q < kWaves - 1; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const acc_t o = part[q][t][lane];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[t][r] += o[r];
+        }
+    T *Us = U + (int64_t)kz * slice;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (!ok[t]) continue;
+        const int64_t c = active[c0 + 16 * t + m];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Us[c * ld + m0 + Mfma<T>::row(lane, r)] = acc[t][r];
+    }
+}
+
+// Wave-streaming product from an FP32 copy of Q: dtype PSDP_F32 (FP32 MFMA)
+// or kGemmF32QF64 (FP64 MFMA on the exactly widened entries). nt (1, 2 or 4)
+// is the number of 16-column tiles per block; the grid covers ncol_max
+// columns whatever nt is, so nt only trades MFMA work against Q re-reads.
+template <typename T, int NT, int UNR>
+static void stream_go(const void *Qop, int64_t ld, const void *op, void *U, const int32_t *active,
+                      const int32_t *nactive, int64_t slice, int ksplit, int ncol_max, hipStream_t st) {
+    int64_t kchunk = (ld + ksplit - 1) / ksplit;
+    kchunk = (kchunk + 15) / 16 * 16;
+    const int MT = (int)(ld / 16), NG = (ncol_max + 16 * NT - 1) / (16 * NT);
+    const dim3 grid((unsigned)(MT * ksplit * NG));
+    hipLaunchKernelGGL((stream_kernel<T, NT, UNR>), grid, dim3(kBlock), 0, st, (const float *)Qop, ld,
+                       (const T *)op, active, nactive, (T *)U, slice, kchunk, MT, ksplit, NG);
+}
+
+hipError_t launch_stream(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
+                         const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
+                         int ncol_max, int nt, hipStream_t st) {
+    if (dtype == PSDP_F32) {
+        if (nt <= 1) stream_go<float, 1, 8>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+        else if (nt == 2) stream_go<float, 2, 8>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+        else stream_go<float, 4, 4>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+    } else if (dtype == kGemmF32QF64) {
+        if (nt <= 1) stream_go<double, 1, 8>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+        else if (nt == 2) stream_go<double, 2, 4>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+        else stream_go<double, 4, 2>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -235,18 +461,27 @@ hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart, 
     return hipGetLastError();
 }
 
+// dtype: PSDP_F32 (FP32 Q and X, FP32 MFMA), PSDP_F64 (FP64 Q and X, FP64
+// MFMA) or kGemmF32QF64 (FP32-stored Q widened exactly, FP64 X, FP64 MFMA).
 hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
                        const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
                        int ncol_max, hipStream_t st) {
     int64_t kchunk = (ld + ksplit - 1) / ksplit;
-    kchunk = (kchunk + 15) / 16 * 16;
-    const dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((ncol_max + 63) / 64), (unsigned)ksplit);
+    kchunk = (kchunk + kGK - 1) / kGK * kGK;
+    const int MT = (int)((ld + kGM - 1) / kGM), NT = (ncol_max + kGN - 1) / kGN;
+    const int total = MT * NT * ksplit;
+    const dim3 grid((unsigned)((total + 7) / 8 * 8));
     if (dtype == PSDP_F32)
-        hipLaunchKernelGGL((gemm_kernel<float, 16>), grid, dim3(kBlock), 0, st, (const float *)Qop, ld,
-                           (const float *)op, active, nactive, (float *)U, slice, kchunk);
+        hipLaunchKernelGGL((gemm_kernel<float, float>), grid, dim3(kBlock), 0, st, (const float *)Qop, ld,
+                           (const float *)op, active, nactive, (float *)U, slice, kchunk, MT, NT, ksplit);
     else if (dtype == PSDP_F64)
-        hipLaunchKernelGGL((gemm_kernel<double, 16>), grid, dim3(kBlock), 0, st, (const double *)Qop,
-                           ld, (const double *)op, active, nactive, (double *)U, slice, kchunk);
+        hipLaunchKernelGGL((gemm_kernel<double, double>), grid, dim3(kBlock), 0, st, (const double *)Qop,
+                           ld, (const double *)op, active, nactive, (double *)U, slice, kchunk, MT, NT,
+                           ksplit);
+    else if (dtype == kGemmF32QF64)
+        hipLaunchKernelGGL((gemm_kernel<double, float>), grid, dim3(kBlock), 0, st, (const float *)Qop,
+                           ld, (const double *)op, active, nactive, (double *)U, slice, kchunk, MT, NT,
+                           ksplit);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -1,9 +1,9 @@
 // Per-column solver state machine of the vectorized PSDP method.
 //
-// One workgroup owns one column (one start of one instance). Every sweep the
-// Q.X kernels apply the off-diagonal part of the (perturbed) Q to one vector
-// per live column; this kernel consumes that product according to the
-// column's phase and prepares the next operand:
+// One workgroup (512 threads) owns one column (one start of one instance).
+// Every sweep the Q.X kernels apply the off-diagonal part of the (perturbed)
+// Q to one vector per live column; this kernel consumes that product
+// according to the column's phase and prepares the next operand:
 //   PH_INNER  subproblem step of Algorithm 2 (projected alternating BB,
 //             eqs. (bb1), (x2)) or Algorithm 1 (diagonal proximal step,
 //             eqs. (d2), (x1)), stopping rule eq. (cret) (Section 3.3);
@@ -16,9 +16,19 @@
 // is never formed: the product covers Q_off and the FP64 diagonal
 // (dq + gamma) - p is applied here, so the gradient is exactly the paper's
 // 2 (Q_r - Diag p) x + (b_r + p) with b_r = b - gamma.
+//
+// Element loops are unrolled EPT times per thread so that every load of a
+// pass is in flight at once; the last workgroup to finish a sweep rebuilds
+// the live-column lists for the next one.
 #include "common.hpp"
 
 namespace psdp {
+
+// Visits i = threadIdx.x + j * kSB (+ multiples of EPT * kSB) for i < n.
+#define FOR_I(n)                                                       \
+    for (int64_t _b = 0; _b < (n); _b += (int64_t)EPT * kSB)           \
+        _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j)             \
+            if (const int64_t i = _b + threadIdx.x + (int64_t)_j * kSB; i < (n))
 
 template <typename UT>
 __device__ __forceinline__ double uval(const Work &w, int64_t idx) {
@@ -52,10 +62,17 @@ __device__ __forceinline__ void put_main(const Work &w, int64_t idx, double v) {
 
 __device__ __forceinline__ bool interior(double x) { return x > 0.0 && x < 1.0; }
 
+template <int N> __device__ __forceinline__ void bsum(double (&v)[N], double *red) {
+    block_sum<N, kSB>(v, red);
+}
+template <int N> __device__ __forceinline__ void bmax(double (&v)[N], double *red) {
+    block_max<N, kSB>(v, red);
+}
+
 // ---------------------------------------------------------------------------
 // Outer loop head (Algorithm 3): exit tests, then start lambda_min.
 
-template <typename OpT>
+template <typename OpT, int EPT>
 __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) {
     const int64_t n = c.n;
     const double *x = w.x + c.off;
@@ -63,7 +80,7 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
     const double *b = w.b + in.off, *gam = w.gam + in.off, *R = w.R + in.off, *dq = w.dq + in.off;
     double mx[4] = {0.0, 0.0, 0.0, 0.0};  // binary gap, pinned-at-half flag, row term, |b_r + p|
     double sm[2] = {0.0, 0.0};            // sum of z over I, |I|
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         mx[0] = fmax(mx[0], fmin(xi, 1.0 - xi));
         if (fabs(xi - 0.5) < 1e-9) mx[1] = 1.0;
@@ -75,8 +92,8 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
         mx[2] = fmax(mx[2], 2.0 * (R[i] + fabs(A)));
         mx[3] = fmax(mx[3], fabs((b[i] - gam[i]) + p[i]));
     }
-    block_max<4>(mx, red);
-    block_sum<2>(sm, red);
+    bmax<4>(mx, red);
+    bsum<2>(sm, red);
     const double rho = fmax(1.0, fmax(mx[2], mx[3]));
     int32_t exitr = -1;
     if (mx[0] <= w.tol_binary) exitr = PSDP_EXIT_CONVERGED;
@@ -100,7 +117,7 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
     // first LOBPCG vector: constant on I, normalized in the Z inner product
     const double v0 = 1.0 / sqrt(sm[0]);
     double *v = w.v + c.off;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double vi = interior(x[i]) ? v0 : 0.0;
         v[i] = vi;
         put_aux<OpT>(w, c.off + i, vi);
@@ -111,7 +128,7 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
 // Penalty update: alpha = eta * max(lambda, floor * rho), p_I += alpha z_I
 // (eqs. (pp1), (alpha1)); then the next subproblem starts from the same x.
 
-template <typename OpT>
+template <typename OpT, int EPT>
 __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, double lam) {
     const int64_t n = c.n;
     const double *x = w.x + c.off;
@@ -119,7 +136,7 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
     const double *b = w.b + in.off, *gam = w.gam + in.off, *R = w.R + in.off, *dq = w.dq + in.off;
     const double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
     double mx[2] = {0.0, 0.0};
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         double pi = p[i];
         if (interior(xi)) {
@@ -131,7 +148,7 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
         mx[1] = fmax(mx[1], fabs((b[i] - gam[i]) + pi));
         put_main<OpT>(w, c.off + i, xi);
     }
-    block_max<2>(mx, red);
+    bmax<2>(mx, red);
     if (threadIdx.x == 0) {
         c.rho = fmax(1.0, fmax(mx[0], mx[1]));
         c.lam = lam;
@@ -146,7 +163,7 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
 // ---------------------------------------------------------------------------
 // End of a subproblem (Algorithm 3 after line 6).
 
-template <typename OpT>
+template <typename OpT, int EPT>
 __device__ void end_subproblem(const Work &w, Col &c, const Inst &in, double *red, int ci,
                                bool moved, double rel) {
     if (threadIdx.x == 0) {
@@ -164,13 +181,13 @@ __device__ void end_subproblem(const Work &w, Col &c, const Inst &in, double *re
         c.s += 1;
     }
     __syncthreads();
-    outer_begin<OpT>(w, c, in, red);
+    outer_begin<OpT, EPT>(w, c, in, red);
 }
 
 // ---------------------------------------------------------------------------
 // Subproblem iteration (Algorithms 1 and 2).
 
-template <typename OpT, typename UT>
+template <typename OpT, typename UT, int EPT>
 __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, int ci) {
     const int64_t n = c.n;
     double *x = w.x + c.off, *xp = w.xp + c.off, *g = w.g + c.off, *gp = w.gp + c.off;
@@ -179,7 +196,7 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
     const int k = c.k;
     double mx[2] = {0.0, 0.0};       // cret, any nonzero step component
     double sm[3] = {0.0, 0.0, 0.0};  // s's, s'y, y'y
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         const double A = (dq[i] + gam[i]) - p[i];
         const double bbar = (b[i] - gam[i]) + p[i];
@@ -199,8 +216,8 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
             if (s != 0.0) mx[1] = 1.0;
         }
     }
-    block_max<2>(mx, red);
-    if (k > 0) block_sum<3>(sm, red);
+    bmax<2>(mx, red);
+    if (k > 0) bsum<3>(sm, red);
     const double rel = mx[0] / c.rho;
     if (threadIdx.x == 0) {
         c.evals += 1;
@@ -208,11 +225,11 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
     }
     __syncthreads();
     if (rel < w.tol_kkt) {
-        end_subproblem<OpT>(w, c, in, red, ci, k > 0, rel);
+        end_subproblem<OpT, EPT>(w, c, in, red, ci, k > 0, rel);
         return;
     }
     if (k > 0 && mx[1] == 0.0) {
-        end_subproblem<OpT>(w, c, in, red, ci, true, rel);
+        end_subproblem<OpT, EPT>(w, c, in, red, ci, true, rel);
         return;
     }
     double alpha = 0.0;
@@ -227,7 +244,7 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
             alpha = fmin(fmax(a, w.alpha_min), w.alpha_max);
         }
     }
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         const double gi = g[i];
         double xn;
@@ -244,7 +261,7 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
     }
     if (k + 1 >= w.max_inner) {
         __syncthreads();
-        end_subproblem<OpT>(w, c, in, red, ci, true, rel);
+        end_subproblem<OpT, EPT>(w, c, in, red, ci, true, rel);
         return;
     }
     if (threadIdx.x == 0) c.k = k + 1;
@@ -252,78 +269,163 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
 }
 
 // ---------------------------------------------------------------------------
-// Small dense helpers for the LOBPCG Rayleigh-Ritz step (m <= 3).
+// Rayleigh-Ritz for LOBPCG on span{v, w, P}, fully unrolled 3 x 3 code
+// (static indexing keeps every array in registers). Without P, the third
+// direction is decoupled: unit Gram diagonal, no coupling, and a Ritz value
+// far above the others, so it never becomes the minimum and its
+// coefficient is exactly zero.
 
-__device__ bool chol3(int m, const double (&G)[3][3], double (&L)[3][3]) {
+// Cholesky G = L L^T of a 3 x 3 matrix with unit diagonal; false when the
+// basis is numerically dependent.
+__device__ __forceinline__ bool chol3(const double (&G)[3][3], double (&L)[3][3]) {
+    bool ok = true;
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) L[i][j] = 0.0;
-    for (int j = 0; j < m; ++j) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
         double d = G[j][j];
+#pragma unroll
         for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
-        if (!(d > 1e-12)) return false;  // near-dependent basis (G has unit diagonal)
-        L[j][j] = sqrt(d);
-        for (int i = j + 1; i < m; ++i) {
-            double s = G[i][j];
-            for (int q = 0; q < j; ++q) s -= L[i][q] * L[j][q];
-            L[i][j] = s / L[j][j];
+        ok = ok && (d > 1e-12);
+        const double lj = sqrt(fmax(d, 1e-300));
+        L[j][j] = lj;
+#pragma unroll
+        for (int i = j + 1; i < 3; ++i) {
+            double t = G[i][j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) t -= L[i][q] * L[j][q];
+            L[i][j] = t / lj;
         }
     }
-    return true;
+    return ok;
 }
 
-// Cyclic Jacobi on a symmetric m x m matrix; returns the smallest eigenpair.
-__device__ void jacobi_min(int m, double (&C)[3][3], double &theta, double (&y)[3]) {
-    double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) {
-                tot += C[i][j] * C[i][j];
-                if (i != j) off += C[i][j] * C[i][j];
-            }
-        if (off <= 1e-32 * tot) break;
-        for (int pq = 0; pq < m; ++pq)
-            for (int qq = pq + 1; qq < m; ++qq) {
-                const double apq = C[pq][qq];
-                if (apq == 0.0) continue;
-                const double tau = (C[qq][qq] - C[pq][pq]) / (2.0 * apq);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-                for (int r = 0; r < m; ++r) {
-                    const double a = C[r][pq], bq = C[r][qq];
-                    C[r][pq] = cs * a - sn * bq;
-                    C[r][qq] = sn * a + cs * bq;
-                }
-                for (int r = 0; r < m; ++r) {
-                    const double a = C[pq][r], bq = C[qq][r];
-                    C[pq][r] = cs * a - sn * bq;
-                    C[qq][r] = sn * a + cs * bq;
-                }
-                for (int r = 0; r < m; ++r) {
-                    const double a = V[r][pq], bq = V[r][qq];
-                    V[r][pq] = cs * a - sn * bq;
-                    V[r][qq] = sn * a + cs * bq;
-                }
-            }
+// One Jacobi rotation annihilating C[p][q] (p < q) of a symmetric 3 x 3 C,
+// accumulated into V.
+template <int PP, int QQ>
+__device__ __forceinline__ void jacobi_rot(double (&C)[3][3], double (&V)[3][3]) {
+    const double apq = C[PP][QQ];
+    if (apq == 0.0) return;
+    const double tau = (C[QQ][QQ] - C[PP][PP]) / (2.0 * apq);
+    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double a = C[r][PP], b = C[r][QQ];
+        C[r][PP] = cs * a - sn * b;
+        C[r][QQ] = sn * a + cs * b;
     }
-    int best = 0;
-    for (int i = 1; i < m; ++i)
-        if (C[i][i] < C[best][best]) best = i;
-    theta = C[best][best];
-    for (int i = 0; i < 3; ++i) y[i] = i < m ? V[i][best] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double a = C[PP][r], b = C[QQ][r];
+        C[PP][r] = cs * a - sn * b;
+        C[QQ][r] = sn * a + cs * b;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double a = V[r][PP], b = V[r][QQ];
+        V[r][PP] = cs * a - sn * b;
+        V[r][QQ] = sn * a + cs * b;
+    }
+}
+
+// sm = {v'Zv, v'Zw, w'Zw, v'ZP, w'ZP, P'ZP, v'Av, v'Aw, w'Aw, v'AP, w'AP, P'AP};
+// out = {a_v, a_w, a_P, theta, ok}: the new v = a_v v + a_w w + a_P P.
+__device__ __forceinline__ void rayleigh_ritz(const double *sm, bool hasP, double *out) {
+    const double d0 = 1.0 / sqrt(sm[0]), d1 = 1.0 / sqrt(sm[2]);
+    const double d2 = hasP ? 1.0 / sqrt(sm[5]) : 1.0;
+    const double d[3] = {d0, d1, d2};
+    double G[3][3], H[3][3];
+    G[0][0] = sm[0] * d0 * d0; G[0][1] = sm[1] * d0 * d1; G[1][1] = sm[2] * d1 * d1;
+    H[0][0] = sm[6] * d0 * d0; H[0][1] = sm[7] * d0 * d1; H[1][1] = sm[8] * d1 * d1;
+    if (hasP) {
+        G[0][2] = sm[3] * d0 * d2; G[1][2] = sm[4] * d1 * d2; G[2][2] = sm[5] * d2 * d2;
+        H[0][2] = sm[9] * d0 * d2; H[1][2] = sm[10] * d1 * d2; H[2][2] = sm[11] * d2 * d2;
+    } else {
+        G[0][2] = 0.0; G[1][2] = 0.0; G[2][2] = 1.0;
+        H[0][2] = 0.0; H[1][2] = 0.0; H[2][2] = 0.0;  // replaced below
+    }
+    G[1][0] = G[0][1]; G[2][0] = G[0][2]; G[2][1] = G[1][2];
+    H[1][0] = H[0][1]; H[2][0] = H[0][2]; H[2][1] = H[1][2];
+    double L[3][3];
+    bool ok = chol3(G, L);
+    bool useP = hasP;
+    if (!ok && hasP) {  // drop P: decouple the third direction
+        useP = false;
+        G[0][2] = G[1][2] = G[2][0] = G[2][1] = 0.0;
+        G[2][2] = 1.0;
+        H[0][2] = H[1][2] = H[2][0] = H[2][1] = 0.0;
+        ok = chol3(G, L);
+    }
+    if (!ok || !(sm[2] > 0.0) || !isfinite(d1)) {
+        out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
+        return;
+    }
+    // L^-1 (lower triangular)
+    double Li[3][3];
+    Li[0][0] = 1.0 / L[0][0]; Li[1][1] = 1.0 / L[1][1]; Li[2][2] = 1.0 / L[2][2];
+    Li[0][1] = Li[0][2] = Li[1][2] = 0.0;
+    Li[1][0] = -L[1][0] * Li[0][0] / L[1][1];
+    Li[2][1] = -L[2][1] * Li[1][1] / L[2][2];
+    Li[2][0] = -(L[2][0] * Li[0][0] + L[2][1] * Li[1][0]) / L[2][2];
+    // C = L^-1 H L^-T
+    double T[3][3], C[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) T[i][j] = Li[i][0] * H[0][j] + Li[i][1] * H[1][j] + Li[i][2] * H[2][j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) C[i][j] = T[i][0] * Li[j][0] + T[i][1] * Li[j][1] + T[i][2] * Li[j][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            const double sym = 0.5 * (C[i][j] + C[j][i]);
+            C[i][j] = sym;
+            C[j][i] = sym;
+        }
+    if (!useP) {  // third Ritz value far above the others
+        const double big = 1e3 * (fabs(C[0][0]) + fabs(C[1][1]) + fabs(C[0][1]) + 1.0);
+        C[0][2] = C[1][2] = C[2][0] = C[2][1] = 0.0;
+        C[2][2] = big;
+    }
+    double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        const double off = C[0][1] * C[0][1] + C[0][2] * C[0][2] + C[1][2] * C[1][2];
+        const double dia = C[0][0] * C[0][0] + C[1][1] * C[1][1] + C[2][2] * C[2][2];
+        if (off <= 1e-32 * (dia + 2.0 * off)) break;
+        jacobi_rot<0, 1>(C, V);
+        jacobi_rot<0, 2>(C, V);
+        jacobi_rot<1, 2>(C, V);
+    }
+    // smallest eigenpair (lowest index on ties)
+    double theta = C[0][0];
+    double y0 = V[0][0], y1 = V[1][0], y2 = V[2][0];
+    if (C[1][1] < theta) { theta = C[1][1]; y0 = V[0][1]; y1 = V[1][1]; y2 = V[2][1]; }
+    if (C[2][2] < theta) { theta = C[2][2]; y0 = V[0][2]; y1 = V[1][2]; y2 = V[2][2]; }
+    // a = D L^-T y
+    out[0] = (Li[0][0] * y0 + Li[1][0] * y1 + Li[2][0] * y2) * d[0];
+    out[1] = (Li[1][1] * y1 + Li[2][1] * y2) * d[1];
+    out[2] = useP ? (Li[2][2] * y2) * d[2] : 0.0;
+    out[3] = theta;
+    out[4] = 1.0;
 }
 
 // ---------------------------------------------------------------------------
 // lambda_min: first LOBPCG vector applied.
 
-template <typename OpT, typename UT>
+template <typename OpT, typename UT, int EPT>
 __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
     const int64_t n = c.n;
     const double *x = w.x + c.off, *p = w.p + c.off;
     const double *gam = w.gam + in.off, *dq = w.dq + in.off;
     double *v = w.v + c.off, *Av = w.Av + c.off, *wv = w.w + c.off;
     double sm[2] = {0.0, 0.0};  // v'Av, v'Zv
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         double av = 0.0;
         if (interior(xi)) {
@@ -334,10 +436,10 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
         }
         Av[i] = av;
     }
-    block_sum<2>(sm, red);
+    bsum<2>(sm, red);
     const double lam = sm[0] / sm[1];
     double rn[1] = {0.0};
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         double wi = 0.0;
         if (interior(xi)) {
@@ -350,7 +452,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
         wv[i] = wi;
         put_aux<OpT>(w, c.off + i, wi);
     }
-    block_sum<1>(rn, red);
+    bsum<1>(rn, red);
     if (threadIdx.x == 0) {
         c.aux += 1;
         c.it = 1;
@@ -359,7 +461,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     __syncthreads();
     if (sqrt(rn[0] / sm[1]) <= w.eig_tol * fabs(lam) || w.eig_maxit <= 1) {
-        eig_finish<OpT>(w, c, in, red, lam);
+        eig_finish<OpT, EPT>(w, c, in, red, lam);
         return;
     }
     if (threadIdx.x == 0) c.phase = PH_EIG;
@@ -369,7 +471,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
 // ---------------------------------------------------------------------------
 // lambda_min: one LOBPCG iteration (Rayleigh-Ritz on span{v, w, P}).
 
-template <typename OpT, typename UT>
+template <typename OpT, typename UT, int EPT>
 __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     const int64_t n = c.n;
     const double *x = w.x + c.off, *p = w.p + c.off;
@@ -381,7 +483,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     double sm[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) sm[j] = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         double aw = 0.0;
         if (interior(xi)) {
@@ -407,70 +509,23 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         }
         Aw[i] = aw;
     }
-    block_sum<12>(sm, red);
-    // Rayleigh-Ritz, computed identically by every thread
-    int m = hasP ? 3 : 2;
-    double d[3] = {1.0 / sqrt(sm[0]), 1.0 / sqrt(sm[2]), hasP ? 1.0 / sqrt(sm[5]) : 0.0};
-    double G0[3][3] = {{sm[0], sm[1], sm[3]}, {sm[1], sm[2], sm[4]}, {sm[3], sm[4], sm[5]}};
-    double H0[3][3] = {{sm[6], sm[7], sm[9]}, {sm[7], sm[8], sm[10]}, {sm[9], sm[10], sm[11]}};
-    double G[3][3], H[3][3], L[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            G[i][j] = G0[i][j] * d[i] * d[j];
-            H[i][j] = H0[i][j] * d[i] * d[j];
-        }
-    bool ok = chol3(m, G, L);
-    if (!ok && m == 3) {
-        m = 2;
-        ok = chol3(m, G, L);
-    }
-    const bool w_ok = sm[2] > 0.0 && isfinite(d[1]);
-    if (!ok || !w_ok) {
+    bsum<12>(sm, red);
+    // Rayleigh-Ritz on thread 0; the coefficients go through shared memory
+    __shared__ double rr[5];  // a0, a1, a2, theta, ok
+    if (threadIdx.x == 0) rayleigh_ritz(sm, hasP, rr);
+    __syncthreads();
+    const bool ok = rr[4] != 0.0;
+    const double a[3] = {rr[0], rr[1], rr[2]};
+    const double theta = rr[3];
+    if (!ok) {
         // the residual direction is numerically inside span{v}: converged
         if (threadIdx.x == 0) c.aux += 1;
         __syncthreads();
-        eig_finish<OpT>(w, c, in, red, c.lam);
+        eig_finish<OpT, EPT>(w, c, in, red, c.lam);
         return;
     }
-    // C = L^-1 H L^-T
-    double Li[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int j = 0; j < m; ++j) {
-        Li[j][j] = 1.0 / L[j][j];
-        for (int i = j + 1; i < m; ++i) {
-            double s = 0.0;
-            for (int q = j; q < i; ++q) s -= L[i][q] * Li[q][j];
-            Li[i][j] = s / L[i][i];
-        }
-    }
-    double T[3][3], C[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
-            for (int q = 0; q < m; ++q) s += Li[i][q] * H[q][j];
-            T[i][j] = (i < m && j < m) ? s : 0.0;
-        }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
-            for (int q = 0; q < m; ++q) s += T[i][q] * Li[j][q];
-            C[i][j] = (i < m && j < m) ? s : 0.0;
-        }
-    for (int i = 0; i < m; ++i)
-        for (int j = i + 1; j < m; ++j) {
-            const double s = 0.5 * (C[i][j] + C[j][i]);
-            C[i][j] = s;
-            C[j][i] = s;
-        }
-    double theta, y[3];
-    jacobi_min(m, C, theta, y);
-    double a[3] = {0.0, 0.0, 0.0};  // a = D L^-T y
-    for (int i = 0; i < m; ++i) {
-        double s = 0.0;
-        for (int q = 0; q < m; ++q) s += Li[q][i] * y[q];
-        a[i] = s * d[i];
-    }
     double rn[2] = {0.0, 0.0};  // ||r||^2_{Z^-1}, v'Zv
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double xi = x[i];
         double wn = 0.0;
         if (interior(xi)) {
@@ -493,7 +548,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         wv[i] = wn;
         put_aux<OpT>(w, c.off + i, wn);
     }
-    block_sum<2>(rn, red);
+    bsum<2>(rn, red);
     const int it = c.it + 1;
     if (threadIdx.x == 0) {
         c.aux += 1;
@@ -503,29 +558,29 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     __syncthreads();
     if (sqrt(rn[0] / rn[1]) <= w.eig_tol * fabs(theta) || it >= w.eig_maxit) {
-        eig_finish<OpT>(w, c, in, red, theta);
+        eig_finish<OpT, EPT>(w, c, in, red, theta);
     }
 }
 
 // ---------------------------------------------------------------------------
 // x^0 by Jacobi-preconditioned CG on K = 2 (Q + Diag gamma).
 
-template <typename OpT, typename UT>
+template <typename OpT, typename UT, int EPT>
 __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
     const int64_t n = c.n;
     double *x = w.x + c.off;
     double *r = w.v + c.off, *d = w.w + c.off, *Kd = w.Av + c.off;
     const double *gam = w.gam + in.off, *dq = w.dq + in.off;
     double s1[1] = {0.0};
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double kd = 2.0 * (uaux<UT>(w, c.off + i) + (dq[i] + gam[i]) * d[i]);
         Kd[i] = kd;
         s1[0] += d[i] * kd;
     }
-    block_sum<1>(s1, red);
+    bsum<1>(s1, red);
     const double a = c.rz / s1[0];
     double s2[2] = {0.0, 0.0};  // r'M^-1 r, r'r
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         x[i] = x[i] + a * d[i];
         const double ri = r[i] - a * Kd[i];
         r[i] = ri;
@@ -533,7 +588,7 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
         s2[0] += ri * zz;
         s2[1] += ri * ri;
     }
-    block_sum<2>(s2, red);
+    bsum<2>(s2, red);
     const int it = c.it + 1;
     if (threadIdx.x == 0) {
         c.aux += 1;
@@ -541,11 +596,11 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     __syncthreads();
     if (sqrt(s2[1]) <= w.cg_tol * c.r0 || it >= w.cg_maxit) {
-        outer_begin<OpT>(w, c, in, red);
+        outer_begin<OpT, EPT>(w, c, in, red);
         return;
     }
     const double beta = s2[0] / c.rz;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    FOR_I(n) {
         const double zz = r[i] / (2.0 * (dq[i] + gam[i]));
         const double dn = zz + beta * d[i];
         d[i] = dn;
@@ -556,40 +611,117 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
 }
 
 // ---------------------------------------------------------------------------
+// Live-column lists for the next sweep, in column order. Split precision:
+// `active` gets the subproblem columns and `active_aux` the lambda_min / CG
+// columns; otherwise `active` gets every live column. Run by one block.
+
+template <int NT>
+__device__ void compact_lists(const Work &w) {
+    __shared__ int32_t cnt[2][NT];
+    const int ncol = w.ncol;
+    const int chunk = (ncol + NT - 1) / NT;
+    const int lo = threadIdx.x * chunk;
+    const int hi = min(ncol, lo + chunk);
+    int my0 = 0, my1 = 0;
+    for (int ci = lo; ci < hi; ++ci) {
+        const int ph = __atomic_load_n(&w.col[ci].phase, __ATOMIC_RELAXED);
+        if (ph == PH_DONE) continue;
+        if (w.split && ph != PH_INNER) ++my1;
+        else ++my0;
+    }
+    cnt[0][threadIdx.x] = my0;
+    cnt[1][threadIdx.x] = my1;
+    __syncthreads();
+    if (threadIdx.x < 64) {  // exclusive prefix sums by wave 0, NT / 64 entries per lane
+        constexpr int E = NT / 64;
+        const int lane = threadIdx.x;
+        int s0 = 0, s1 = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            s0 += cnt[0][lane * E + e];
+            s1 += cnt[1][lane * E + e];
+        }
+        int i0 = s0, i1 = s1;  // inclusive scan over lanes
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u0 = __shfl_up(i0, o, 64), u1 = __shfl_up(i1, o, 64);
+            if (lane >= o) {
+                i0 += u0;
+                i1 += u1;
+            }
+        }
+        int a0 = i0 - s0, a1 = i1 - s1;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int v0 = cnt[0][lane * E + e], v1 = cnt[1][lane * E + e];
+            cnt[0][lane * E + e] = a0;
+            cnt[1][lane * E + e] = a1;
+            a0 += v0;
+            a1 += v1;
+        }
+        if (lane == 63) {
+            *w.nactive = i0;
+            *w.nactive_aux = w.split ? i1 : 0;
+            if (w.sweeps) *w.sweeps += 1;
+        }
+    }
+    __syncthreads();
+    int p0 = cnt[0][threadIdx.x], p1 = cnt[1][threadIdx.x];
+    for (int ci = lo; ci < hi; ++ci) {
+        const int ph = __atomic_load_n(&w.col[ci].phase, __ATOMIC_RELAXED);
+        if (ph == PH_DONE) continue;
+        if (w.split && ph != PH_INNER) w.active_aux[p1++] = ci;
+        else w.active[p0++] = ci;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Kernels.
 
-template <typename OpT, typename UT>
-__global__ void __launch_bounds__(kBlock) solver_step_kernel(Work w) {
+template <typename OpT, typename UT, int EPT>
+__global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     const int ci = blockIdx.x;
-    if (ci >= w.ncol || w.col[ci].phase == PH_DONE) return;
     __shared__ Col c;
     __shared__ Inst in;
-    __shared__ double red[12 * kWaves];
+    __shared__ double red[12 * kSWaves];
+    __shared__ int last;
+    if (threadIdx.x == 0) c = w.col[ci];
+    __syncthreads();
+    if (c.phase != PH_DONE) {
+        if (threadIdx.x == 0) in = w.inst[c.inst];
+        __syncthreads();
+        switch (c.phase) {
+            case PH_INNER: inner_step<OpT, UT, EPT>(w, c, in, red, ci); break;
+            case PH_EIG0: eig0_step<OpT, UT, EPT>(w, c, in, red); break;
+            case PH_EIG: eig_step<OpT, UT, EPT>(w, c, in, red); break;
+            case PH_CG: cg_step<OpT, UT, EPT>(w, c, in, red); break;
+            default: break;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) w.col[ci] = c;
+    }
+    // the last block of the sweep rebuilds the live lists
     if (threadIdx.x == 0) {
-        c = w.col[ci];
-        in = w.inst[c.inst];
+        __threadfence();
+        const int done = atomicAdd(w.done_count, 1);
+        last = (done == w.ncol - 1);
     }
     __syncthreads();
-    switch (c.phase) {
-        case PH_INNER: inner_step<OpT, UT>(w, c, in, red, ci); break;
-        case PH_EIG0: eig0_step<OpT, UT>(w, c, in, red); break;
-        case PH_EIG: eig_step<OpT, UT>(w, c, in, red); break;
-        case PH_CG: cg_step<OpT, UT>(w, c, in, red); break;
-        default: break;
+    if (last) {
+        __threadfence();
+        compact_lists<kSB>(w);
+        if (threadIdx.x == 0) *w.done_count = 0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) w.col[ci] = c;
 }
 
 // Column set-up: x from X0 (column ci of an n x B matrix with leading
 // dimension n) and the first outer step, or the CG start x = 0, r = gamma - b.
-template <typename OpT>
-__global__ void __launch_bounds__(kBlock) solver_init_kernel(Work w, const double *X0, int use_cg) {
+template <typename OpT, int EPT>
+__global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *X0, int use_cg) {
     const int ci = blockIdx.x;
-    if (ci >= w.ncol) return;
     __shared__ Col c;
     __shared__ Inst in;
-    __shared__ double red[12 * kWaves];
+    __shared__ double red[12 * kSWaves];
     if (threadIdx.x == 0) {
         c = w.col[ci];
         in = w.inst[c.inst];
@@ -598,14 +730,14 @@ __global__ void __launch_bounds__(kBlock) solver_init_kernel(Work w, const doubl
     const int64_t n = c.n;
     double *x = w.x + c.off;
     if (!use_cg) {
-        for (int64_t i = threadIdx.x; i < n; i += kBlock) x[i] = X0[(int64_t)ci * n + i];
+        FOR_I(n) x[i] = X0[(int64_t)ci * n + i];
         __syncthreads();
-        outer_begin<OpT>(w, c, in, red);
+        outer_begin<OpT, EPT>(w, c, in, red);
     } else {
         const double *b = w.b + in.off, *gam = w.gam + in.off, *dq = w.dq + in.off;
         double *r = w.v + c.off, *d = w.w + c.off;
         double s[2] = {0.0, 0.0};
-        for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+        FOR_I(n) {
             x[i] = 0.0;
             const double ri = gam[i] - b[i];
             const double zz = ri / (2.0 * (dq[i] + gam[i]));
@@ -615,7 +747,7 @@ __global__ void __launch_bounds__(kBlock) solver_init_kernel(Work w, const doubl
             s[0] += ri * zz;
             s[1] += ri * ri;
         }
-        block_sum<2>(s, red);
+        bsum<2>(s, red);
         if (threadIdx.x == 0) {
             c.rz = s[0];
             c.r0 = sqrt(s[1]);
@@ -628,80 +760,45 @@ __global__ void __launch_bounds__(kBlock) solver_init_kernel(Work w, const doubl
     if (threadIdx.x == 0) w.col[ci] = c;
 }
 
-// Live-column lists for the next sweep, in column order; also counts sweeps.
-// Split precision: `active` gets the subproblem columns and `active_aux` the
-// lambda_min / CG columns; otherwise `active` gets every live column.
-__global__ void __launch_bounds__(kBlock) compact_kernel(Work w, int64_t *sweeps) {
-    __shared__ int32_t cnt[2][kBlock];
-    const int ncol = w.ncol;
-    const int chunk = (ncol + kBlock - 1) / kBlock;
-    const int lo = threadIdx.x * chunk;
-    const int hi = min(ncol, lo + chunk);
-    int my0 = 0, my1 = 0;
-    for (int ci = lo; ci < hi; ++ci) {
-        const int ph = w.col[ci].phase;
-        if (ph == PH_DONE) continue;
-        if (w.split && ph != PH_INNER) ++my1;
-        else ++my0;
-    }
-    cnt[0][threadIdx.x] = my0;
-    cnt[1][threadIdx.x] = my1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int a0 = 0, a1 = 0;
-        for (int t = 0; t < kBlock; ++t) {
-            const int v0 = cnt[0][t], v1 = cnt[1][t];
-            cnt[0][t] = a0;
-            cnt[1][t] = a1;
-            a0 += v0;
-            a1 += v1;
-        }
-        *w.nactive = a0;
-        if (w.split) *w.nactive_aux = a1;
-        if (sweeps) *sweeps += 1;
-    }
-    __syncthreads();
-    int p0 = cnt[0][threadIdx.x], p1 = cnt[1][threadIdx.x];
-    for (int ci = lo; ci < hi; ++ci) {
-        const int ph = w.col[ci].phase;
-        if (ph == PH_DONE) continue;
-        if (w.split && ph != PH_INNER) w.active_aux[p1++] = ci;
-        else w.active[p0++] = ci;
-    }
-}
+__global__ void __launch_bounds__(kSB) compact_kernel(Work w) { compact_lists<kSB>(w); }
 
-template <typename OpT, typename UT>
+template <typename OpT, typename UT, int EPT>
 static hipError_t step_launch(const Work &w, hipStream_t st) {
-    hipLaunchKernelGGL((solver_step_kernel<OpT, UT>), dim3(w.ncol), dim3(kBlock), 0, st, w);
+    hipLaunchKernelGGL((solver_step_kernel<OpT, UT, EPT>), dim3(w.ncol), dim3(kSB), 0, st, w);
     return hipGetLastError();
 }
 
-hipError_t launch_solver_step(int optype, int utype, const Work &w, hipStream_t st) {
-    if (optype == PSDP_F64 && utype == PSDP_F64) return step_launch<double, double>(w, st);
-    if (optype == PSDP_F32 && utype == PSDP_F32) return step_launch<float, float>(w, st);
-    if (optype == PSDP_BF16 && utype == PSDP_F32) return step_launch<__hip_bfloat16, float>(w, st);
+template <typename OpT, typename UT>
+static hipError_t step_ept(const Work &w, int64_t nmax, hipStream_t st) {
+    if (nmax <= 1 * kSB) return step_launch<OpT, UT, 1>(w, st);
+    if (nmax <= 2 * kSB) return step_launch<OpT, UT, 2>(w, st);
+    if (nmax <= 4 * kSB) return step_launch<OpT, UT, 4>(w, st);
+    if (nmax <= 6 * kSB) return step_launch<OpT, UT, 6>(w, st);
+    return step_launch<OpT, UT, 8>(w, st);
+}
+
+hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax, hipStream_t st) {
+    if (optype == PSDP_F64 && utype == PSDP_F64) return step_ept<double, double>(w, nmax, st);
+    if (optype == PSDP_F32 && utype == PSDP_F32) return step_ept<float, float>(w, nmax, st);
+    if (optype == PSDP_BF16 && utype == PSDP_F32) return step_ept<__hip_bfloat16, float>(w, nmax, st);
     return hipErrorInvalidValue;
+}
+
+template <typename OpT>
+static hipError_t init_launch(const Work &w, const double *X0, int use_cg, hipStream_t st) {
+    hipLaunchKernelGGL((solver_init_kernel<OpT, 4>), dim3(w.ncol), dim3(kSB), 0, st, w, X0, use_cg);
+    return hipGetLastError();
 }
 
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,
                               hipStream_t st) {
-    if (optype == PSDP_F64)
-        hipLaunchKernelGGL(solver_init_kernel<double>, dim3(w.ncol), dim3(kBlock), 0, st, w, X0, use_cg);
-    else if (optype == PSDP_F32)
-        hipLaunchKernelGGL(solver_init_kernel<float>, dim3(w.ncol), dim3(kBlock), 0, st, w, X0, use_cg);
-    else
-        hipLaunchKernelGGL(solver_init_kernel<__hip_bfloat16>, dim3(w.ncol), dim3(kBlock), 0, st, w,
-                           X0, use_cg);
-    return hipGetLastError();
+    if (optype == PSDP_F64) return init_launch<double>(w, X0, use_cg, st);
+    if (optype == PSDP_F32) return init_launch<float>(w, X0, use_cg, st);
+    return init_launch<__hip_bfloat16>(w, X0, use_cg, st);
 }
 
 hipError_t launch_compact(const Work &w, hipStream_t st) {
-    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kBlock), 0, st, w, (int64_t *)nullptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_compact_count(const Work &w, int64_t *sweeps, hipStream_t st) {
-    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kBlock), 0, st, w, sweeps);
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kSB), 0, st, w);
     return hipGetLastError();
 }
 
