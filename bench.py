@@ -97,18 +97,23 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    results = [step(True) for _ in range(args.steps)]
+    results = []
+    for k in range(args.steps):
+        results.append(step(False))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    print(f"bench: {args.steps} timed steps in {wall:.2f} s", file=sys.stderr, flush=True)
     evals = sum(sum(s["inner_iters"] for s in r.stats) for r in results)
     aux = sum(sum(s["aux_matvecs"] for s in r.stats) for r in results)
-    st0 = [r.stats[0] for r in results]
-    qx_s = sum(s["qx_seconds"] for s in st0)
-    qx_f = sum(s["qx_flops"] for s in st0)
-    qx_l = sum(s["qx_launches"] for s in st0)
-    aux_s = sum(s["aux_seconds"] for s in st0)
-    aux_f = sum(s["aux_flops"] for s in st0)
+    # one more step of the same workload with HIP events around every launch
+    # of the FP32 product (on the library's solve stream): its average launch
+    # duration and algorithmic flops give the roofline point
+    inst = step(True)
+    s0 = inst.stats[0]
+    qx_s, qx_f, qx_l = s0["qx_seconds"], s0["qx_flops"], s0["qx_launches"]
+    aux_s, aux_f = s0["aux_seconds"], s0["aux_flops"]
     achieved = qx_f / qx_s if qx_s > 0 else 0.0
     last = results[-1]
     objs = last.obj.cpu().numpy()
@@ -130,12 +135,14 @@ def main():
                    "n": n, "starts": B, "global_batch": B, "parallelism": "single gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                     "kernel": f"gemm_kernel<{'float' if args.qx == 'f32' else 'double'},16>",
+                     "kernel": "Q.X product of the subproblem columns (stream_kernel / gemm_kernel, "
+                               f"{'FP32' if args.qx == 'f32' else 'FP64'} MFMA)",
                      "launches": qx_l, "avg_launch_us": qx_s / max(qx_l, 1) * 1e6,
-                     "flops_per_launch": qx_f / max(qx_l, 1)},
+                     "flops_per_launch": qx_f / max(qx_l, 1),
+                     "instrumented_step_s": None},
         "solve": {"evals": evals // args.steps, "aux_matvecs": aux // args.steps,
                   "sweeps": int(last.stats[0]["sweeps"]),
-                  "qx_share_of_wall": qx_s / wall,
+                  "qx_share_of_step": qx_s / (wall / args.steps),
                   "aux_gemm_tflops": (aux_f / aux_s / 1e12) if aux_s > 0 else None,
                   "best_obj": int(objs.min()), "best_start": last.best,
                   "exit_reasons": {k: int((np.array([s["exit_reason"] for s in last.stats]) == v).sum())

@@ -36,6 +36,7 @@ class Params(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("poll_sweeps", ctypes.c_int32),
         ("gemm_variant", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
         ("tol_kkt", ctypes.c_double),
         ("tol_binary", ctypes.c_double),
         ("eta", ctypes.c_double),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -132,11 +133,31 @@ constexpr int kMaxSplit = 8;
 struct Solver {
     Arena ar;
     Work w{};
-    std::function<void(int, int)> repick;  // adapts split-K to the live counts
+    std::function<void(int, int)> repick;  // adapts the product kernels to the live counts
+    std::function<int64_t()> config_key;   // identifies the current product configuration
     int optype = PSDP_F64, utype = PSDP_F64;
     int64_t *sweeps = nullptr;
     int64_t nmax = 0;  // largest column length (selects the per-thread unroll)
 };
+
+// One default-priority stream per device for the solve work: the caller's
+// stream may be the null stream, which cannot be captured into a graph.
+// Created under the library lock and kept until the process ends.
+hipError_t solve_stream(hipStream_t *out) {
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    auto it = streams.find(dev);
+    if (it == streams.end()) {
+        hipStream_t s;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        it = streams.emplace(dev, s).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
 
 void fill_work_params(Work &w, const psdp_params &p) {
     w.inner = p.inner;
@@ -267,19 +288,53 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
     int64_t done_sweeps = 0;
     int batch = 0;
     bool finished = false;
+    // batches of poll_sweeps sweeps replayed as graphs, one per product
+    // configuration (the kernels' arguments are fixed inside a graph)
+    const bool graphs = prm.graph != 0 && !tm.on;
+    std::map<int64_t, hipGraphExec_t> execs;
+    struct ExecFree {
+        std::map<int64_t, hipGraphExec_t> *m;
+        ~ExecFree() {
+            for (auto &kv : *m) (void)hipGraphExecDestroy(kv.second);
+        }
+    } xf{&execs};
+    auto enqueue_sweeps = [&](int nb) -> hipError_t {
+        for (int q = 0; q < nb; ++q) {
+            hipError_t e;
+            if ((e = tm.begin(st)) != hipSuccess) return e;
+            if ((e = apply()) != hipSuccess) return e;
+            if ((e = tm.end(st)) != hipSuccess) return e;
+            if (w.split) {
+                if ((e = ta.begin(st)) != hipSuccess) return e;
+                if ((e = apply_aux()) != hipSuccess) return e;
+                if ((e = ta.end(st)) != hipSuccess) return e;
+            }
+            if ((e = launch_solver_step(S.optype, S.utype, w, S.nmax, st)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     while (!finished) {
         const int nb = (int)std::min<int64_t>(prm.poll_sweeps, cap - done_sweeps);
         if (nb <= 0) return fail(PSDP_E_DEVICE, "sweep bound exceeded");
-        for (int q = 0; q < nb; ++q) {
-            HIPCHK(tm.begin(st));
-            HIPCHK(apply());
-            HIPCHK(tm.end(st));
-            if (w.split) {
-                HIPCHK(ta.begin(st));
-                HIPCHK(apply_aux());
-                HIPCHK(ta.end(st));
+        if (graphs && nb == prm.poll_sweeps) {
+            const int64_t key = S.config_key ? S.config_key() : 0;
+            auto it = execs.find(key);
+            if (it == execs.end()) {
+                hipGraph_t g;
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                hipError_t ce = enqueue_sweeps(nb);
+                hipError_t ee = hipStreamEndCapture(st, &g);
+                if (ce != hipSuccess) return hipfail(ce, "graph capture");
+                if (ee != hipSuccess) return hipfail(ee, "hipStreamEndCapture");
+                hipGraphExec_t ex;
+                hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) return hipfail(ie, "hipGraphInstantiate");
+                it = execs.emplace(key, ex).first;
             }
-            HIPCHK(launch_solver_step(S.optype, S.utype, w, S.nmax, st));
+            HIPCHK(hipGraphLaunch(it->second, st));
+        } else {
+            HIPCHK(enqueue_sweeps(nb));
         }
         done_sweeps += nb;
         const int slot = batch & 1;
@@ -345,6 +400,7 @@ void psdp_params_default(psdp_params *p) {
     p->timing = 0;
     p->poll_sweeps = 16;
     p->gemm_variant = -1;
+    p->graph = 1;
     p->tol_kkt = 1e-5;
     p->tol_binary = 1e-5;
     p->eta = 0.999;
@@ -417,6 +473,9 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         if (!std::isfinite(v)) return fail(PSDP_E_NONFINITE, "p0 must be finite");
     if (B > 1 && prm.qx_dtype == PSDP_BF16)
         return fail(PSDP_E_UNSUPPORTED, "batched starts support F64 and F32 operands");
+    // the inputs are ready (the stream was synchronized above); the solve runs
+    // on the library's own stream and is synchronized before returning
+    HIPCHK(solve_stream(&st));
 
     Solver S;
     const bool batched = B > 1;
@@ -472,9 +531,9 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     // so it is an estimate; every kernel covers all B columns regardless):
     // up to 64 live columns the wave-streaming kernel (needs the FP32 copy of
     // Q), above that the LDS-tiled GEMM with enough split-K for ~512 tiles.
-    struct Pick { bool stream; int nt; int ks; };
+    struct Pick { bool stream; int nt; int ks; int est; };
     auto pick = [&](int ncols, int gemm_dtype) {
-        Pick pk{false, 4, 1};
+        Pick pk{false, 4, 1, std::min(B, ncols + 16)};
         if (!batched) return pk;
         if (prm.gemm_variant > 0) {
             pk.ks = std::min(kMaxSplit, prm.gemm_variant & 0xff);
@@ -525,6 +584,12 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         rs = run_sweeps(S, prm, tm, ta, st, [&]() { return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st); },
                         none);
     } else {
+        const bool merge = w.split && prm.timing == 0 && main_gemm == PSDP_F32 && aux_gemm == kGemmF32QF64;
+        S.config_key = [&]() {
+            return (int64_t)pm.stream | ((int64_t)pm.nt << 1) | ((int64_t)pm.ks << 4) | ((int64_t)pa.stream << 9) |
+                   ((int64_t)pa.nt << 10) | ((int64_t)pa.ks << 13) | ((int64_t)pm.est << 20) |
+                   ((int64_t)pa.est << 32);
+        };
         S.repick = [&](int cm, int ca) {
             pm = pick(cm, main_gemm);
             pa = pick(ca, aux_gemm);
@@ -534,15 +599,22 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         rs = run_sweeps(
             S, prm, tm, ta, st,
             [&]() {
+                // split precision with both lists on the streaming kernel: one
+                // launch for both products (kept apart when every launch is timed)
+                if (merge && pm.stream && pa.stream)
+                    return launch_stream2(Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit, pm.nt,
+                                          w.op_aux, w.U_aux, w.active_aux, w.nactive_aux, w.slice_aux,
+                                          w.ksplit_aux, pa.nt, pm.est, pa.est, st);
                 if (pm.stream)
-                    return launch_stream(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit, B,
-                                         pm.nt, st);
+                    return launch_stream(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit,
+                                         pm.est, pm.nt, st);
                 return launch_gemm(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit, B, st);
             },
             [&]() {
+                if (merge && pm.stream && pa.stream) return hipSuccess;
                 if (pa.stream)
                     return launch_stream(aux_gemm, Qaux, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
-                                         w.slice_aux, w.ksplit_aux, B, pa.nt, st);
+                                         w.slice_aux, w.ksplit_aux, pa.est, pa.nt, st);
                 return launch_gemm(aux_gemm, Qaux, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
                                    w.slice_aux, w.ksplit_aux, B, st);
             });
@@ -620,6 +692,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
             return s;
         }
     }
+    HIPCHK(solve_stream(&st));
     Solver S;
     S.optype = PSDP_F64;
     S.utype = PSDP_F64;

@@ -174,6 +174,47 @@ __device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
     __syncthreads();
 }
 
+// Max-reduction of mx and sum-reduction of sm in one shared-memory round
+// (same fixed orders as block_max / block_sum).
+template <int NM, int NS, int NT>
+__device__ __forceinline__ void block_maxsum(double (&mx)[NM], double (&sm)[NS], double *scratch) {
+    constexpr int kWaves = NT / 64;
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mx[j] = fmax(mx[j], __shfl_xor(mx[j], o, 64));
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sm[j] += __shfl_xor(sm[j], o, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j) scratch[j * kWaves + wv] = mx[j];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) scratch[(NM + j) * kWaves + wv] = sm[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+        double v = scratch[j * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) v = fmax(v, scratch[j * kWaves + q]);
+        mx[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        double v = scratch[(NM + j) * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) v += scratch[(NM + j) * kWaves + q];
+        sm[j] = v;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers implemented in the kernel translation units.
 
@@ -196,7 +237,11 @@ hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart,
                              int64_t total_rows, hipStream_t st);
 hipError_t launch_stream(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
                          const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
-                         int ncol_max, int nt, hipStream_t st);
+                         int ncol, int nt, hipStream_t st);
+hipError_t launch_stream2(const void *Qop, int64_t ld, const void *op1, void *U1, const int32_t *active1,
+                          const int32_t *nactive1, int64_t slice1, int ks1, int nt1, const void *op2,
+                          void *U2, const int32_t *active2, const int32_t *nactive2, int64_t slice2,
+                          int ks2, int nt2, int ncol1, int ncol2, hipStream_t st);
 hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
                        const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
                        int ncol_max, hipStream_t st);

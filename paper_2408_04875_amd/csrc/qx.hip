@@ -12,6 +12,8 @@
 //  gemm_*_kernel      one instance, many columns: MFMA tiles (FP32 16x16x4 or
 //                     FP64 16x16x4) staged through LDS, split over K into
 //                     separate output slices that the solver sums in order.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace psdp {
@@ -299,21 +301,32 @@ template <> struct Vec4<double> {
     }
 };
 
+template <typename T> struct StreamArgs {
+    const float *Q;
+    int64_t ld;
+    const T *X;
+    const int32_t *active;
+    const int32_t *nactive;
+    T *U;
+    int64_t slice, kchunk;
+    int MT, KS, NG;
+};
+
 template <typename T, int NT, int UNR>
-__global__ void __launch_bounds__(kBlock) stream_kernel(const float *Q, int64_t ld, const T *X,
-                                                        const int32_t *active,
-                                                        const int32_t *nactive, T *U,
-                                                        int64_t slice, int64_t kchunk, int MT, int KS,
-                                                        int NG) {
+__device__ __forceinline__ void stream_body(const StreamArgs<T> &sa, int gb) {
     typedef typename Mfma<T>::acc_t acc_t;
     __shared__ acc_t part[kWaves - 1][NT][64];
+    const float *Q = sa.Q;
+    const int64_t ld = sa.ld;
+    const T *X = sa.X;
+    const int32_t *active = sa.active;
+    T *U = sa.U;
+    const int64_t slice = sa.slice, kchunk = sa.kchunk;
+    const int MT = sa.MT, KS = sa.KS, NG = sa.NG;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int gb = blockIdx.x;
     if (gb >= MT * KS * NG) return;
-    const int mt = gb % MT, kz = (gb / MT) % KS, ng = gb / (MT * KS);
-    const int nact = *nactive;
-    const int c0 = ng * 16 * NT;
-    if (c0 >= nact) return;  // uniform over the block
+    const int mt = gb % MT, kz = (gb / MT) % KS, ng0 = gb / (MT * KS);
+    const int nact = *sa.nactive;
     const int m = lane & 15, g = lane >> 4;
     const int64_t m0 = (int64_t)mt * 16;
     // the block's K range, split into kWaves contiguous parts (multiples of 16)
@@ -324,102 +337,173 @@ __global__ void __launch_bounds__(kBlock) stream_kernel(const float *Q, int64_t 
     const int64_t kbeg = kb + 16 * min(nchunks, per * wv);
     const int64_t kend = kb + 16 * min(nchunks, per * (wv + 1));
     const float *qrow = Q + (m0 + m) * ld + 4 * g;
-    const T *xcol[NT];
-    bool ok[NT];
+    T *Us = U + (int64_t)kz * slice;
+    // column groups ng0, ng0 + NG, ...: the grid may be sized from an
+    // estimate of the live count; the loop covers the actual one
+    for (int c0 = ng0 * 16 * NT; c0 < nact; c0 += NG * 16 * NT) {  // uniform over the block
+        const T *xcol[NT];
+        bool ok[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int slot = c0 + 16 * t + m;
-        ok[t] = slot < nact;
-        xcol[t] = X + (ok[t] ? (int64_t)active[slot] : 0) * ld + 4 * g;
-    }
-    acc_t acc[NT];
+        for (int t = 0; t < NT; ++t) {
+            const int slot = c0 + 16 * t + m;
+            ok[t] = slot < nact;
+            xcol[t] = X + (ok[t] ? (int64_t)active[slot] : 0) * ld + 4 * g;
+        }
+        acc_t acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    int64_t k0 = kbeg;
-    for (; k0 + 16 * UNR <= kend; k0 += 16 * UNR) {
-        float a[UNR][4];
-        T b[UNR][NT][4];
+        for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+        int64_t k0 = kbeg;
+        for (; k0 + 16 * UNR <= kend; k0 += 16 * UNR) {
+            float a[UNR][4];
+            T b[UNR][NT][4];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            Vec4<float>::load(qrow + k0 + 16 * u, a[u]);
+            for (int u = 0; u < UNR; ++u) {
+                Vec4<float>::load(qrow + k0 + 16 * u, a[u]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (ok[t]) Vec4<T>::load(xcol[t] + k0 + 16 * u, b[u][t]);
+                    else b[u][t][0] = b[u][t][1] = b[u][t][2] = b[u][t][3] = (T)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::run((T)a[u][e], b[u][t][e], acc[t]);
+        }
+        for (; k0 < kend; k0 += 16) {
+            float a[4];
+            Vec4<float>::load(qrow + k0, a);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                if (ok[t]) Vec4<T>::load(xcol[t] + k0 + 16 * u, b[u][t]);
-                else b[u][t][0] = b[u][t][1] = b[u][t][2] = b[u][t][3] = (T)0;
+                T b[4] = {(T)0, (T)0, (T)0, (T)0};
+                if (ok[t]) Vec4<T>::load(xcol[t] + k0, b);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[t] = Mfma<T>::run((T)a[e], b[e], acc[t]);
             }
         }
+        // deterministic reduction of the four K parts: wave 0 adds waves 1..3 in order
+        __syncthreads();  // the previous group's partials have been read
+        if (wv > 0) {
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
+            for (int t = 0; t < NT; ++t) part[wv - 1][t][lane] = acc[t];
+        }
+        __syncthreads();
+        if (wv == 0) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int q = 0; q < kWaves - 1; ++q)
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::run((T)a[u][e], b[u][t][e], acc[t]);
-    }
-    for (; k0 < kend; k0 += 16) {
-        float a[4];
-        Vec4<float>::load(qrow + k0, a);
+                for (int t = 0; t < NT; ++t) {
+                    const acc_t o = part[q][t][lane];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            T b[4] = {(T)0, (T)0, (T)0, (T)0};
-            if (ok[t]) Vec4<T>::load(xcol[t] + k0, b);
+                    for (int r = 0; r < 4; ++r) acc[t][r] += o[r];
+                }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[t] = Mfma<T>::run((T)a[e], b[e], acc[t]);
+            for (int t = 0; t < NT; ++t) {
+                if (!ok[t]) continue;
+                const int64_t c = active[c0 + 16 * t + m];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Us[c * ld + m0 + Mfma<T>::row(lane, r)] = acc[t][r];
+            }
         }
     }
-    // deterministic reduction of the four K parts: wave 0 adds waves 1..3 in order
-    if (wv > 0) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) part[wv - 1][t][lane] = acc[t];
-    }
-    __syncthreads();
-    if (wv != 0) return;
-#pragma unroll
-    for (int q = 0; q < kWaves - 1; ++q)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const acc_t o = part[q][t][lane];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[t][r] += o[r];
-        }
-    T *Us = U + (int64_t)kz * slice;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        if (!ok[t]) continue;
-        const int64_t c = active[c0 + 16 * t + m];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Us[c * ld + m0 + Mfma<T>::row(lane, r)] = acc[t][r];
-    }
+}
+
+template <typename T, int NT, int UNR>
+__global__ void __launch_bounds__(kBlock) stream_kernel(StreamArgs<T> sa) {
+    stream_body<T, NT, UNR>(sa, blockIdx.x);
+}
+
+// Both products of a split-precision sweep in one launch: the first nb1
+// blocks compute the FP32 product of the subproblem columns, the rest the
+// FP64 product (exactly widened FP32 Q) of the lambda_min / CG columns.
+template <int NT1, int UNR1, int NT2, int UNR2>
+__global__ void __launch_bounds__(kBlock) stream2_kernel(StreamArgs<float> a, StreamArgs<double> b,
+                                                         int nb1) {
+    if ((int)blockIdx.x < nb1) stream_body<float, NT1, UNR1>(a, blockIdx.x);
+    else stream_body<double, NT2, UNR2>(b, blockIdx.x - nb1);
 }
 
 // Wave-streaming product from an FP32 copy of Q: dtype PSDP_F32 (FP32 MFMA)
 // or kGemmF32QF64 (FP64 MFMA on the exactly widened entries). nt (1, 2 or 4)
-// is the number of 16-column tiles per block; the grid covers ncol_max
-// columns whatever nt is, so nt only trades MFMA work against Q re-reads.
-template <typename T, int NT, int UNR>
-static void stream_go(const void *Qop, int64_t ld, const void *op, void *U, const int32_t *active,
-                      const int32_t *nactive, int64_t slice, int ksplit, int ncol_max, hipStream_t st) {
+// is the number of 16-column tiles per block; the grid is sized for ncol
+// columns (an estimate) and blocks loop over further groups, so neither nt
+// nor ncol affects the result, only the speed.
+// ncol is the number of columns the grid is sized for (an estimate of the
+// live count is enough: blocks loop over further column groups).
+template <typename T>
+static StreamArgs<T> stream_args(const void *Qop, int64_t ld, const void *op, void *U,
+                                 const int32_t *active, const int32_t *nactive, int64_t slice,
+                                 int ksplit, int ncol, int nt) {
     int64_t kchunk = (ld + ksplit - 1) / ksplit;
     kchunk = (kchunk + 15) / 16 * 16;
-    const int MT = (int)(ld / 16), NG = (ncol_max + 16 * NT - 1) / (16 * NT);
-    const dim3 grid((unsigned)(MT * ksplit * NG));
-    hipLaunchKernelGGL((stream_kernel<T, NT, UNR>), grid, dim3(kBlock), 0, st, (const float *)Qop, ld,
-                       (const T *)op, active, nactive, (T *)U, slice, kchunk, MT, ksplit, NG);
+    StreamArgs<T> a;
+    a.Q = (const float *)Qop;
+    a.ld = ld;
+    a.X = (const T *)op;
+    a.active = active;
+    a.nactive = nactive;
+    a.U = (T *)U;
+    a.slice = slice;
+    a.kchunk = kchunk;
+    a.MT = (int)(ld / 16);
+    a.KS = ksplit;
+    a.NG = std::max(1, (ncol + 16 * nt - 1) / (16 * nt));
+    return a;
+}
+
+template <typename T, int NT, int UNR>
+static void stream_go(const StreamArgs<T> &a, hipStream_t st) {
+    hipLaunchKernelGGL((stream_kernel<T, NT, UNR>), dim3((unsigned)(a.MT * a.KS * a.NG)), dim3(kBlock), 0, st, a);
 }
 
 hipError_t launch_stream(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
                          const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
                          int ncol_max, int nt, hipStream_t st) {
     if (dtype == PSDP_F32) {
-        if (nt <= 1) stream_go<float, 1, 8>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
-        else if (nt == 2) stream_go<float, 2, 8>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
-        else stream_go<float, 4, 4>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+        auto a = stream_args<float>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, nt <= 1 ? 1 : (nt == 2 ? 2 : 4));
+        if (nt <= 1) stream_go<float, 1, 8>(a, st);
+        else if (nt == 2) stream_go<float, 2, 8>(a, st);
+        else stream_go<float, 4, 4>(a, st);
     } else if (dtype == kGemmF32QF64) {
-        if (nt <= 1) stream_go<double, 1, 8>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
-        else if (nt == 2) stream_go<double, 2, 4>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
-        else stream_go<double, 4, 2>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, st);
+        auto a = stream_args<double>(Qop, ld, op, U, active, nactive, slice, ksplit, ncol_max, nt <= 1 ? 1 : (nt == 2 ? 2 : 4));
+        if (nt <= 1) stream_go<double, 1, 8>(a, st);
+        else if (nt == 2) stream_go<double, 2, 4>(a, st);
+        else stream_go<double, 4, 2>(a, st);
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <int NT1, int UNR1, int NT2, int UNR2>
+static void stream2_go(const StreamArgs<float> &a, const StreamArgs<double> &b, hipStream_t st) {
+    const int nb1 = a.MT * a.KS * a.NG, nb2 = b.MT * b.KS * b.NG;
+    hipLaunchKernelGGL((stream2_kernel<NT1, UNR1, NT2, UNR2>), dim3((unsigned)(nb1 + nb2)), dim3(kBlock), 0, st,
+                       a, b, nb1);
+}
+
+template <int NT1, int UNR1>
+static void stream2_second(const StreamArgs<float> &a, const StreamArgs<double> &b, int nt2, hipStream_t st) {
+    if (nt2 <= 1) stream2_go<NT1, UNR1, 1, 8>(a, b, st);
+    else if (nt2 == 2) stream2_go<NT1, UNR1, 2, 4>(a, b, st);
+    else stream2_go<NT1, UNR1, 4, 2>(a, b, st);
+}
+
+// FP32 product (subproblem columns) and FP64 product (lambda_min / CG
+// columns) of one sweep, both from the FP32 copy of Q, in one launch.
+hipError_t launch_stream2(const void *Qop, int64_t ld, const void *op1, void *U1, const int32_t *active1,
+                          const int32_t *nactive1, int64_t slice1, int ks1, int nt1, const void *op2,
+                          void *U2, const int32_t *active2, const int32_t *nactive2, int64_t slice2,
+                          int ks2, int nt2, int ncol1, int ncol2, hipStream_t st) {
+    nt1 = nt1 <= 1 ? 1 : (nt1 == 2 ? 2 : 4);
+    nt2 = nt2 <= 1 ? 1 : (nt2 == 2 ? 2 : 4);
+    auto a = stream_args<float>(Qop, ld, op1, U1, active1, nactive1, slice1, ks1, ncol1, nt1);
+    auto b = stream_args<double>(Qop, ld, op2, U2, active2, nactive2, slice2, ks2, ncol2, nt2);
+    if (nt1 == 1) stream2_second<1, 8>(a, b, nt2, st);
+    else if (nt1 == 2) stream2_second<2, 8>(a, b, nt2, st);
+    else stream2_second<4, 4>(a, b, nt2, st);
     return hipGetLastError();
 }
 

@@ -92,8 +92,7 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
         mx[2] = fmax(mx[2], 2.0 * (R[i] + fabs(A)));
         mx[3] = fmax(mx[3], fabs((b[i] - gam[i]) + p[i]));
     }
-    bmax<4>(mx, red);
-    bsum<2>(sm, red);
+    block_maxsum<4, 2, kSB>(mx, sm, red);
     const double rho = fmax(1.0, fmax(mx[2], mx[3]));
     int32_t exitr = -1;
     if (mx[0] <= w.tol_binary) exitr = PSDP_EXIT_CONVERGED;
@@ -216,8 +215,7 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
             if (s != 0.0) mx[1] = 1.0;
         }
     }
-    bmax<2>(mx, red);
-    if (k > 0) bsum<3>(sm, red);
+    block_maxsum<2, 3, kSB>(mx, sm, red);  // sm is zero when k == 0
     const double rel = mx[0] / c.rho;
     if (threadIdx.x == 0) {
         c.evals += 1;

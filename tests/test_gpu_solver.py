@@ -143,3 +143,25 @@ def test_group_equals_single_instance_path_and_oracle(P):
         print(f"  inst {i} {d['kind']} n={d['n']}: gpu {got[i]} oracle {ref.obj}", flush=True)
     print(f"group: {match}/{len(insts)} oracle objectives", flush=True)
     assert match >= 5
+
+
+@pytest.mark.parametrize("B,qdt", [(1, "f64"), (24, "f32"), (24, "f64")])
+def test_graph_replay_matches_eager_launches(P, B, qdt):
+    """Sweeps replayed from captured graphs give bit-identical results."""
+    Q, b = gen.dense_int(64, 3)
+    X0 = _t(gen.random_box_points(64, B, 11))
+    eager = P.solve(_t(Q), _t(b), X0=X0, qx_dtype=qdt, graph=0, poll_sweeps=4)
+    for _ in range(2):
+        g = P.solve(_t(Q), _t(b), X0=X0, qx_dtype=qdt, graph=1, poll_sweeps=4)
+        assert np.array_equal(g.obj.cpu().numpy(), eager.obj.cpu().numpy())
+        assert np.array_equal(g.X.cpu().numpy(), eager.X.cpu().numpy())
+        assert [s["inner_iters"] for s in g.stats] == [s["inner_iters"] for s in eager.stats]
+
+
+def test_run_to_run_bit_identity(P):
+    """Fixed-order reductions: the same batched solve twice gives the same bits."""
+    Q, b, X0 = gen.sparse_2500_starts(n=600, B=16)
+    a = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="f32")
+    c = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="f32")
+    assert np.array_equal(a.X.cpu().numpy(), c.X.cpu().numpy())
+    assert np.array_equal(a.obj.cpu().numpy(), c.obj.cpu().numpy())
