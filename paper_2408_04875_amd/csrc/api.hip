@@ -576,6 +576,12 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(launch_solver_init(S.optype, w, X0, X0 ? 0 : 1, st));
     HIPCHK(launch_compact(w, st));
 
+    // optional per-phase timing of the column kernel (diagnostics, env PSDP_PHASE_PROFILE=1)
+    const bool phase_prof = getenv("PSDP_PHASE_PROFILE") != nullptr;
+    if (phase_prof) {
+        HIPCHK(S.ar.get((void **)&w.phase_prof, 16 * sizeof(unsigned long long)));
+        HIPCHK(hipMemsetAsync(w.phase_prof, 0, 16 * sizeof(unsigned long long), st));
+    }
     QxTimer tm, ta;
     tm.on = ta.on = prm.timing != 0;
     auto none = []() { return hipSuccess; };
@@ -620,6 +626,17 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
             });
     }
     if (rs != PSDP_OK) return rs;
+    if (phase_prof) {
+        unsigned long long hp[16];
+        HIPCHK(hipMemcpy(hp, w.phase_prof, sizeof hp, hipMemcpyDeviceToHost));
+        int rate_khz = 100000;
+        (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, 0);
+        const char *nm[5] = {"done", "cg", "eig0", "eig", "inner"};
+        for (int q = 1; q < 5; ++q)
+            if (hp[3 * q + 1])
+                fprintf(stderr, "phase %-5s n=%llu avg %.2f us max %.2f us\n", nm[q], hp[3 * q + 1],
+                        1e3 * (double)hp[3 * q] / hp[3 * q + 1] / rate_khz, 1e3 * (double)hp[3 * q + 2] / rate_khz);
+    }
     // rounding and exact objective on the original data
     int64_t *partial;
     const int64_t nblk = (n + 15) / 16;

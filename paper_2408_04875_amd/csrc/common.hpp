@@ -91,6 +91,7 @@ struct Work {
     int32_t *nactive_aux;
     int32_t *done_count;  // blocks finished in the current sweep (last one compacts)
     int64_t *sweeps;      // sweep counter (nullable)
+    unsigned long long *phase_prof;  // optional per-phase {sum, count, max} of step ticks
     double *trace;       // per column trace_cap records of 6 doubles, or null
     int32_t trace_cap;
     // parameters

@@ -186,7 +186,7 @@ __device__ void end_subproblem(const Work &w, Col &c, const Inst &in, double *re
 // ---------------------------------------------------------------------------
 // Subproblem iteration (Algorithms 1 and 2).
 
-template <typename OpT, typename UT, int EPT>
+template <typename OpT, typename UT, int EPT, bool CACHE>
 __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, int ci) {
     const int64_t n = c.n;
     double *x = w.x + c.off, *xp = w.xp + c.off, *g = w.g + c.off, *gp = w.gp + c.off;
@@ -195,12 +195,18 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
     const int k = c.k;
     double mx[2] = {0.0, 0.0};       // cret, any nonzero step component
     double sm[3] = {0.0, 0.0, 0.0};  // s's, s'y, y'y
+    double xr[EPT], gr[EPT];         // register copies when one pass covers the column
     FOR_I(n) {
         const double xi = x[i];
         const double A = (dq[i] + gam[i]) - p[i];
         const double bbar = (b[i] - gam[i]) + p[i];
         const double gi = 2.0 * (uval<UT>(w, c.off + i) + A * xi) + bbar;
-        g[i] = gi;
+        if (CACHE) {
+            xr[_j] = xi;
+            gr[_j] = gi;
+        } else {
+            g[i] = gi;
+        }
         double viol;
         if (interior(xi)) viol = fabs(gi);
         else if (xi == 0.0) viol = fmax(-gi, 0.0);
@@ -243,8 +249,8 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
         }
     }
     FOR_I(n) {
-        const double xi = x[i];
-        const double gi = g[i];
+        const double xi = CACHE ? xr[_j] : x[i];
+        const double gi = CACHE ? gr[_j] : g[i];
         double xn;
         if (w.inner == PSDP_INNER_PABB) {
             xn = fmin(fmax(xi - alpha * gi, 0.0), 1.0);
@@ -273,41 +279,30 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
 // far above the others, so it never becomes the minimum and its
 // coefficient is exactly zero.
 
-// Cholesky G = L L^T of a 3 x 3 matrix with unit diagonal; false when the
-// basis is numerically dependent.
+// Cholesky G = L L^T of a 3 x 3 matrix with unit diagonal (L00 = 1); false
+// when the basis is numerically dependent.
 __device__ __forceinline__ bool chol3(const double (&G)[3][3], double (&L)[3][3]) {
-    bool ok = true;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) L[i][j] = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        double d = G[j][j];
-#pragma unroll
-        for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
-        ok = ok && (d > 1e-12);
-        const double lj = sqrt(fmax(d, 1e-300));
-        L[j][j] = lj;
-#pragma unroll
-        for (int i = j + 1; i < 3; ++i) {
-            double t = G[i][j];
-#pragma unroll
-            for (int q = 0; q < j; ++q) t -= L[i][q] * L[j][q];
-            L[i][j] = t / lj;
-        }
-    }
-    return ok;
+    const double l10 = G[1][0], l20 = G[2][0];
+    const double d1 = 1.0 - l10 * l10;
+    const double l11 = sqrt(fmax(d1, 1e-300));
+    const double l21 = (G[2][1] - l20 * l10) / l11;
+    const double d2 = 1.0 - l20 * l20 - l21 * l21;
+    const double l22 = sqrt(fmax(d2, 1e-300));
+    L[0][0] = 1.0; L[0][1] = 0.0; L[0][2] = 0.0;
+    L[1][0] = l10; L[1][1] = l11; L[1][2] = 0.0;
+    L[2][0] = l20; L[2][1] = l21; L[2][2] = l22;
+    return d1 > 1e-12 && d2 > 1e-12;
 }
 
 // One Jacobi rotation annihilating C[p][q] (p < q) of a symmetric 3 x 3 C,
-// accumulated into V.
+// accumulated into V: t = tan of the angle from the stable quadratic root,
+// c = 1/sqrt(1 + t^2), s = t c.
 template <int PP, int QQ>
 __device__ __forceinline__ void jacobi_rot(double (&C)[3][3], double (&V)[3][3]) {
     const double apq = C[PP][QQ];
     if (apq == 0.0) return;
-    const double tau = (C[QQ][QQ] - C[PP][PP]) / (2.0 * apq);
-    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    const double diff = C[QQ][QQ] - C[PP][PP];
+    const double t = (diff >= 0.0 ? 2.0 * apq : -2.0 * apq) / (fabs(diff) + sqrt(diff * diff + 4.0 * apq * apq));
     const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -361,13 +356,14 @@ __device__ __forceinline__ void rayleigh_ritz(const double *sm, bool hasP, doubl
         out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
         return;
     }
-    // L^-1 (lower triangular)
+    // L^-1 (lower triangular, unit first diagonal entry)
     double Li[3][3];
-    Li[0][0] = 1.0 / L[0][0]; Li[1][1] = 1.0 / L[1][1]; Li[2][2] = 1.0 / L[2][2];
+    const double i11 = 1.0 / L[1][1], i22 = 1.0 / L[2][2];
+    Li[0][0] = 1.0; Li[1][1] = i11; Li[2][2] = i22;
     Li[0][1] = Li[0][2] = Li[1][2] = 0.0;
-    Li[1][0] = -L[1][0] * Li[0][0] / L[1][1];
-    Li[2][1] = -L[2][1] * Li[1][1] / L[2][2];
-    Li[2][0] = -(L[2][0] * Li[0][0] + L[2][1] * Li[1][0]) / L[2][2];
+    Li[1][0] = -L[1][0] * i11;
+    Li[2][1] = -L[2][1] * i11 * i22;
+    Li[2][0] = -(L[2][0] + L[2][1] * Li[1][0]) * i22;
     // C = L^-1 H L^-T
     double T[3][3], C[3][3];
 #pragma unroll
@@ -469,7 +465,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
 // ---------------------------------------------------------------------------
 // lambda_min: one LOBPCG iteration (Rayleigh-Ritz on span{v, w, P}).
 
-template <typename OpT, typename UT, int EPT>
+template <typename OpT, typename UT, int EPT, bool CACHE>
 __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     const int64_t n = c.n;
     const double *x = w.x + c.off, *p = w.p + c.off;
@@ -481,14 +477,27 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     double sm[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) sm[j] = 0.0;
+    // register copies when one pass covers the column (z = 0 marks i outside I)
+    double zr[EPT], Ar[EPT], vr[EPT], wr[EPT], awr[EPT], avr[EPT], pr[EPT], apr[EPT];
     FOR_I(n) {
         const double xi = x[i];
         double aw = 0.0;
+        if (CACHE) zr[_j] = 0.0;
         if (interior(xi)) {
             const double z = xi - xi * xi;
             const double A = (dq[i] + gam[i]) - p[i];
             const double wi = wv[i], vi = v[i];
             aw = uaux<UT>(w, c.off + i) + A * wi;
+            if (CACHE) {
+                zr[_j] = z;
+                Ar[_j] = A;
+                vr[_j] = vi;
+                wr[_j] = wi;
+                awr[_j] = aw;
+                avr[_j] = Av[i];
+                pr[_j] = hasP ? P[i] : 0.0;
+                apr[_j] = hasP ? AP[i] : 0.0;
+            }
             sm[0] += z * vi * vi;
             sm[1] += z * vi * wi;
             sm[2] += z * wi * wi;
@@ -505,7 +514,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
                 sm[11] += pi * AP[i];
             }
         }
-        Aw[i] = aw;
+        if (!CACHE) Aw[i] = aw;
     }
     bsum<12>(sm, red);
     // Rayleigh-Ritz on thread 0; the coefficients go through shared memory
@@ -524,16 +533,27 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     double rn[2] = {0.0, 0.0};  // ||r||^2_{Z^-1}, v'Zv
     FOR_I(n) {
-        const double xi = x[i];
+        double z, A, vi, wi, awi, avi, pi, api;
+        bool in_I;
+        if (CACHE) {
+            z = zr[_j];
+            in_I = z > 0.0;  // for 0 < x < 1, x - x*x rounds to a positive double
+            A = Ar[_j]; vi = vr[_j]; wi = wr[_j]; awi = awr[_j]; avi = avr[_j]; pi = pr[_j]; api = apr[_j];
+        } else {
+            const double xi = x[i];
+            in_I = interior(xi);
+            z = xi - xi * xi;
+            A = (dq[i] + gam[i]) - p[i];
+            vi = v[i]; wi = wv[i]; awi = Aw[i]; avi = Av[i];
+            pi = hasP ? P[i] : 0.0;
+            api = hasP ? AP[i] : 0.0;
+        }
         double wn = 0.0;
-        if (interior(xi)) {
-            const double z = xi - xi * xi;
-            const double A = (dq[i] + gam[i]) - p[i];
-            const double pi = hasP ? P[i] : 0.0, api = hasP ? AP[i] : 0.0;
-            const double vn = a[0] * v[i] + a[1] * wv[i] + a[2] * pi;
-            const double avn = a[0] * Av[i] + a[1] * Aw[i] + a[2] * api;
-            const double pn = a[1] * wv[i] + a[2] * pi;
-            const double apn = a[1] * Aw[i] + a[2] * api;
+        if (in_I) {
+            const double vn = a[0] * vi + a[1] * wi + a[2] * pi;
+            const double avn = a[0] * avi + a[1] * awi + a[2] * api;
+            const double pn = a[1] * wi + a[2] * pi;
+            const double apn = a[1] * awi + a[2] * api;
             v[i] = vn;
             Av[i] = avn;
             P[i] = pn;
@@ -676,7 +696,7 @@ __device__ void compact_lists(const Work &w) {
 // ---------------------------------------------------------------------------
 // Kernels.
 
-template <typename OpT, typename UT, int EPT>
+template <typename OpT, typename UT, int EPT, bool CI, bool CE>
 __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     const int ci = blockIdx.x;
     __shared__ Col c;
@@ -688,15 +708,25 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     if (c.phase != PH_DONE) {
         if (threadIdx.x == 0) in = w.inst[c.inst];
         __syncthreads();
+        const int ph0 = c.phase;
+        const unsigned long long t0 = w.phase_prof ? wall_clock64() : 0ull;
         switch (c.phase) {
-            case PH_INNER: inner_step<OpT, UT, EPT>(w, c, in, red, ci); break;
+            case PH_INNER: inner_step<OpT, UT, EPT, CI>(w, c, in, red, ci); break;
             case PH_EIG0: eig0_step<OpT, UT, EPT>(w, c, in, red); break;
-            case PH_EIG: eig_step<OpT, UT, EPT>(w, c, in, red); break;
+            case PH_EIG: eig_step<OpT, UT, EPT, CE>(w, c, in, red); break;
             case PH_CG: cg_step<OpT, UT, EPT>(w, c, in, red); break;
             default: break;
         }
         __syncthreads();
-        if (threadIdx.x == 0) w.col[ci] = c;
+        if (threadIdx.x == 0) {
+            w.col[ci] = c;
+            if (w.phase_prof) {
+                const unsigned long long dt = wall_clock64() - t0;
+                atomicAdd(&w.phase_prof[3 * ph0], dt);
+                atomicAdd(&w.phase_prof[3 * ph0 + 1], 1ull);
+                atomicMax(&w.phase_prof[3 * ph0 + 2], dt);
+            }
+        }
     }
     // the last block of the sweep rebuilds the live lists
     if (threadIdx.x == 0) {
@@ -760,19 +790,24 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
 
 __global__ void __launch_bounds__(kSB) compact_kernel(Work w) { compact_lists<kSB>(w); }
 
-template <typename OpT, typename UT, int EPT>
+template <typename OpT, typename UT, int EPT, bool CI, bool CE>
 static hipError_t step_launch(const Work &w, hipStream_t st) {
-    hipLaunchKernelGGL((solver_step_kernel<OpT, UT, EPT>), dim3(w.ncol), dim3(kSB), 0, st, w);
+    hipLaunchKernelGGL((solver_step_kernel<OpT, UT, EPT, CI, CE>), dim3(w.ncol), dim3(kSB), 0, st, w);
     return hipGetLastError();
 }
 
+// EPT elements per thread. When EPT * kSB covers the longest column the
+// subproblem step keeps x and g in registers between its two passes, and for
+// short columns the LOBPCG step keeps its eight vectors there too (beyond
+// two elements per thread they would not fit in the register file).
 template <typename OpT, typename UT>
 static hipError_t step_ept(const Work &w, int64_t nmax, hipStream_t st) {
-    if (nmax <= 1 * kSB) return step_launch<OpT, UT, 1>(w, st);
-    if (nmax <= 2 * kSB) return step_launch<OpT, UT, 2>(w, st);
-    if (nmax <= 4 * kSB) return step_launch<OpT, UT, 4>(w, st);
-    if (nmax <= 6 * kSB) return step_launch<OpT, UT, 6>(w, st);
-    return step_launch<OpT, UT, 8>(w, st);
+    if (nmax <= 1 * kSB) return step_launch<OpT, UT, 1, true, true>(w, st);
+    if (nmax <= 2 * kSB) return step_launch<OpT, UT, 2, true, true>(w, st);
+    if (nmax <= 4 * kSB) return step_launch<OpT, UT, 4, true, false>(w, st);
+    if (nmax <= 6 * kSB) return step_launch<OpT, UT, 6, true, false>(w, st);
+    if (nmax <= 8 * kSB) return step_launch<OpT, UT, 8, true, false>(w, st);
+    return step_launch<OpT, UT, 8, false, false>(w, st);
 }
 
 hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax, hipStream_t st) {
