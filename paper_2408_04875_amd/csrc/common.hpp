@@ -121,78 +121,59 @@ template <> __device__ __forceinline__ __hip_bfloat16 from_f64<__hip_bfloat16>(d
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic block reductions over kBlock threads: a fixed butterfly inside
-// each wave, then the wave partials combined in wave order. Every thread gets
-// the result. `scratch` must hold N * kWaves doubles of shared memory.
+// Deterministic block reductions over NT threads. Inside a wave the values
+// move with DPP row shifts and row broadcasts (plain VALU moves, no LDS
+// traffic) in a fixed pattern that leaves the wave's total in lane 63:
+// each row of 16 lanes forms prefix sums over shifts of 1, 2, 4 and 8, then
+// lane 15 of rows 0 and 2 joins rows 1 and 3, and lane 31 joins row 3. The
+// wave totals are then combined in wave order through shared memory, so
+// every thread gets the same value. `scratch` must hold N * NT / 64 doubles
+// of shared memory and is free again when the call returns. The max
+// reductions take 0 as identity: their inputs must be non-negative.
 
-template <int N, int NT = kBlock>
-__device__ __forceinline__ void block_sum(double (&v)[N], double *scratch) {
-    constexpr int kWaves = NT / 64;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v[j] += __shfl_xor(v[j], o, 64);
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) scratch[j * kWaves + wv] = v[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        double s = scratch[j * kWaves];
-#pragma unroll
-        for (int q = 1; q < kWaves; ++q) s += scratch[j * kWaves + q];
-        v[j] = s;
-    }
-    __syncthreads();
+// A double moved across lanes by DPP control CTRL on the rows in ROWMASK;
+// lanes whose source lies outside the row, or whose row is masked off, get 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-template <int N, int NT = kBlock>
-__device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
-    constexpr int kWaves = NT / 64;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v[j] = fmax(v[j], __shfl_xor(v[j], o, 64));
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) scratch[j * kWaves + wv] = v[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        double s = scratch[j * kWaves];
-#pragma unroll
-        for (int q = 1; q < kWaves; ++q) s = fmax(s, scratch[j * kWaves + q]);
-        v[j] = s;
-    }
-    __syncthreads();
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+__device__ __forceinline__ double wave_sum_to_63(double v) {
+    v += dpp_f64<kDppRowShr1, 0xf>(v);
+    v += dpp_f64<kDppRowShr2, 0xf>(v);
+    v += dpp_f64<kDppRowShr4, 0xf>(v);
+    v += dpp_f64<kDppRowShr8, 0xf>(v);
+    v += dpp_f64<kDppRowBcast15, 0xa>(v);
+    v += dpp_f64<kDppRowBcast31, 0xc>(v);
+    return v;
 }
 
-// Max-reduction of mx and sum-reduction of sm in one shared-memory round
-// (same fixed orders as block_max / block_sum).
+__device__ __forceinline__ double wave_max_to_63(double v) {
+    v = fmax(v, dpp_f64<kDppRowShr1, 0xf>(v));
+    v = fmax(v, dpp_f64<kDppRowShr2, 0xf>(v));
+    v = fmax(v, dpp_f64<kDppRowShr4, 0xf>(v));
+    v = fmax(v, dpp_f64<kDppRowShr8, 0xf>(v));
+    v = fmax(v, dpp_f64<kDppRowBcast15, 0xa>(v));
+    v = fmax(v, dpp_f64<kDppRowBcast31, 0xc>(v));
+    return v;
+}
+
+// Max-reduction of mx and sum-reduction of sm in one shared-memory round.
 template <int NM, int NS, int NT>
 __device__ __forceinline__ void block_maxsum(double (&mx)[NM], double (&sm)[NS], double *scratch) {
     constexpr int kWaves = NT / 64;
 #pragma unroll
-    for (int j = 0; j < NM; ++j) {
+    for (int j = 0; j < NM; ++j) mx[j] = wave_max_to_63(mx[j]);
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) mx[j] = fmax(mx[j], __shfl_xor(mx[j], o, 64));
-    }
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) sm[j] += __shfl_xor(sm[j], o, 64);
-    }
+    for (int j = 0; j < NS; ++j) sm[j] = wave_sum_to_63(sm[j]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int j = 0; j < NM; ++j) scratch[j * kWaves + wv] = mx[j];
 #pragma unroll
@@ -212,6 +193,48 @@ __device__ __forceinline__ void block_maxsum(double (&mx)[NM], double (&sm)[NS],
 #pragma unroll
         for (int q = 1; q < kWaves; ++q) v += scratch[(NM + j) * kWaves + q];
         sm[j] = v;
+    }
+    __syncthreads();
+}
+
+template <int N, int NT = kBlock>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *scratch) {
+    constexpr int kWaves = NT / 64;
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = wave_sum_to_63(v[j]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 63) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) scratch[j * kWaves + wv] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = scratch[j * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) s += scratch[j * kWaves + q];
+        v[j] = s;
+    }
+    __syncthreads();
+}
+
+template <int N, int NT = kBlock>
+__device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
+    constexpr int kWaves = NT / 64;
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = wave_max_to_63(v[j]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 63) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) scratch[j * kWaves + wv] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = scratch[j * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) s = fmax(s, scratch[j * kWaves + q]);
+        v[j] = s;
     }
     __syncthreads();
 }
