@@ -61,8 +61,19 @@ typedef enum { PSDP_INNER_PABB = 0, PSDP_INNER_PPA = 1 } psdp_inner;
 /* Storage/arithmetic type of the Q.X product operands. F64 runs FP64 MFMA /
  * FP64 FMA; F32 runs FP32 MFMA with FP32 accumulation (batched) or FP32
  * storage with FP64 accumulation (single instance); BF16 stores Q in bfloat16
- * and accumulates in FP32/FP64. All other solver state is FP64. */
-typedef enum { PSDP_F64 = 0, PSDP_F32 = 1, PSDP_BF16 = 2 } psdp_dtype;
+ * and accumulates in FP32/FP64. All other solver state is FP64.
+ *
+ * I8 (solver operands only) makes every product exact integer arithmetic:
+ * Q off the diagonal is stored as int8 (so |Q_ij| <= 127 for i != j is
+ * required, and FULL perturbation is not available), and the vector operand
+ * is split into signed base-128 digits that int8 MFMA multiplies with int32
+ * accumulation; the digit products combine in int64. A subproblem iterate
+ * x in [0,1]^n is first rounded to the grid 2^-27 (4 digits) and its product
+ * is exactly Q_off x_q; a lambda_min or CG vector v is scaled by the power of
+ * two 2^e > max|v| and rounded to the grid 2^(e-55) (8 digits), and its
+ * product is Q_off v_q rounded once to FP64. psdp_qx_digits exposes this
+ * product on its own. */
+typedef enum { PSDP_F64 = 0, PSDP_F32 = 1, PSDP_BF16 = 2, PSDP_I8 = 3 } psdp_dtype;
 
 /* Random symmetric perturbation of Q before the reformation (Section 3.5,
  * "Random Perturbation"): none, every entry (i <= j, mirrored), or the
@@ -145,6 +156,8 @@ int32_t psdp_version(void);
  *         all starts together (MFMA Q.X per sweep). With B > 1 and F32
  *         operands the subproblem products run on FP32 MFMA while the
  *         lambda_min and x^0 products keep FP64 operands (FP64 MFMA).
+ *         With I8 operands every B (including 1) runs the exact integer
+ *         digit products described at psdp_dtype.
  * prm     host, parameters (psdp_params_default then edit; NULL = defaults).
  * xhat    device, uint8, n x B: rounded solutions, x_i = 1 iff x_i > 1/2.
  * obj     device, int64, length B: f(xhat) on the original Q and b, exact.
@@ -154,8 +167,9 @@ int32_t psdp_version(void);
  * Errors: PSDP_E_INVALID (n < 1, B < 1, null required pointer, bad params),
  *         PSDP_E_NOT_SYMMETRIC, PSDP_E_NONFINITE (X0 outside [0,1]),
  *         PSDP_E_OVERFLOW (n^2 max|Q| + n max|b| >= 2^62),
- *         PSDP_E_UNSUPPORTED (FULL perturbation with BF16 operands),
- *         PSDP_E_DEVICE / PSDP_E_NOMEM.
+ *         PSDP_E_UNSUPPORTED (FULL perturbation with BF16 operands; I8
+ *         operands with |Q_ij| > 127 off the diagonal or a FULL
+ *         perturbation; BF16 with B > 1), PSDP_E_DEVICE / PSDP_E_NOMEM.
  * Validation reads Q, b and X0 back to the host once.
  */
 psdp_status psdp_solve_i32(const int32_t *Q, const int32_t *b, int64_t n,
@@ -256,6 +270,33 @@ psdp_status psdp_round_objective_i32(const int32_t *Q, const int32_t *b, int64_t
  */
 psdp_status psdp_perturbation(int64_t n, double sigma, uint64_t seed, int32_t mode,
                               double *mu, hipStream_t stream);
+
+/*
+ * psdp_qx_digits - the exact integer Q.X product of the I8 solver path
+ * (the O(n^2) part of every gradient evaluation, eq. (kkt1), and of every
+ * lambda_min and x^0 matvec, eqs. (alpha) and (gamma)) on given vectors:
+ * Y[:, c] = Q_off X_q[:, c], Q_off = Q with a zero diagonal.
+ *
+ * digits 4: entries of X must lie in [0,1]; X_q = rint(X 2^27) 2^-27 (ties
+ *           to even) and Y is exact.
+ * digits 8: for each column, e_c is the least integer with
+ *           max_i |X_ic| < 2^e_c (e_c = 0 for a zero column);
+ *           X_q = rint(X 2^(55 - e_c)) 2^(e_c - 55) and Y is X_q's exact
+ *           product rounded once to double (ties to even).
+ * Q       device, int32, n x n row-major, |Q_ij| <= 127 for i != j (the
+ *         diagonal is ignored; symmetry is not checked, the product uses row
+ *         i of Q for Y_ic).
+ * X       device, double, n x B column-major (leading dimension n).
+ * Y       device, double, n x B column-major (leading dimension n), output.
+ * The call allocates its own device workspace, reads Q back to the host once
+ * for the range check, and synchronizes `stream` before returning.
+ * Errors: PSDP_E_INVALID (n < 1 or n > 65536, B < 1, digits not 4 or 8, null
+ *         pointer), PSDP_E_NONFINITE (non-finite X, or digits 4 with X
+ *         outside [0,1]), PSDP_E_UNSUPPORTED (|Q_ij| > 127 off the diagonal),
+ *         PSDP_E_DEVICE / PSDP_E_NOMEM.
+ */
+psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t B,
+                           int32_t digits, double *Y, hipStream_t stream);
 
 /* Releases the cached device workspace of every device (optional). */
 void psdp_release(void);

@@ -4,7 +4,7 @@ The public functions forward to libpsdp.so through ``binding``; they raise if
 the library is not built. Nothing here computes on the CPU.
 """
 from .binding import (  # noqa: F401
-    F32, F64, BF16, PABB, PPA, EXIT_NAMES, PSDPError, Params, Stats,
+    F32, F64, BF16, I8, PABB, PPA, EXIT_NAMES, PSDPError, Params, Stats,
     default_params, eval_penalty_grad, load, penalty_adjoint, penalty_fn,
-    perturbation, round_objective, solve, solve_group,
+    perturbation, qx_digits, round_objective, solve, solve_group,
 )

@@ -16,7 +16,7 @@ from typing import List, Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpsdp.so")
 
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, I8 = 0, 1, 2, 3
 PABB, PPA = 0, 1
 PERTURB = {"none": 0, "full": 1, "diag": 2}
 EXIT_NAMES = {0: "converged", 1: "outer_cap", 2: "stall"}
@@ -89,6 +89,7 @@ SIGNATURES = {
     "psdp_penalty_adjoint": (_I32, [_I32, _I32, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P]),
     "psdp_round_objective_i32": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
     "psdp_perturbation": (_I32, [_I64, _D, _U64, _I32, _P, _P]),
+    "psdp_qx_digits": (_I32, [_P, _I64, _P, _I32, _I32, _P, _P]),
     "psdp_release": (None, []),
 }
 
@@ -126,7 +127,7 @@ def _check(status: int):
 def default_params(**overrides) -> Params:
     """psdp_params_default() then keyword overrides (names as in psdp.h).
 
-    inner may be "pabb"/"ppa", qx_dtype "f64"/"f32"/"bf16", perturb
+    inner may be "pabb"/"ppa", qx_dtype "f64"/"f32"/"bf16"/"i8", perturb
     "none"/"full"/"diag".
     """
     p = Params()
@@ -138,7 +139,7 @@ def default_params(**overrides) -> Params:
         if k == "inner" and isinstance(v, str):
             v = {"pabb": PABB, "ppa": PPA}[v]
         if k == "qx_dtype" and isinstance(v, str):
-            v = {"f64": F64, "f32": F32, "bf16": BF16}[v]
+            v = {"f64": F64, "f32": F32, "bf16": BF16, "i8": I8}[v]
         if k == "perturb" and isinstance(v, str):
             v = PERTURB[v]
         setattr(p, k, v)
@@ -314,6 +315,23 @@ def round_objective(Q, b, X):
     obj = torch.empty(B, dtype=torch.int64, device=X.device)
     _check(lib.psdp_round_objective_i32(_ptr(Q), _ptr(b), n, _ptr(X2), B, _ptr(xhat), _ptr(obj), _stream()))
     return xhat, obj
+
+
+def qx_digits(Q, X, digits: int = 4):
+    """Exact integer product of the I8 path: rows of X (shape (B, n) float64)
+    times Q with a zero diagonal, returned as (B, n) float64. digits=4 needs
+    X in [0,1] (grid 2^-27, exact result); digits=8 scales each row by a
+    power of two (grid 2^(e-55), result rounded once)."""
+    torch = _torch()
+    lib = load()
+    _dev(Q, torch.int32, "Q")
+    _dev(X, torch.float64, "X")
+    n = Q.shape[0]
+    X2 = X.reshape(-1, n)
+    B = X2.shape[0]
+    Y = torch.empty((B, n), dtype=torch.float64, device=X.device)
+    _check(lib.psdp_qx_digits(_ptr(Q), n, _ptr(X2), B, int(digits), _ptr(Y), _stream()))
+    return Y
 
 
 def perturbation(n: int, sigma: float, seed: int, mode: str = "full", device="cuda"):

@@ -56,11 +56,11 @@ struct Arena {
     }
 };
 
-size_t esize(int dtype) { return dtype == PSDP_F64 ? 8 : dtype == PSDP_F32 ? 4 : 2; }
+size_t esize(int dtype) { return dtype == PSDP_F64 ? 8 : dtype == PSDP_F32 ? 4 : dtype == PSDP_I8 ? 1 : 2; }
 
 psdp_status check_params(const psdp_params &p) {
     if (p.inner != PSDP_INNER_PABB && p.inner != PSDP_INNER_PPA) return fail(PSDP_E_INVALID, "params.inner");
-    if (p.qx_dtype < PSDP_F64 || p.qx_dtype > PSDP_BF16) return fail(PSDP_E_INVALID, "params.qx_dtype");
+    if (p.qx_dtype < PSDP_F64 || p.qx_dtype > PSDP_I8) return fail(PSDP_E_INVALID, "params.qx_dtype");
     if (p.perturb < PSDP_PERTURB_NONE || p.perturb > PSDP_PERTURB_DIAG)
         return fail(PSDP_E_INVALID, "params.perturb");
     if (p.max_inner < 1 || p.max_outer < 0 || p.stall_outer < 1 || p.eig_maxit < 1 || p.cg_maxit < 1 ||
@@ -102,6 +102,10 @@ psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int3
         return fail(PSDP_E_UNSUPPORTED, "bfloat16 operands need |Q_ij| <= 256 off the diagonal");
     if (p.qx_dtype == PSDP_F32 && offmax > (1 << 24))
         return fail(PSDP_E_UNSUPPORTED, "float operands need |Q_ij| <= 2^24 off the diagonal");
+    if (p.qx_dtype == PSDP_I8 && offmax > 127)
+        return fail(PSDP_E_UNSUPPORTED, "int8 operands need |Q_ij| <= 127 off the diagonal");
+    if (p.qx_dtype == PSDP_I8 && p.perturb == PSDP_PERTURB_FULL && p.sigma > 0.0)
+        return fail(PSDP_E_UNSUPPORTED, "FULL perturbation is not integer (int8 operands)");
     if (offmax_out) *offmax_out = offmax;
     return PSDP_OK;
 }
@@ -178,19 +182,33 @@ void fill_work_params(Work &w, const psdp_params &p) {
 }
 
 // Allocates the per-column vectors for `total` doubles of column storage.
-psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit) {
+psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, int64_t ld = 0) {
     Work &w = S.w;
     double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w};
     for (double **v : vecs) {
         HIPCHK(S.ar.get((void **)v, total * sizeof(double)));
         HIPCHK(hipMemset(*v, 0, total * sizeof(double)));
     }
-    HIPCHK(S.ar.get(&w.op, total * esize(S.optype)));
-    HIPCHK(hipMemset(w.op, 0, total * esize(S.optype)));
+    // integer path: int64 product slices; the operands are digit planes
+    const size_t oe = w.i8 ? 0 : esize(S.optype), ue = w.i8 ? sizeof(int64_t) : esize(S.utype);
+    if (oe) {
+        HIPCHK(S.ar.get(&w.op, total * oe));
+        HIPCHK(hipMemset(w.op, 0, total * oe));
+    }
     w.ksplit = 1;
     w.slice = total;
-    HIPCHK(S.ar.get(&w.U, ksplit * total * esize(S.utype)));
-    HIPCHK(hipMemset(w.U, 0, ksplit * total * esize(S.utype)));
+    HIPCHK(S.ar.get(&w.U, ksplit * total * ue));
+    HIPCHK(hipMemset(w.U, 0, ksplit * total * ue));
+    if (w.i8) {
+        // one extra all-zero column stands in for the unused rows of a digit tile
+        const int64_t pl = (int64_t)(ncol + 1) * ld;
+        HIPCHK(S.ar.get((void **)&w.dig, 4 * pl));
+        HIPCHK(hipMemset(w.dig, 0, 4 * pl));
+        HIPCHK(S.ar.get((void **)&w.dig_aux, 8 * pl));
+        HIPCHK(hipMemset(w.dig_aux, 0, 8 * pl));
+        HIPCHK(S.ar.get((void **)&w.U_lo, ksplit * total * sizeof(int64_t)));
+        HIPCHK(hipMemset(w.U_lo, 0, ksplit * total * sizeof(int64_t)));
+    }
     HIPCHK(S.ar.get((void **)&w.active, (ncol + 1) * sizeof(int32_t)));
     HIPCHK(S.ar.get((void **)&w.nactive, 64));
     HIPCHK(hipMemset(w.nactive, 0, 64));
@@ -478,8 +496,9 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(solve_stream(&st));
 
     Solver S;
-    const bool batched = B > 1;
-    const int64_t ld = padld(n);
+    const bool i8 = prm.qx_dtype == PSDP_I8;  // exact integer products, any B
+    const bool batched = B > 1 || i8;
+    const int64_t ld = i8 ? (n + 63) / 64 * 64 : padld(n);
     S.optype = batched ? prm.qx_dtype : PSDP_F64;  // single instance: FP64 x, Q in qx_dtype
     S.utype = batched ? prm.qx_dtype : PSDP_F64;
     Work &w = S.w;
@@ -487,6 +506,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     fill_work_params(w, prm);
     // batched lower-precision products: lambda_min and CG keep FP64 operands
     w.split = (batched && prm.qx_dtype != PSDP_F64) ? 1 : 0;
+    w.i8 = i8 ? 1 : 0;
     // Q~ off the diagonal is exact in FP32 for integers up to 2^24 unless a
     // FULL perturbation adds 2^-16-grid values to entries of 2^8 or more
     const bool q32_exact = offmax <= (1 << 24) &&
@@ -494,14 +514,23 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
                             (double)offmax + 3.5 * prm.sigma < 256.0);
     // Qop: operand of the main product; Qaux: operand of the FP64 products
     // (the exact FP32 copy widened in the kernel, or an FP64 copy)
-    const int qtype = batched ? ((prm.qx_dtype == PSDP_F32 || q32_exact) ? PSDP_F32 : PSDP_F64) : prm.qx_dtype;
+    const int qtype = i8 ? PSDP_I8
+                         : batched ? ((prm.qx_dtype == PSDP_F32 || q32_exact) ? PSDP_F32 : PSDP_F64) : prm.qx_dtype;
     int main_gemm = PSDP_F64, aux_gemm = PSDP_F64;
     if (batched) {
         main_gemm = prm.qx_dtype == PSDP_F32 ? PSDP_F32 : (q32_exact ? kGemmF32QF64 : PSDP_F64);
         aux_gemm = q32_exact ? kGemmF32QF64 : PSDP_F64;
     }
     void *Qop = nullptr;
-    HIPCHK(S.ar.get(&Qop, ld * ld * esize(qtype)));
+    if (i8) {
+        // int8 rows up to a multiple of kDigitRowsAlign: the digit kernel's row
+        // blocks may run past ld into these zero rows
+        const int64_t rows = (ld + kDigitRowsAlign - 1) / kDigitRowsAlign * kDigitRowsAlign;
+        HIPCHK(S.ar.get(&Qop, rows * ld));
+        HIPCHK(hipMemsetAsync(Qop, 0, rows * ld, st));
+    } else {
+        HIPCHK(S.ar.get(&Qop, ld * ld * esize(qtype)));
+    }
     double *bd, *gam, *R, *dq;
     HIPCHK(S.ar.get((void **)&bd, ld * 8));
     HIPCHK(S.ar.get((void **)&gam, ld * 8));
@@ -509,7 +538,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(S.ar.get((void **)&dq, ld * 8));
     HIPCHK(launch_prep_q(qtype, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qop, R, dq, st));
     void *Qaux = Qop;
-    if (w.split && aux_gemm == PSDP_F64) {
+    if (w.split && !i8 && aux_gemm == PSDP_F64) {
         HIPCHK(S.ar.get(&Qaux, ld * ld * sizeof(double)));
         HIPCHK(launch_prep_q(PSDP_F64, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qaux, R, dq, st));
     }
@@ -525,7 +554,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
     // column data
     const int kmax = batched ? kMaxSplit : 1;
-    if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax)) return s2;
+    if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, ld)) return s2;
     const int MT = (int)((ld + 63) / 64);
     // Product kernel per live count (the count comes from the last host poll,
     // so it is an estimate; every kernel covers all B columns regardless):
@@ -551,9 +580,23 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         pk.ks = std::max(1, std::min(kMaxSplit, (512 + tiles - 1) / tiles));
         return pk;
     };
+    // integer path: digit tiles per wave from the estimated live count, and
+    // enough K slices for about 640 blocks
+    struct Pick8 { int mt; int ks; int est; };
+    const int IB8 = (int)((ld + 127) / 128);
+    auto pick8 = [&](int ncols, int D) {
+        Pick8 pk;
+        pk.est = std::min(B, ncols + 16);
+        const int rows = pk.est * D;
+        pk.mt = rows <= 16 ? 1 : (rows <= 32 ? 2 : 4);
+        const int ag = (pk.est + 16 * pk.mt / D - 1) / (16 * pk.mt / D);
+        pk.ks = std::max(1, std::min(kMaxSplit, (640 + ag * IB8 - 1) / (ag * IB8)));
+        return pk;
+    };
+    Pick8 p8m = pick8(B, 4), p8a = pick8(B, 8);
     Pick pm = pick(B, main_gemm), pa = pick(B, aux_gemm);
-    w.ksplit = pm.ks;
-    w.ksplit_aux = w.split ? pa.ks : w.ksplit;
+    w.ksplit = i8 ? p8m.ks : pm.ks;
+    w.ksplit_aux = i8 ? p8a.ks : (w.split ? pa.ks : w.ksplit);
     std::vector<Col> hcol(B);
     for (int c = 0; c < B; ++c) {
         Col &cc = hcol[c];
@@ -562,6 +605,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         cc.n = n;
         cc.ld = ld;
         cc.off = (int64_t)c * ld;
+        cc.id = c;
         cc.phase = PH_INNER;  // placeholder, set by the init kernel
     }
     HIPCHK(S.ar.get((void **)&w.col, B * sizeof(Col)));
@@ -586,7 +630,39 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     tm.on = ta.on = prm.timing != 0;
     auto none = []() { return hipSuccess; };
     psdp_status rs;
-    if (!batched) {
+    if (i8) {
+        auto job_main = [&]() {
+            return DigitJob{w.dig, w.active, w.nactive, (int64_t *)w.U, nullptr, w.slice, B,
+                            p8m.ks, p8m.mt, p8m.est};
+        };
+        auto job_aux = [&]() {
+            return DigitJob{w.dig_aux, w.active_aux, w.nactive_aux, (int64_t *)w.U_aux, w.U_lo, w.slice_aux, B,
+                            p8a.ks, p8a.mt, p8a.est};
+        };
+        const int8_t *Q8 = (const int8_t *)Qop;
+        S.config_key = [&]() {
+            return (int64_t)p8m.mt | ((int64_t)p8m.ks << 3) | ((int64_t)p8a.mt << 7) | ((int64_t)p8a.ks << 10) |
+                   ((int64_t)p8m.est << 14) | ((int64_t)p8a.est << 34);
+        };
+        S.repick = [&](int cm, int ca) {
+            p8m = pick8(cm, 4);
+            p8a = pick8(ca, 8);
+            w.ksplit = p8m.ks;
+            w.ksplit_aux = p8a.ks;
+        };
+        // both products in one launch, or apart when every launch is timed
+        rs = run_sweeps(
+            S, prm, tm, ta, st,
+            [&]() {
+                const DigitJob jm = job_main(), ja = job_aux();
+                return launch_digit(Q8, ld, n, ld, &jm, tm.on ? nullptr : &ja, st);
+            },
+            [&]() {
+                if (!tm.on) return hipSuccess;
+                const DigitJob ja = job_aux();
+                return launch_digit(Q8, ld, n, ld, nullptr, &ja, st);
+            });
+    } else if (!batched) {
         rs = run_sweeps(S, prm, tm, ta, st, [&]() { return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st); },
                         none);
     } else {
@@ -695,6 +771,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     }
     if (psdp_status s = check_params(prm)) return s;
     if (count < 1 || !n || !Q || !b || !xhat || !obj) return fail(PSDP_E_INVALID, "null or empty group");
+    if (prm.qx_dtype == PSDP_I8) return fail(PSDP_E_UNSUPPORTED, "the group solve takes F64, F32 or BF16 operands");
     for (int i = 0; i < count; ++i) {
         if (n[i] < 1 || n[i] > 65536) return fail(PSDP_E_INVALID, "instance size out of range");
         if (!Q[i] || !b[i] || !xhat[i]) return fail(PSDP_E_INVALID, "null instance pointer");
@@ -755,6 +832,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         cc.n = n[i];
         cc.ld = ld[i];
         cc.off = off[i];
+        cc.id = i;
         cc.phase = PH_INNER;
     }
     HIPCHK(S.ar.get((void **)&w.col, count * sizeof(Col)));
@@ -848,6 +926,62 @@ psdp_status psdp_perturbation(int64_t n, double sigma, uint64_t seed, int32_t mo
     if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(PSDP_E_INVALID, "sigma");
     hipError_t e = launch_perturbation(n, sigma, seed, mode, mu, st);
     if (e != hipSuccess) return hipfail(e, "perturbation");
+    return PSDP_OK;
+}
+
+psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits, double *Y,
+                           hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    if (!Q || !X || !Y) return fail(PSDP_E_INVALID, "null pointer");
+    if (n < 1 || n > 65536 || B < 1) return fail(PSDP_E_INVALID, "n must be in [1, 65536] and B >= 1");
+    if (digits != 4 && digits != 8) return fail(PSDP_E_INVALID, "digits must be 4 or 8");
+    std::vector<int32_t> hQ(n * n);
+    std::vector<double> hX(n * B);
+    HIPCHK(hipMemcpyAsync(hQ.data(), Q, n * n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hX.data(), X, n * B * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            if (i != j && std::llabs((long long)hQ[i * n + j]) > 127)
+                return fail(PSDP_E_UNSUPPORTED, "int8 operands need |Q_ij| <= 127 off the diagonal");
+    for (double v : hX) {
+        if (!std::isfinite(v)) return fail(PSDP_E_NONFINITE, "X must be finite");
+        if (digits == 4 && !(v >= 0.0 && v <= 1.0)) return fail(PSDP_E_NONFINITE, "digits 4 needs X in [0,1]");
+    }
+    Arena ar;
+    const int64_t ld = (n + 63) / 64 * 64;
+    const int64_t rows = (ld + kDigitRowsAlign - 1) / kDigitRowsAlign * kDigitRowsAlign;
+    const int D = digits;
+    const int ks = std::max(1, std::min(kMaxSplit, (int)((ld + 511) / 512)));
+    int8_t *Q8, *dig;
+    double *R, *dq;
+    int64_t *U0, *U1 = nullptr;
+    int32_t *act, *cnt, *esc;
+    HIPCHK(ar.get((void **)&Q8, rows * ld));
+    HIPCHK(hipMemsetAsync(Q8, 0, rows * ld, st));
+    HIPCHK(ar.get((void **)&R, ld * 8));
+    HIPCHK(ar.get((void **)&dq, ld * 8));
+    HIPCHK(launch_prep_q(PSDP_I8, Q, n, ld, PSDP_PERTURB_NONE, 0.0, 0, Q8, R, dq, st));
+    HIPCHK(ar.get((void **)&dig, (int64_t)(B + 1) * D * ld));
+    HIPCHK(hipMemsetAsync(dig, 0, (int64_t)(B + 1) * D * ld, st));
+    HIPCHK(ar.get((void **)&esc, (int64_t)B * sizeof(int32_t)));
+    HIPCHK(launch_digits_from_vectors(X, n, n, B, D, dig, ld, esc, st));
+    const int64_t slice = (int64_t)B * ld;
+    HIPCHK(ar.get((void **)&U0, ks * slice * sizeof(int64_t)));
+    if (D == 8) HIPCHK(ar.get((void **)&U1, ks * slice * sizeof(int64_t)));
+    std::vector<int32_t> iota(B + 1);
+    for (int c = 0; c < B; ++c) iota[c] = c;
+    iota[B] = B;  // live count
+    HIPCHK(ar.get((void **)&act, (B + 1) * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(act, iota.data(), (B + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    cnt = act + B;
+    const int rws = B * D;
+    const int mt = rws <= 16 ? 1 : (rws <= 32 ? 2 : 4);
+    const DigitJob job{dig, act, cnt, U0, U1, slice, B, ks, mt, B};
+    HIPCHK(launch_digit(Q8, ld, n, ld, D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
+    HIPCHK(launch_digit_combine(U0, U1, slice, ks, n, ld, B, D, esc, Y, st));
+    HIPCHK(hipStreamSynchronize(st));
     return PSDP_OK;
 }
 

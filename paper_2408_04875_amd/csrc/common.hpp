@@ -48,7 +48,7 @@ struct Col {
     int32_t hasP;        // LOBPCG search direction present
     int32_t exit_reason;
     int32_t ntrace;      // trace records written
-    int32_t pad0;
+    int32_t id;          // column index (digit planes of the integer path)
     double rho;          // rho at the current p (Section 3.3)
     double rho_outer;    // rho at the p of the current penalty update
     double lam;          // current Ritz value
@@ -61,7 +61,7 @@ struct Col {
     int64_t aux;         // lambda_min and CG products
     int64_t inner_start; // evals at the start of the current subproblem
     int32_t nI;          // |I| of the current penalty update
-    int32_t pad1;
+    int32_t escale;      // integer path: lambda_min / CG operand scaled by 2^-escale
 };
 
 // Flat solver workspace (device pointers), passed to every solver kernel.
@@ -89,6 +89,14 @@ struct Work {
     double *U_aux;
     int32_t *active_aux;
     int32_t *nactive_aux;
+    // exact integer products (I8): digit planes of the subproblem operands
+    // ([ncol + 1][4][ld] int8) and of the lambda_min / CG operands
+    // ([ncol + 1][8][ld]); U holds int64 slices, U_aux the high halves and
+    // U_lo the low halves of the 8-digit products
+    int32_t i8;
+    int8_t *dig;
+    int8_t *dig_aux;
+    int64_t *U_lo;
     int32_t *done_count;  // blocks finished in the current sweep (last one compacts)
     int64_t *sweeps;      // sweep counter (nullable)
     unsigned long long *phase_prof;  // optional per-phase {sum, count, max} of step ticks
@@ -114,10 +122,56 @@ template <> __device__ __forceinline__ double to_f64<__hip_bfloat16>(__hip_bfloa
 template <typename T> __device__ __forceinline__ T from_f64(double v);
 template <> __device__ __forceinline__ double from_f64<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_f64<float>(double v) { return __double2float_rn(v); }
+// int8 operand of the integer path: callers pass integers in [-127, 127]
+template <> __device__ __forceinline__ int8_t from_f64<int8_t>(double v) { return (int8_t)__double2int_rn(v); }
 template <> __device__ __forceinline__ __hip_bfloat16 from_f64<__hip_bfloat16>(double v) {
     // double -> float is exact for every value the callers pass (vectors in
     // [0,1] or preconditioned residuals); float -> bf16 rounds to nearest even
     return __float2bfloat16(__double2float_rn(v));
+}
+
+// ---------------------------------------------------------------------------
+// Integer operands of the exact product path: an integer T with
+// |T| <= 2^27 as four signed base-128 digits, most significant first,
+// T = d0 2^21 + d1 2^14 + d2 2^7 + d3 with every d in [-64, 64]
+// (each step keeps the nearest multiple of the next power, ties upward).
+// Digit t of element i goes to p[t * plane + i].
+constexpr double kMainScale = 134217728.0;  // 2^27: iterate grid of the 4-digit operand
+constexpr int kAuxBits = 55;                // 8-digit operand: v 2^(55 - e) rounded
+__device__ __forceinline__ void put_digits4(int8_t *p, int64_t plane, int64_t i, int64_t T) {
+    const int64_t d0 = (T + (1ll << 20)) >> 21;
+    T -= d0 << 21;
+    const int64_t d1 = (T + (1ll << 13)) >> 14;
+    T -= d1 << 14;
+    const int64_t d2 = (T + (1ll << 6)) >> 7;
+    T -= d2 << 7;
+    p[i] = (int8_t)d0;
+    p[plane + i] = (int8_t)d1;
+    p[2 * plane + i] = (int8_t)d2;
+    p[3 * plane + i] = (int8_t)T;
+}
+
+// Eight digits of v scaled by 2^-e (|v| < 2^e): T = rint(v 2^(55 - e)),
+// split as T = T_hi 2^28 + T_lo with |T_hi|, |T_lo| <= 2^27, each in four
+// digits (planes 0-3 and 4-7).
+__device__ __forceinline__ void put_digits8(int8_t *p, int64_t plane, int64_t i, double v, int e) {
+    const int64_t T = __double2ll_rn(ldexp(v, kAuxBits - e));
+    const int64_t hi = (T + (1ll << 27)) >> 28;
+    put_digits4(p, plane, i, hi);
+    put_digits4(p + 4 * plane, plane, i, T - (hi << 28));
+}
+
+// Value of an 8-digit product from its summed halves: (hi 2^28 + lo) 2^(e - 55),
+// both halves exact in FP64 (|hi|, |lo| < 2^51), one rounding in the sum.
+__device__ __forceinline__ double digits8_value(int64_t hi, int64_t lo, int e) {
+    return ldexp((double)hi * 268435456.0 + (double)lo, e - kAuxBits);
+}
+
+// Least e with |m| < 2^e for m > 0 (0 for m = 0): the 8-digit operand scale.
+__device__ __forceinline__ int digits8_exponent(double maxabs) {
+    int e = 0;
+    if (maxabs > 0.0) (void)frexp(maxabs, &e);
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -269,6 +323,28 @@ hipError_t launch_stream2(const void *Qop, int64_t ld, const void *op1, void *U1
 hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
                        const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
                        int ncol_max, hipStream_t st);
+
+// Exact integer products: U[kz][c][i] = sum_k Q8[i][k] T[c][k] over the K
+// slice kz, where T is a column's value in base-128 digits (4 digits, or 8
+// digits whose two 4-digit halves go to U0 and U1).
+struct DigitJob {
+    const int8_t *dig;       // digit planes [ncol + 1][D][ldq]; column ncol is zero
+    const int32_t *active;   // live column list and its device count
+    const int32_t *nactive;
+    int64_t *U0, *U1;        // outputs: column stride ldu, slice stride `slice`
+    int64_t slice;
+    int zero_col;            // index of the all-zero column
+    int ks;                  // K slices (1..8)
+    int mt;                  // 16-row digit tiles per wave (1, 2 or 4)
+    int est;                 // live count the grid is sized for (0: no launch)
+};
+constexpr int kDigitRowsAlign = 256;  // Q8 rows are allocated up to a multiple of this
+hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob *main4,
+                        const DigitJob *aux8, hipStream_t st);
+hipError_t launch_digits_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int8_t *dig,
+                                      int64_t ldq, int32_t *escale, hipStream_t st);
+hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t slice, int ks, int64_t n,
+                                int64_t ldu, int B, int D, const int32_t *escale, double *Y, hipStream_t st);
 
 // Solver kernels.
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,

@@ -160,6 +160,9 @@ hipError_t launch_prep_q(int dtype, const int32_t *Q, int64_t n, int64_t ld, int
     else if (dtype == PSDP_F32)
         hipLaunchKernelGGL(prep_q_kernel<float>, dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
                            sigma, key, (float *)Qop, R, dq);
+    else if (dtype == PSDP_I8)
+        hipLaunchKernelGGL(prep_q_kernel<int8_t>, dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
+                           sigma, key, (int8_t *)Qop, R, dq);
     else
         hipLaunchKernelGGL(prep_q_kernel<__hip_bfloat16>, dim3(ld), dim3(kBlock), 0, st, Q, n, ld,
                            perturb, sigma, key, (__hip_bfloat16 *)Qop, R, dq);

@@ -1,0 +1,280 @@
+// Exact integer Q.X products of the I8 operand path on gfx950 int8 MFMA:
+// the O(n^2) part of every penalty-gradient evaluation (eq. (kkt1)), of every
+// lambda_min matvec (eq. (alpha)) and of every x^0 CG matvec (eq. (gamma)).
+//
+// Q (integer, |Q_ij| <= 127 off the diagonal) is stored once as int8 with a
+// zero diagonal, ldq x ldq row-major (ldq a multiple of 64; rows allocated up
+// to a multiple of kDigitRowsAlign, the extra rows zero). A vector operand is
+// an integer column T in signed base-128 digits (put_digits4 / put_digits8):
+// 4 digits for an iterate on the grid 2^-27, 8 digits (two 4-digit halves)
+// for a lambda_min / CG vector scaled by a power of two. Digit plane t of
+// column c starts at dig + (c D + t) ldq.
+//
+// v_mfma_i32_16x16x64_i8 forms every digit product exactly in int32
+// (|sum| <= 64 * 127 * n < 2^31 for n <= 65536) and the epilogue combines
+// four digits in int64, U = ((Y0 128 + Y1) 128 + Y2) 128 + Y3 = Q T exactly.
+// The kernel computes D^T Q (Q is symmetric, so its row i is column i): the
+// A operand is the digit matrix (row r = (column, digit), K = n), the B
+// operand is Q. Register q of lane l of the accumulator holds row
+// 4 (l / 16) + q, column l % 16 (measured on gfx950), so the four digit rows
+// of one column land in one lane and combine without lane exchange; with 8
+// digits, the lane groups alternate between the high and the low half. Lane
+// l feeds A row l % 16 and B column l % 16 with the 16-byte K run
+// 16 (l / 16) .. + 15 of that row; A and B use the same run, so the sum
+// covers the same products whatever K order the unit applies.
+//
+// Work split: a block of 4 waves owns one group of MT digit tiles (16 MT / D
+// columns), one block of 4 * kDigitNT * 16 rows of Q (kDigitNT tiles per
+// wave) and one K slice; the waves read the same digit rows (L1 hits).
+// Blocks are ordered so that the column groups sharing one Q block run on
+// one XCD (one L2). Partial sums are integers, so K slices are exact and
+// the consumer's sum over slices does not depend on their order. The grid
+// is sized for an estimate of the live count; blocks loop over further
+// column groups, so the estimate changes only the speed.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace psdp {
+
+typedef int intx4 __attribute__((ext_vector_type(4)));
+
+struct DigitArgs {
+    const int8_t *Q;
+    int64_t ldq;
+    const int8_t *dig;
+    const int32_t *active;
+    const int32_t *nactive;
+    int64_t *U0, *U1;
+    int64_t ldu, slice, nrow, kchunk;
+    int AG, IB, KS, zero_col;
+};
+
+constexpr int kDigitNT = 2;   // 16-row Q tiles per wave
+constexpr int kDigitUNR = 2;  // K steps of 64 in flight per wave
+
+__device__ __forceinline__ int64_t combine4(const intx4 &a) {
+    return (((int64_t)a[0] * 128 + (int64_t)a[1]) * 128 + (int64_t)a[2]) * 128 + (int64_t)a[3];
+}
+
+__device__ __forceinline__ intx4 ld16(const int8_t *p) { return *(const intx4 *)p; }
+
+template <int D, int MT>
+__device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
+    constexpr int NT = kDigitNT, UNR = kDigitUNR;
+    constexpr int RA = 16 * MT;  // digit rows per column group
+    constexpr int CA = RA / D;   // columns per column group
+    if (L >= da.AG * da.IB * da.KS) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int nact = *da.nactive;
+    const int ag0 = L % da.AG;
+    const int rest = L / da.AG;
+    const int ib = rest % da.IB, kz = rest / da.IB;
+    const int64_t ldq = da.ldq;
+    const int64_t i0 = ((int64_t)ib * 4 + wv) * (16 * NT);
+    const int64_t kb = (int64_t)kz * da.kchunk;
+    const int64_t ke = min(ldq, kb + da.kchunk);
+    const int8_t *bq[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bq[t] = da.Q + (i0 + 16 * t + m) * ldq + 16 * g;
+    for (int ag = ag0; ag * CA < nact; ag += da.AG) {  // uniform over the block
+        const int8_t *ap[MT];
+#pragma unroll
+        for (int s = 0; s < MT; ++s) {
+            const int r = ag * RA + s * 16 + m;
+            const int slot = r / D;
+            const int64_t c = slot < nact ? (int64_t)da.active[slot] : (int64_t)da.zero_col;
+            ap[s] = da.dig + (c * D + (r % D)) * ldq + 16 * g;
+        }
+        intx4 acc[MT][NT];
+#pragma unroll
+        for (int s = 0; s < MT; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[s][t] = intx4{0, 0, 0, 0};
+        int64_t k0 = kb;
+        for (; k0 + 64 * UNR <= ke; k0 += 64 * UNR) {
+            intx4 a[UNR][MT], b[UNR][NT];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+                for (int s = 0; s < MT; ++s) a[u][s] = ld16(ap[s] + k0 + 64 * u);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) b[u][t] = ld16(bq[t] + k0 + 64 * u);
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int s = 0; s < MT; ++s)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][s], b[u][t], acc[s][t], 0, 0, 0);
+        }
+        for (; k0 < ke; k0 += 64) {
+            intx4 a[MT], b[NT];
+#pragma unroll
+            for (int s = 0; s < MT; ++s) a[s] = ld16(ap[s] + k0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[t] = ld16(bq[t] + k0);
+#pragma unroll
+            for (int s = 0; s < MT; ++s)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], b[t], acc[s][t], 0, 0, 0);
+        }
+        // lane group g holds digit rows 4 g .. 4 g + 3 of each tile: one column's
+        // 4 digits, or (D = 8) one half of one column's 8 digits
+#pragma unroll
+        for (int s = 0; s < MT; ++s) {
+            const int row0 = ag * RA + s * 16 + 4 * g;
+            const int slot = row0 / D;
+            if (slot >= nact) continue;
+            const int64_t c = da.active[slot];
+            int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
+            Uo += (int64_t)kz * da.slice + c * da.ldu;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int64_t i = i0 + 16 * t + m;
+                if (i < da.nrow) Uo[i] = combine4(acc[s][t]);
+            }
+        }
+    }
+}
+
+// Blocks b and b + 8 run on the same XCD; consecutive tile ids go to one XCD.
+// nb is a multiple of 8, so this is a bijection of [0, nb).
+__device__ __forceinline__ int xcd_order(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+
+// The 4-digit product (subproblem columns) in the first nb1 blocks, the
+// 8-digit product (lambda_min / CG columns) in the next nb2.
+template <int MT1, int MT2>
+__global__ void __launch_bounds__(kBlock) digit_kernel(DigitArgs a, DigitArgs b, int nb1, int nb2) {
+    const int bx = blockIdx.x;
+    if (bx < nb1) digit_body<4, MT1>(a, xcd_order(bx, nb1));
+    else digit_body<8, MT2>(b, xcd_order(bx - nb1, nb2));
+}
+
+static int clamp_mt(int mt) { return mt <= 1 ? 1 : (mt == 2 ? 2 : 4); }
+
+static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob &j, int D,
+                            int *nb) {
+    DigitArgs a{};
+    const int MT = clamp_mt(j.mt);
+    const int CA = 16 * MT / D;
+    const int ks = std::max(1, std::min(8, j.ks));
+    int64_t kc = (ldq + ks - 1) / ks;
+    kc = (kc + 63) / 64 * 64;
+    a.Q = Q8;
+    a.ldq = ldq;
+    a.dig = j.dig;
+    a.active = j.active;
+    a.nactive = j.nactive;
+    a.U0 = j.U0;
+    a.U1 = j.U1;
+    a.ldu = ldu;
+    a.slice = j.slice;
+    a.nrow = nrow;
+    a.kchunk = kc;
+    a.AG = std::max(1, (j.est + CA - 1) / CA);
+    a.IB = (int)((ldq + 64 * kDigitNT - 1) / (64 * kDigitNT));
+    a.KS = ks;  // a slice with an empty K range writes zeros
+    a.zero_col = j.zero_col;
+    const int total = a.AG * a.IB * a.KS;
+    *nb = (total + 7) / 8 * 8;
+    return a;
+}
+
+template <int MT1, int MT2>
+static void digit_go(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, hipStream_t st) {
+    hipLaunchKernelGGL((digit_kernel<MT1, MT2>), dim3((unsigned)(nb1 + nb2)), dim3(kBlock), 0, st, a, b, nb1,
+                       nb2);
+}
+
+template <int MT1>
+static void digit_go2(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, int mt2, hipStream_t st) {
+    if (mt2 == 1) digit_go<MT1, 1>(a, b, nb1, nb2, st);
+    else if (mt2 == 2) digit_go<MT1, 2>(a, b, nb1, nb2, st);
+    else digit_go<MT1, 4>(a, b, nb1, nb2, st);
+}
+
+// Either job may be null or have est = 0 (then it is not launched). Rows of
+// Q8 up to a multiple of kDigitRowsAlign must exist (zero past ldq).
+hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob *main4,
+                        const DigitJob *aux8, hipStream_t st) {
+    if (ldq % 64 != 0 || nrow > ldu || nrow > ldq) return hipErrorInvalidValue;
+    DigitArgs a{}, b{};
+    int nb1 = 0, nb2 = 0, mt1 = 1, mt2 = 1;
+    if (main4 && main4->est > 0) {
+        a = digit_args(Q8, ldq, nrow, ldu, *main4, 4, &nb1);
+        mt1 = clamp_mt(main4->mt);
+    }
+    if (aux8 && aux8->est > 0) {
+        b = digit_args(Q8, ldq, nrow, ldu, *aux8, 8, &nb2);
+        mt2 = clamp_mt(aux8->mt);
+    }
+    if (nb1 + nb2 == 0) return hipSuccess;
+    if (mt1 == 1) digit_go2<1>(a, b, nb1, nb2, mt2, st);
+    else if (mt1 == 2) digit_go2<2>(a, b, nb1, nb2, mt2, st);
+    else digit_go2<4>(a, b, nb1, nb2, mt2, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stand-alone product on user vectors (psdp_qx_digits): digits from the FP64
+// columns, then the summed slices back to FP64.
+
+// One block per column. D = 4: entries in [0,1] on the grid 2^-27. D = 8:
+// the column's scale exponent from its largest magnitude, then 8 digits.
+template <int D>
+__global__ void __launch_bounds__(kBlock) digits_from_vectors_kernel(const double *X, int64_t n, int64_t ldx,
+                                                                     int8_t *dig, int64_t ldq, int32_t *escale) {
+    const int64_t c = blockIdx.x;
+    const double *x = X + c * ldx;
+    int8_t *p = dig + c * D * ldq;
+    if constexpr (D == 4) {
+        for (int64_t i = threadIdx.x; i < n; i += kBlock) put_digits4(p, ldq, i, __double2ll_rn(x[i] * kMainScale));
+    } else {
+        __shared__ double red[kWaves];
+        double mx[1] = {0.0};
+        for (int64_t i = threadIdx.x; i < n; i += kBlock) mx[0] = fmax(mx[0], fabs(x[i]));
+        block_max<1>(mx, red);
+        const int e = digits8_exponent(mx[0]);
+        for (int64_t i = threadIdx.x; i < n; i += kBlock) put_digits8(p, ldq, i, x[i], e);
+        if (threadIdx.x == 0) escale[c] = e;
+    }
+}
+
+hipError_t launch_digits_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int8_t *dig,
+                                      int64_t ldq, int32_t *escale, hipStream_t st) {
+    if (D == 4)
+        hipLaunchKernelGGL(digits_from_vectors_kernel<4>, dim3(B), dim3(kBlock), 0, st, X, n, ldx, dig, ldq, escale);
+    else if (D == 8)
+        hipLaunchKernelGGL(digits_from_vectors_kernel<8>, dim3(B), dim3(kBlock), 0, st, X, n, ldx, dig, ldq, escale);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock) digit_combine_kernel(const int64_t *U0, const int64_t *U1, int64_t slice,
+                                                               int ks, int64_t n, int64_t ldu, int D,
+                                                               const int32_t *escale, double *Y) {
+    const int64_t c = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t idx = c * ldu + i;
+    int64_t s0 = 0, s1 = 0;
+    for (int t = 0; t < ks; ++t) {
+        s0 += U0[(int64_t)t * slice + idx];
+        if (D == 8) s1 += U1[(int64_t)t * slice + idx];
+    }
+    Y[c * n + i] = D == 4 ? (double)s0 / kMainScale : digits8_value(s0, s1, escale[c]);
+}
+
+hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t slice, int ks, int64_t n,
+                                int64_t ldu, int B, int D, const int32_t *escale, double *Y, hipStream_t st) {
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)B);
+    hipLaunchKernelGGL(digit_combine_kernel, grid, dim3(kBlock), 0, st, U0, U1, slice, ks, n, ldu, D, escale, Y);
+    return hipGetLastError();
+}
+
+}  // namespace psdp

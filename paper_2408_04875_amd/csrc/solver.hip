@@ -20,6 +20,8 @@
 // Element loops are unrolled EPT times per thread so that every load of a
 // pass is in flight at once; the last workgroup to finish a sweep rebuilds
 // the live-column lists for the next one.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace psdp {
@@ -30,34 +32,80 @@ namespace psdp {
         _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j)             \
             if (const int64_t i = _b + threadIdx.x + (int64_t)_j * kSB; i < (n))
 
+template <typename OpT> constexpr bool kDigits = std::is_same<OpT, int8_t>::value;
+
+// Product for a subproblem column, element i.
 template <typename UT>
-__device__ __forceinline__ double uval(const Work &w, int64_t idx) {
-    const UT *U = (const UT *)w.U;
-    double s = to_f64<UT>(U[idx]);
-    for (int t = 1; t < w.ksplit; ++t) s += to_f64<UT>(U[(int64_t)t * w.slice + idx]);
-    return s;
+__device__ __forceinline__ double uval(const Work &w, const Col &c, int64_t i) {
+    const int64_t idx = c.off + i;
+    if constexpr (std::is_same<UT, int64_t>::value) {
+        // integer path: Q x_q on the grid 2^-27, exact
+        const int64_t *U = (const int64_t *)w.U;
+        int64_t s = U[idx];
+        for (int t = 1; t < w.ksplit; ++t) s += U[(int64_t)t * w.slice + idx];
+        return (double)s / kMainScale;
+    } else {
+        const UT *U = (const UT *)w.U;
+        double s = to_f64<UT>(U[idx]);
+        for (int t = 1; t < w.ksplit; ++t) s += to_f64<UT>(U[(int64_t)t * w.slice + idx]);
+        return s;
+    }
 }
 
-// Product for a lambda_min / CG column (FP64 buffers when precision is split).
+// Product for a lambda_min / CG column (FP64 buffers when precision is split;
+// on the integer path the two int64 halves of the 8-digit product).
 template <typename UT>
-__device__ __forceinline__ double uaux(const Work &w, int64_t idx) {
-    if (!w.split) return uval<UT>(w, idx);
-    double s = w.U_aux[idx];
-    for (int t = 1; t < w.ksplit_aux; ++t) s += w.U_aux[(int64_t)t * w.slice_aux + idx];
-    return s;
+__device__ __forceinline__ double uaux(const Work &w, const Col &c, int64_t i) {
+    const int64_t idx = c.off + i;
+    if constexpr (std::is_same<UT, int64_t>::value) {
+        const int64_t *H = (const int64_t *)w.U_aux;
+        int64_t hi = H[idx], lo = w.U_lo[idx];
+        for (int t = 1; t < w.ksplit_aux; ++t) {
+            hi += H[(int64_t)t * w.slice_aux + idx];
+            lo += w.U_lo[(int64_t)t * w.slice_aux + idx];
+        }
+        return digits8_value(hi, lo, c.escale);
+    } else {
+        if (!w.split) return uval<UT>(w, c, i);
+        double s = w.U_aux[idx];
+        for (int t = 1; t < w.ksplit_aux; ++t) s += w.U_aux[(int64_t)t * w.slice_aux + idx];
+        return s;
+    }
 }
 
-// Next operand of a lambda_min / CG column.
+// Next operand of a lambda_min / CG column. The integer path keeps the FP64
+// value; its digits follow in aux_digits once the column's largest
+// magnitude is known.
 template <typename OpT>
-__device__ __forceinline__ void put_aux(const Work &w, int64_t idx, double v) {
-    if (w.split) w.op_aux[idx] = v;
-    else ((OpT *)w.op)[idx] = from_f64<OpT>(v);
+__device__ __forceinline__ void put_aux(const Work &w, const Col &c, int64_t i, double v) {
+    if (kDigits<OpT> || w.split) w.op_aux[c.off + i] = v;
+    else ((OpT *)w.op)[c.off + i] = from_f64<OpT>(v);
 }
 
-// Next operand of a subproblem column.
+// Next operand of a subproblem column (x in [0,1]; the integer path rounds
+// it to the grid 2^-27 and writes its 4 digits).
 template <typename OpT>
-__device__ __forceinline__ void put_main(const Work &w, int64_t idx, double v) {
-    ((OpT *)w.op)[idx] = from_f64<OpT>(v);
+__device__ __forceinline__ void put_main(const Work &w, const Col &c, int64_t i, double v) {
+    if constexpr (kDigits<OpT>)
+        put_digits4(w.dig + (int64_t)c.id * 4 * c.ld, c.ld, i, __double2ll_rn(v * kMainScale));
+    else
+        ((OpT *)w.op)[c.off + i] = from_f64<OpT>(v);
+}
+
+// Integer path: 8 digits of the lambda_min / CG operand just written by
+// put_aux (every thread rereads its own elements), scaled by 2^-e with e the
+// least integer above log2(maxabs). No-op on the floating-point paths.
+template <typename OpT, int EPT>
+__device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs) {
+    if constexpr (kDigits<OpT>) {
+        const int e = digits8_exponent(maxabs);
+        const int64_t n = c.n;
+        const double *src = w.op_aux + c.off;
+        int8_t *dst = w.dig_aux + (int64_t)c.id * 8 * c.ld;
+        FOR_I(n) put_digits8(dst, c.ld, i, src[i], e);
+        __syncthreads();  // every thread has read c.escale for this sweep
+        if (threadIdx.x == 0) c.escale = e;
+    }
 }
 
 __device__ __forceinline__ bool interior(double x) { return x > 0.0 && x < 1.0; }
@@ -119,8 +167,9 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
     FOR_I(n) {
         const double vi = interior(x[i]) ? v0 : 0.0;
         v[i] = vi;
-        put_aux<OpT>(w, c.off + i, vi);
+        put_aux<OpT>(w, c, i, vi);
     }
+    aux_digits<OpT, EPT>(w, c, v0);
 }
 
 // ---------------------------------------------------------------------------
@@ -145,7 +194,7 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
         const double A = (dq[i] + gam[i]) - pi;
         mx[0] = fmax(mx[0], 2.0 * (R[i] + fabs(A)));
         mx[1] = fmax(mx[1], fabs((b[i] - gam[i]) + pi));
-        put_main<OpT>(w, c.off + i, xi);
+        put_main<OpT>(w, c, i, xi);
     }
     bmax<2>(mx, red);
     if (threadIdx.x == 0) {
@@ -200,7 +249,7 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
         const double xi = x[i];
         const double A = (dq[i] + gam[i]) - p[i];
         const double bbar = (b[i] - gam[i]) + p[i];
-        const double gi = 2.0 * (uval<UT>(w, c.off + i) + A * xi) + bbar;
+        const double gi = 2.0 * (uval<UT>(w, c, i) + A * xi) + bbar;
         if (CACHE) {
             xr[_j] = xi;
             gr[_j] = gi;
@@ -261,7 +310,7 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
         xp[i] = xi;
         gp[i] = gi;
         x[i] = xn;
-        put_main<OpT>(w, c.off + i, xn);
+        put_main<OpT>(w, c, i, xn);
     }
     if (k + 1 >= w.max_inner) {
         __syncthreads();
@@ -424,7 +473,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
         double av = 0.0;
         if (interior(xi)) {
             const double A = (dq[i] + gam[i]) - p[i];
-            av = uaux<UT>(w, c.off + i) + A * v[i];
+            av = uaux<UT>(w, c, i) + A * v[i];
             sm[0] += v[i] * av;
             sm[1] += (xi - xi * xi) * v[i] * v[i];
         }
@@ -432,7 +481,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     bsum<2>(sm, red);
     const double lam = sm[0] / sm[1];
-    double rn[1] = {0.0};
+    double rn[1] = {0.0}, mw[1] = {0.0};
     FOR_I(n) {
         const double xi = x[i];
         double wi = 0.0;
@@ -444,9 +493,10 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
             wi = r / (A != 0.0 ? fabs(A) : 1.0);
         }
         wv[i] = wi;
-        put_aux<OpT>(w, c.off + i, wi);
+        mw[0] = fmax(mw[0], fabs(wi));
+        put_aux<OpT>(w, c, i, wi);
     }
-    bsum<1>(rn, red);
+    block_maxsum<1, 1, kSB>(mw, rn, red);
     if (threadIdx.x == 0) {
         c.aux += 1;
         c.it = 1;
@@ -458,6 +508,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
         eig_finish<OpT, EPT>(w, c, in, red, lam);
         return;
     }
+    aux_digits<OpT, EPT>(w, c, mw[0]);
     if (threadIdx.x == 0) c.phase = PH_EIG;
     __syncthreads();
 }
@@ -487,7 +538,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
             const double z = xi - xi * xi;
             const double A = (dq[i] + gam[i]) - p[i];
             const double wi = wv[i], vi = v[i];
-            aw = uaux<UT>(w, c.off + i) + A * wi;
+            aw = uaux<UT>(w, c, i) + A * wi;
             if (CACHE) {
                 zr[_j] = z;
                 Ar[_j] = A;
@@ -532,6 +583,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         return;
     }
     double rn[2] = {0.0, 0.0};  // ||r||^2_{Z^-1}, v'Zv
+    double mw[1] = {0.0};       // max |w| (scale of the integer operand)
     FOR_I(n) {
         double z, A, vi, wi, awi, avi, pi, api;
         bool in_I;
@@ -564,9 +616,10 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
             wn = r / (A != 0.0 ? fabs(A) : 1.0);
         }
         wv[i] = wn;
-        put_aux<OpT>(w, c.off + i, wn);
+        mw[0] = fmax(mw[0], fabs(wn));
+        put_aux<OpT>(w, c, i, wn);
     }
-    bsum<2>(rn, red);
+    block_maxsum<1, 2, kSB>(mw, rn, red);
     const int it = c.it + 1;
     if (threadIdx.x == 0) {
         c.aux += 1;
@@ -577,6 +630,8 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     __syncthreads();
     if (sqrt(rn[0] / rn[1]) <= w.eig_tol * fabs(theta) || it >= w.eig_maxit) {
         eig_finish<OpT, EPT>(w, c, in, red, theta);
+    } else {
+        aux_digits<OpT, EPT>(w, c, mw[0]);
     }
 }
 
@@ -591,7 +646,7 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
     const double *gam = w.gam + in.off, *dq = w.dq + in.off;
     double s1[1] = {0.0};
     FOR_I(n) {
-        const double kd = 2.0 * (uaux<UT>(w, c.off + i) + (dq[i] + gam[i]) * d[i]);
+        const double kd = 2.0 * (uaux<UT>(w, c, i) + (dq[i] + gam[i]) * d[i]);
         Kd[i] = kd;
         s1[0] += d[i] * kd;
     }
@@ -618,11 +673,17 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
         return;
     }
     const double beta = s2[0] / c.rz;
+    double md[1] = {0.0};
     FOR_I(n) {
         const double zz = r[i] / (2.0 * (dq[i] + gam[i]));
         const double dn = zz + beta * d[i];
         d[i] = dn;
-        put_aux<OpT>(w, c.off + i, dn);
+        md[0] = fmax(md[0], fabs(dn));
+        put_aux<OpT>(w, c, i, dn);
+    }
+    if constexpr (kDigits<OpT>) {
+        bmax<1>(md, red);
+        aux_digits<OpT, EPT>(w, c, md[0]);
     }
     if (threadIdx.x == 0) c.rz = s2[0];
     __syncthreads();
@@ -764,18 +825,20 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
     } else {
         const double *b = w.b + in.off, *gam = w.gam + in.off, *dq = w.dq + in.off;
         double *r = w.v + c.off, *d = w.w + c.off;
-        double s[2] = {0.0, 0.0};
+        double s[2] = {0.0, 0.0}, mz[1] = {0.0};
         FOR_I(n) {
             x[i] = 0.0;
             const double ri = gam[i] - b[i];
             const double zz = ri / (2.0 * (dq[i] + gam[i]));
             r[i] = ri;
             d[i] = zz;
-            put_aux<OpT>(w, c.off + i, zz);
+            mz[0] = fmax(mz[0], fabs(zz));
+            put_aux<OpT>(w, c, i, zz);
             s[0] += ri * zz;
             s[1] += ri * ri;
         }
-        bsum<2>(s, red);
+        block_maxsum<1, 2, kSB>(mz, s, red);
+        aux_digits<OpT, EPT>(w, c, mz[0]);
         if (threadIdx.x == 0) {
             c.rz = s[0];
             c.r0 = sqrt(s[1]);
@@ -811,6 +874,7 @@ static hipError_t step_ept(const Work &w, int64_t nmax, hipStream_t st) {
 }
 
 hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax, hipStream_t st) {
+    if (optype == PSDP_I8 && utype == PSDP_I8) return step_ept<int8_t, int64_t>(w, nmax, st);
     if (optype == PSDP_F64 && utype == PSDP_F64) return step_ept<double, double>(w, nmax, st);
     if (optype == PSDP_F32 && utype == PSDP_F32) return step_ept<float, float>(w, nmax, st);
     if (optype == PSDP_BF16 && utype == PSDP_F32) return step_ept<__hip_bfloat16, float>(w, nmax, st);
@@ -825,6 +889,7 @@ static hipError_t init_launch(const Work &w, const double *X0, int use_cg, hipSt
 
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,
                               hipStream_t st) {
+    if (optype == PSDP_I8) return init_launch<int8_t>(w, X0, use_cg, st);
     if (optype == PSDP_F64) return init_launch<double>(w, X0, use_cg, st);
     if (optype == PSDP_F32) return init_launch<float>(w, X0, use_cg, st);
     return init_launch<__hip_bfloat16>(w, X0, use_cg, st);

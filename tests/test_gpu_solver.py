@@ -27,7 +27,7 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("qdt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("qdt", ["f64", "f32", "bf16", "i8"])
 def test_plain_solve_bruteforce_set_bit_exact(P, qdt):
     mism = []
     cases = gen.bruteforce_set()
@@ -65,10 +65,11 @@ def test_plain_solve_n64_trace_matches_oracle(P):
     assert worst <= 1e-5
 
 
-def test_initial_point_matches_cholesky(P):
+@pytest.mark.parametrize("qdt", ["f64", "i8"])
+def test_initial_point_matches_cholesky(P, qdt):
     """max_outer = 0 returns x^0 of eq. (gamma) (CG on the GPU, Cholesky in the oracle)."""
     Q, b = gen.dense_int(200, 77)
-    r = P.solve(_t(Q), _t(b), max_outer=0)
+    r = P.solve(_t(Q), _t(b), max_outer=0, qx_dtype=qdt)
     gam = O.reformation_gamma(Q, b)
     x0 = O.initial_point(Q + np.diag(gam), b - gam)
     assert np.max(np.abs(r.X.cpu().numpy() - x0)) <= 1e-10
@@ -105,7 +106,7 @@ def test_single_start_from_x0_matches_oracle(P):
     assert sum(a == b_ for a, b_ in res) >= 5
 
 
-@pytest.mark.parametrize("qdt", ["f64", "f32"])
+@pytest.mark.parametrize("qdt", ["f64", "f32", "i8"])
 def test_batched_starts_match_per_start_oracle(P, qdt):
     Q, b = gen.dense_int(64, 3)
     X0 = gen.random_box_points(64, 24, 11)
@@ -145,7 +146,7 @@ def test_group_equals_single_instance_path_and_oracle(P):
     assert match >= 5
 
 
-@pytest.mark.parametrize("B,qdt", [(1, "f64"), (24, "f32"), (24, "f64")])
+@pytest.mark.parametrize("B,qdt", [(1, "f64"), (24, "f32"), (24, "f64"), (1, "i8"), (24, "i8")])
 def test_graph_replay_matches_eager_launches(P, B, qdt):
     """Sweeps replayed from captured graphs give bit-identical results."""
     Q, b = gen.dense_int(64, 3)
@@ -158,10 +159,48 @@ def test_graph_replay_matches_eager_launches(P, B, qdt):
         assert [s["inner_iters"] for s in g.stats] == [s["inner_iters"] for s in eager.stats]
 
 
-def test_run_to_run_bit_identity(P):
+@pytest.mark.parametrize("qdt", ["f32", "i8"])
+def test_run_to_run_bit_identity(P, qdt):
     """Fixed-order reductions: the same batched solve twice gives the same bits."""
     Q, b, X0 = gen.sparse_2500_starts(n=600, B=16)
-    a = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="f32")
-    c = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="f32")
+    a = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype=qdt)
+    c = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype=qdt)
     assert np.array_equal(a.X.cpu().numpy(), c.X.cpu().numpy())
     assert np.array_equal(a.obj.cpu().numpy(), c.obj.cpu().numpy())
+
+
+def test_integer_path_single_start_from_x0(P):
+    """I8 single starts (B = 1, exact integer products) against the oracle."""
+    Q, b = gen.dense_int(64, 3)
+    X0 = gen.random_box_points(64, 6, 11)
+    res = []
+    for c in range(len(X0)):
+        r = P.solve(_t(Q), _t(b), X0=_t(X0[c]), qx_dtype="i8")
+        _invariants(Q, b, r)
+        res.append((int(r.obj[0]), O.solve(Q, b, x0=X0[c]).obj))
+    print(f"i8 single start (gpu obj, oracle obj): {res}", flush=True)
+    assert sum(a == b_ for a, b_ in res) >= 5
+
+
+def test_integer_path_rejects_out_of_range(P):
+    Q, b = gen.dense_int(40, 5)
+    Q = Q.copy()
+    Q[0, 1] = Q[1, 0] = 200
+    with pytest.raises(P.PSDPError, match="unsupported"):
+        P.solve(_t(Q), _t(b), qx_dtype="i8")
+    Q[0, 1] = Q[1, 0] = 3
+    with pytest.raises(P.PSDPError, match="unsupported"):
+        P.solve(_t(Q), _t(b), qx_dtype="i8", perturb="full", sigma=0.5)
+
+
+def test_integer_path_batched_invariants_n1000(P):
+    """Batched I8 solve at n = 1000 (10% density): exact invariants of every column."""
+    Q, b, X0 = gen.sparse_2500_starts(n=1000, B=32)
+    r = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8")
+    _invariants(Q, b, r)
+    f = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="f32")
+    gi, gf = r.obj.cpu().numpy(), f.obj.cpu().numpy()
+    print(f"n=1000 B=32: i8 best {gi.min()} mean {gi.mean():.1f}; f32 best {gf.min()} mean {gf.mean():.1f}",
+          flush=True)
+    # different rounding, different trajectories: same quality on average (within 1%)
+    assert abs(gi.mean() - gf.mean()) <= 0.01 * abs(gf.mean())
