@@ -4,20 +4,32 @@ Workload: one UBQP instance, n = 2500, symmetric integer Q at 10% density with
 nonzeros uniform over +-{1..100}, b = 0, and 256 random starts uniform in
 [0,1)^n, all solved together (Algorithm 3 with projected alternating BB
 subproblems). One step = one whole batched solve: Q preparation, every sweep
-of Q.X products (FP32 MFMA for subproblem iterations, FP64 MFMA for lambda_min
-products), the per-column state machine, and the exact int64 objectives.
-Inputs are resident in device memory before the timed region starts.
+of Q.X products (subproblem and lambda_min / CG products), the per-column
+state machine, and the exact int64 objectives. Inputs are resident in device
+memory before the timed region starts.
+
+The default operand type is I8: exact integer products on int8 MFMA (an
+iterate rounded to the grid 2^-27, eigen/CG vectors to 55 bits of their
+scale; see include/psdp.h). Its only error is that rounding of x, below the
+rounding error of an FP32 GEMM. The same line also reports the FP32-GEMM solve
+of the same workload (`fp32_gemm`).
 
 value = penalty-gradient evaluations (one column of Q.X plus its gradient
 epilogue) per second over the timed steps. The JSON line also reports the
-roofline of the dominant kernel (the FP32 MFMA GEMM, timed with HIP events on
-its own stream around every launch), a plain single-instance comparison at
-equal objective on a subset of starts, and the FP64 oracle's rate on a bounded
-sample of the same workload on the host cores.
+roofline of the dominant kernel (the per-column step kernel, HBM-bound, timed
+with HIP events on the library's solve stream around every launch of one
+more solve of the same workload), the roofline of the Q.X product kernels, a
+plain single-instance comparison at equal objective on a subset of starts,
+and the FP64 oracle's rate on a bounded sample of the same workload on the
+host cores.
+
+`python bench.py --calibrate-copy` only copies 1 GiB between two device
+buffers (the reference kernel for the HBM byte counters).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,8 +39,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix FLOP/s
-PEAK_HBM = 8.0e12           # MI355X HBM3E bytes/s
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E, GB/s
+PEAK_INT8_TOPS = 5000.0     # MI355X dense int8 MFMA, TOPS
+PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 MFMA
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 MFMA
+STEP_BYTES_PER_COLUMN = 80  # about 10 FP64 vectors of n per column update
+STEP_SOURCES = ("paper_2408_04875_amd/csrc/solver.hip", "paper_2408_04875_amd/csrc/common.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_traffic.json")
 
 
 def parse():
@@ -41,14 +58,48 @@ def parse():
     ap.add_argument("--plain-starts", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--qx", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--qx", default="i8", choices=["i8", "f32", "f64"])
+    ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
+
+
+def step_source_hash():
+    h = hashlib.sha256()
+    for rel in STEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    runs, or None when they are missing or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != step_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def calibrate_copy():
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
 
 
 def cpu_baseline(Q, b, X0, budget_s=20.0):
     """FP64 oracle (as it stands) on a bounded sample: one start, until the
     subproblem evaluations of whole penalty updates exceed ~budget_s."""
-    import numpy as np
     from oracle import psdp as O
     try:
         from threadpoolctl import threadpool_info
@@ -56,14 +107,13 @@ def cpu_baseline(Q, b, X0, budget_s=20.0):
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
     t0 = time.perf_counter()
-    evals = 0
-    outer = 0
-    # grow max_outer until the sample takes long enough (each run restarts)
+    evals = outer = 0
+    wall = 1.0
     for mo in (1, 2, 4):
         t = time.perf_counter()
         r = O.solve(Q, b, O.Params(max_outer=mo), x0=X0[0])
-        el = time.perf_counter() - t
-        evals, outer, wall = r.inner_iters, r.outer_iters, el
+        wall = time.perf_counter() - t
+        evals, outer = r.inner_iters, r.outer_iters
         if time.perf_counter() - t0 > budget_s:
             break
     return {"value": evals / wall, "unit": "evals/s", "cores": cores, "kind": "oracle",
@@ -77,6 +127,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
               "described in the design notes but not part of this build.", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     import numpy as np
     import torch
     import paper_2408_04875_amd as P
@@ -91,30 +144,50 @@ def main():
     X0d = torch.from_numpy(X0).to(dev)
     torch.cuda.synchronize()
 
-    def step(timing):
-        return P.solve(Qd, bd, X0=X0d, qx_dtype=args.qx, timing=1 if timing else 0)
+    def step(qx, timing=False):
+        return P.solve(Qd, bd, X0=X0d, qx_dtype=qx, timing=1 if timing else 0)
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    results = []
-    for k in range(args.steps):
-        results.append(step(False))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    print(f"bench: {args.steps} timed steps in {wall:.2f} s", file=sys.stderr, flush=True)
-    evals = sum(sum(s["inner_iters"] for s in r.stats) for r in results)
+    def timed(qx, steps, warmup):
+        for _ in range(warmup):
+            step(qx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [step(qx) for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        evals = sum(sum(s["inner_iters"] for s in r.stats) for r in res)
+        return res, wall, evals
+
+    results, wall, evals = timed(args.qx, args.steps, args.warmup)
+    print(f"bench: {args.qx} {args.steps} timed steps in {wall:.2f} s", file=sys.stderr, flush=True)
     aux = sum(sum(s["aux_matvecs"] for s in r.stats) for r in results)
-    # one more step of the same workload with HIP events around every launch
-    # of the FP32 product (on the library's solve stream): its average launch
-    # duration and algorithmic flops give the roofline point
-    inst = step(True)
-    s0 = inst.stats[0]
-    qx_s, qx_f, qx_l = s0["qx_seconds"], s0["qx_flops"], s0["qx_launches"]
-    aux_s, aux_f = s0["aux_seconds"], s0["aux_flops"]
-    achieved = qx_f / qx_s if qx_s > 0 else 0.0
+    # one more solve of the same workload with HIP events around every launch
+    # (library solve stream): per-kernel average durations and algorithmic work
+    s0 = step(args.qx, timing=True).stats[0]
+    step_s, step_l, colsteps = s0["step_seconds"], s0["step_launches"], s0["column_steps"]
+    step_bytes = STEP_BYTES_PER_COLUMN * n * colsteps
+    qx_s = s0["qx_seconds"] + s0["aux_seconds"]
+    qx_f = s0["qx_flops"] + s0["aux_flops"]
+    qx_l = s0["qx_launches"]
+    step_rl = {"bound": "hbm", "achieved": step_bytes / step_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+               "frac": step_bytes / step_s / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic(),
+               "kernel": "solver_step_kernel (per-column subproblem / LOBPCG / CG step, one block per column)",
+               "launches": step_l, "avg_launch_us": step_s / max(step_l, 1) * 1e6,
+               "bytes_per_launch": step_bytes / max(step_l, 1),
+               "bytes_per_unit": f"{STEP_BYTES_PER_COLUMN} n per column update", "column_updates": colsteps,
+               "share_of_gpu_time": step_s / (step_s + qx_s) if step_s + qx_s > 0 else None}
+    if args.qx == "i8":
+        qx_peak, qx_unit, qx_name = PEAK_INT8_TOPS, "TOPS", "digit_kernel (int8 MFMA, exact int32/int64)"
+    elif args.qx == "f32":
+        qx_peak, qx_unit, qx_name = PEAK_FP32_TFLOPS, "TFLOP/s", "stream/gemm kernels (FP32 MFMA; FP64 aux)"
+    else:
+        qx_peak, qx_unit, qx_name = PEAK_FP64_TFLOPS, "TFLOP/s", "stream/gemm kernels (FP64 MFMA)"
+    qx_rl = {"bound": "mfma", "achieved": qx_f / qx_s / 1e12 if qx_s > 0 else 0.0, "peak": qx_peak,
+             "unit": qx_unit, "frac": (qx_f / qx_s / 1e12 / qx_peak) if qx_s > 0 else 0.0,
+             "kernel": qx_name, "launches": qx_l, "seconds": qx_s,
+             "work": "2 n^2 multiply-adds per column product (algorithmic; the int8 path executes 4 or 8 "
+                     "digit products per column)"}
+    dominant, other = (step_rl, qx_rl) if step_s >= qx_s else (qx_rl, step_rl)
     last = results[-1]
     objs = last.obj.cpu().numpy()
     out = {
@@ -128,28 +201,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.qx == "f32" else "f64",
+        "dtype": {"i8": "i8 digits, exact i32/i64 Q.X; f64 state", "f32": "f32 Q.X; f64 state",
+                  "f64": "f64"}[args.qx],
         "data": "synthetic",
         "config": {"workload": f"ubqp n={n} 10% density ints +-[1,100] b=0, {B} random starts in [0,1)^n, "
-                               f"batched PABB, Q.X {args.qx} MFMA (lambda_min/CG products f64)",
+                               f"batched PABB, Q.X {args.qx}",
                    "n": n, "starts": B, "global_batch": B, "parallelism": "single gpu"},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
-                     "kernel": "Q.X product of the subproblem columns (stream_kernel / gemm_kernel, "
-                               f"{'FP32' if args.qx == 'f32' else 'FP64'} MFMA)",
-                     "launches": qx_l, "avg_launch_us": qx_s / max(qx_l, 1) * 1e6,
-                     "flops_per_launch": qx_f / max(qx_l, 1),
-                     "instrumented_step_s": None},
+        "roofline": dominant,
+        "roofline_other": other,
         "solve": {"evals": evals // args.steps, "aux_matvecs": aux // args.steps,
                   "sweeps": int(last.stats[0]["sweeps"]),
-                  "qx_share_of_step": qx_s / (wall / args.steps),
-                  "aux_gemm_tflops": (aux_f / aux_s / 1e12) if aux_s > 0 else None,
                   "best_obj": int(objs.min()), "best_start": last.best,
                   "exit_reasons": {k: int((np.array([s["exit_reason"] for s in last.stats]) == v).sum())
                                    for k, v in (("converged", 0), ("outer_cap", 1), ("stall", 2))}},
     }
+    if not args.no_fp32 and args.qx != "f32":
+        fres, fwall, fevals = timed("f32", 1, 0)
+        out["fp32_gemm"] = {"value": fevals / fwall, "unit": "evals/s", "steps": 1,
+                            "best_obj": int(fres[-1].obj.min()),
+                            "note": "same workload with FP32-MFMA Q.X (FP64 lambda_min/CG products)"}
     if not args.no_plain and args.plain_starts > 0:
-        # the same starts one by one through the single-instance path (Q in FP32, GEMV)
+        # the same starts one by one through the single-instance path (same operand type)
         ks = list(range(args.plain_starts))
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -160,12 +232,10 @@ def main():
         po = [int(p.obj[0]) for p in plain]
         same = [k for k in ks if po[k] == int(objs[k])]
         plain_rate = sum(pe) / pw
-        # batched rate restricted to matching starts: their evaluations over the batched wall time share
         be = np.array([s["inner_iters"] for s in last.stats])
-        bat_rate = evals / wall
         out["plain"] = {"starts": len(ks), "evals_per_s": plain_rate, "wall_s": pw,
                         "equal_objective": len(same),
-                        "speedup_batched_vs_plain": bat_rate / plain_rate,
+                        "speedup_batched_vs_plain": (evals / wall) / plain_rate,
                         "batched_evals_matching": int(be[same].sum()) if same else 0,
                         "plain_evals_matching": int(sum(pe[k] for k in same))}
     if not args.no_cpu_baseline:

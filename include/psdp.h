@@ -126,8 +126,12 @@ typedef struct {
     double qx_seconds;         /* summed Q.X kernel time (timing = 1), whole launch */
     double qx_flops;           /* algorithmic flops of those Q.X launches (2 n^2 per column) */
     int64_t qx_launches;       /* number of Q.X launches timed */
-    double aux_seconds;        /* batched FP32: summed time of the FP64 lambda_min/CG products */
+    double aux_seconds;        /* split precision (batched F32, I8): summed time of the
+                                  lambda_min / CG products (timing = 1) */
     double aux_flops;          /* algorithmic flops of those products */
+    double step_seconds;       /* summed time of the per-column step kernel (timing = 1) */
+    int64_t step_launches;     /* number of step launches timed */
+    int64_t column_steps;      /* column updates performed by those launches (all columns) */
 } psdp_stats;
 
 /* Fills *p with the defaults listed above. */

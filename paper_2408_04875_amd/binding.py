@@ -65,6 +65,9 @@ class Stats(ctypes.Structure):
         ("qx_launches", ctypes.c_int64),
         ("aux_seconds", ctypes.c_double),
         ("aux_flops", ctypes.c_double),
+        ("step_seconds", ctypes.c_double),
+        ("step_launches", ctypes.c_int64),
+        ("column_steps", ctypes.c_int64),
     ]
 
     def as_dict(self):

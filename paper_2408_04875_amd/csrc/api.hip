@@ -281,7 +281,7 @@ struct QxTimer {
 // the main live list, `apply_aux` (split precision only) the FP64 product of
 // the lambda_min / CG list.
 template <typename Apply, typename ApplyAux>
-psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &ta, hipStream_t st,
+psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &ta, QxTimer &ts, hipStream_t st,
                        const Apply &apply, const ApplyAux &apply_aux) {
     Work &w = S.w;
     int32_t *host_cnt = nullptr;
@@ -327,7 +327,9 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
                 if ((e = apply_aux()) != hipSuccess) return e;
                 if ((e = ta.end(st)) != hipSuccess) return e;
             }
+            if ((e = ts.begin(st)) != hipSuccess) return e;
             if ((e = launch_solver_step(S.optype, S.utype, w, S.nmax, st)) != hipSuccess) return e;
+            if ((e = ts.end(st)) != hipSuccess) return e;
         }
         return hipSuccess;
     };
@@ -364,21 +366,25 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
             if (host_cnt[2 * prev] + host_cnt[2 * prev + 1] == 0) finished = true;
             else if (S.repick) S.repick(host_cnt[2 * prev], host_cnt[2 * prev + 1]);
         }
-        if ((tm.on && tm.used > 4096) || (ta.on && ta.used > 4096)) {
+        if ((tm.on && tm.used > 4096) || (ta.on && ta.used > 4096) || (ts.on && ts.used > 4096)) {
             HIPCHK(hipEventSynchronize(evs[slot]));
             HIPCHK(tm.collect());
             HIPCHK(ta.collect());
+            HIPCHK(ts.collect());
         }
         ++batch;
     }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(tm.collect());
     HIPCHK(ta.collect());
+    HIPCHK(ts.collect());
     return PSDP_OK;
 }
 
 void fill_stats(const std::vector<Col> &cols, int64_t sweeps, const QxTimer &tm, double flops_total,
-                const QxTimer &ta, double aux_flops, psdp_stats *stats) {
+                const QxTimer &ta, double aux_flops, const QxTimer &ts, psdp_stats *stats) {
+    int64_t colsteps = 0;
+    for (const Col &c : cols) colsteps += c.evals + c.aux;
     for (size_t c = 0; c < cols.size(); ++c) {
         psdp_stats &s = stats[c];
         std::memset(&s, 0, sizeof s);
@@ -394,6 +400,9 @@ void fill_stats(const std::vector<Col> &cols, int64_t sweeps, const QxTimer &tm,
         s.qx_launches = tm.launches;
         s.aux_seconds = ta.seconds;
         s.aux_flops = aux_flops;
+        s.step_seconds = ts.seconds;
+        s.step_launches = ts.launches;
+        s.column_steps = colsteps;
     }
 }
 
@@ -580,20 +589,20 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         pk.ks = std::max(1, std::min(kMaxSplit, (512 + tiles - 1) / tiles));
         return pk;
     };
-    // integer path: digit tiles per wave from the estimated live count, and
-    // enough K slices for about 640 blocks
+    // integer path: layouts from the estimated live counts, K slices from
+    // the blocks of both products (they share one launch)
     struct Pick8 { int mt; int ks; int est; };
-    const int IB8 = (int)((ld + 127) / 128);
-    auto pick8 = [&](int ncols, int D) {
-        Pick8 pk;
-        pk.est = std::min(B, ncols + 16);
-        const int rows = pk.est * D;
-        pk.mt = rows <= 16 ? 1 : (rows <= 32 ? 2 : 4);
-        const int ag = (pk.est + 16 * pk.mt / D - 1) / (16 * pk.mt / D);
-        pk.ks = std::max(1, std::min(kMaxSplit, (640 + ag * IB8 - 1) / (ag * IB8)));
-        return pk;
+    Pick8 p8m{}, p8a{};
+    auto pick8 = [&](int cm, int ca) {
+        int bm = 0, ba = 0;
+        p8m.est = std::min(B, cm + 16);
+        p8a.est = std::min(B, ca + 16);
+        digit_layout(p8m.est, 4, ld, &p8m.mt, &bm);
+        digit_layout(p8a.est, 8, ld, &p8a.mt, &ba);
+        p8m.ks = digit_slices(p8m.mt, bm + ba);
+        p8a.ks = digit_slices(p8a.mt, bm + ba);
     };
-    Pick8 p8m = pick8(B, 4), p8a = pick8(B, 8);
+    pick8(B, B);
     Pick pm = pick(B, main_gemm), pa = pick(B, aux_gemm);
     w.ksplit = i8 ? p8m.ks : pm.ks;
     w.ksplit_aux = i8 ? p8a.ks : (w.split ? pa.ks : w.ksplit);
@@ -626,8 +635,8 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         HIPCHK(S.ar.get((void **)&w.phase_prof, 16 * sizeof(unsigned long long)));
         HIPCHK(hipMemsetAsync(w.phase_prof, 0, 16 * sizeof(unsigned long long), st));
     }
-    QxTimer tm, ta;
-    tm.on = ta.on = prm.timing != 0;
+    QxTimer tm, ta, ts;
+    tm.on = ta.on = ts.on = prm.timing != 0;
     auto none = []() { return hipSuccess; };
     psdp_status rs;
     if (i8) {
@@ -645,25 +654,20 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
                    ((int64_t)p8m.est << 14) | ((int64_t)p8a.est << 34);
         };
         S.repick = [&](int cm, int ca) {
-            p8m = pick8(cm, 4);
-            p8a = pick8(ca, 8);
+            pick8(cm, ca);
             w.ksplit = p8m.ks;
             w.ksplit_aux = p8a.ks;
         };
-        // both products in one launch, or apart when every launch is timed
+        // both products in one launch (timed as one launch when timing = 1)
         rs = run_sweeps(
-            S, prm, tm, ta, st,
+            S, prm, tm, ta, ts, st,
             [&]() {
                 const DigitJob jm = job_main(), ja = job_aux();
-                return launch_digit(Q8, ld, n, ld, &jm, tm.on ? nullptr : &ja, st);
+                return launch_digit(Q8, ld, n, ld, &jm, &ja, st);
             },
-            [&]() {
-                if (!tm.on) return hipSuccess;
-                const DigitJob ja = job_aux();
-                return launch_digit(Q8, ld, n, ld, nullptr, &ja, st);
-            });
+            none);
     } else if (!batched) {
-        rs = run_sweeps(S, prm, tm, ta, st, [&]() { return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st); },
+        rs = run_sweeps(S, prm, tm, ta, ts, st, [&]() { return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st); },
                         none);
     } else {
         const bool merge = w.split && prm.timing == 0 && main_gemm == PSDP_F32 && aux_gemm == kGemmF32QF64;
@@ -679,7 +683,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
             w.ksplit_aux = w.split ? pa.ks : w.ksplit;
         };
         rs = run_sweeps(
-            S, prm, tm, ta, st,
+            S, prm, tm, ta, ts, st,
             [&]() {
                 // split precision with both lists on the streaming kernel: one
                 // launch for both products (kept apart when every launch is timed)
@@ -742,10 +746,12 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     if (stats) {
         double flops = 0.0, aflops = 0.0;
         for (const Col &cc : hcol) {
-            flops += 2.0 * (double)n * (double)n * (double)(w.split ? cc.evals : cc.evals + cc.aux);
-            aflops += w.split ? 2.0 * (double)n * (double)n * (double)cc.aux : 0.0;
+            // the integer path times both products in one launch
+            const bool apart = w.split && !w.i8;
+            flops += 2.0 * (double)n * (double)n * (double)(apart ? cc.evals : cc.evals + cc.aux);
+            aflops += apart ? 2.0 * (double)n * (double)n * (double)cc.aux : 0.0;
         }
-        fill_stats(hcol, nsweeps, tm, flops, ta, aflops, stats);
+        fill_stats(hcol, nsweeps, tm, flops, ta, aflops, ts, stats);
     }
     return PSDP_OK;
 }
@@ -842,10 +848,10 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     HIPCHK(hipMemcpyAsync(drow, rowstart.data(), (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIPCHK(launch_solver_init(S.optype, w, nullptr, 1, st));
     HIPCHK(launch_compact(w, st));
-    QxTimer tm, ta;
-    tm.on = prm.timing != 0;
+    QxTimer tm, ta, ts;
+    tm.on = ts.on = prm.timing != 0;
     psdp_status rs = run_sweeps(
-        S, prm, tm, ta, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, rowstart[count], st); },
+        S, prm, tm, ta, ts, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, rowstart[count], st); },
         []() { return hipSuccess; });
     if (rs != PSDP_OK) return rs;
     int64_t maxblk = 0;
@@ -862,7 +868,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     if (stats) {
         double flops = 0.0;
         for (const Col &cc : hcol) flops += 2.0 * (double)cc.n * (double)cc.n * (double)(cc.evals + cc.aux);
-        fill_stats(hcol, nsweeps, tm, flops, ta, 0.0, stats);
+        fill_stats(hcol, nsweeps, tm, flops, ta, 0.0, ts, stats);
     }
     return PSDP_OK;
 }
@@ -953,7 +959,9 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     const int64_t ld = (n + 63) / 64 * 64;
     const int64_t rows = (ld + kDigitRowsAlign - 1) / kDigitRowsAlign * kDigitRowsAlign;
     const int D = digits;
-    const int ks = std::max(1, std::min(kMaxSplit, (int)((ld + 511) / 512)));
+    int mt = 4, nb = 1;
+    digit_layout(B, digits, ld, &mt, &nb);
+    const int ks = digit_slices(mt, nb);
     int8_t *Q8, *dig;
     double *R, *dq;
     int64_t *U0, *U1 = nullptr;
@@ -976,8 +984,6 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     HIPCHK(ar.get((void **)&act, (B + 1) * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(act, iota.data(), (B + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
     cnt = act + B;
-    const int rws = B * D;
-    const int mt = rws <= 16 ? 1 : (rws <= 32 ? 2 : 4);
     const DigitJob job{dig, act, cnt, U0, U1, slice, B, ks, mt, B};
     HIPCHK(launch_digit(Q8, ld, n, ld, D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
     HIPCHK(launch_digit_combine(U0, U1, slice, ks, n, ld, B, D, esc, Y, st));

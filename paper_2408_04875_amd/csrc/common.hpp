@@ -339,6 +339,11 @@ struct DigitJob {
     int est;                 // live count the grid is sized for (0: no launch)
 };
 constexpr int kDigitRowsAlign = 256;  // Q8 rows are allocated up to a multiple of this
+// Layout (DigitJob.mt) and base block count (one K slice) of a product sized
+// for est columns of D digits; digit_slices then spreads the K range of both
+// products of a sweep over enough blocks in total.
+void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks);
+int digit_slices(int mt, int blocks_total);
 hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob *main4,
                         const DigitJob *aux8, hipStream_t st);
 hipError_t launch_digits_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int8_t *dig,

@@ -24,8 +24,8 @@
 // covers the same products whatever K order the unit applies.
 //
 // Work split: a block of 4 waves owns one group of MT digit tiles (16 MT / D
-// columns), one block of 4 * kDigitNT * 16 rows of Q (kDigitNT tiles per
-// wave) and one K slice; the waves read the same digit rows (L1 hits).
+// columns), one block of rows of Q and one K slice (DigitShape below); the
+// waves read the same digit rows (L1 hits).
 // Blocks are ordered so that the column groups sharing one Q block run on
 // one XCD (one L2). Partial sums are integers, so K slices are exact and
 // the consumer's sum over slices does not depend on their order. The grid
@@ -50,8 +50,21 @@ struct DigitArgs {
     int AG, IB, KS, zero_col;
 };
 
-constexpr int kDigitNT = 2;   // 16-row Q tiles per wave
-constexpr int kDigitUNR = 2;  // K steps of 64 in flight per wave
+// Two block layouts, both 4 waves (chosen by a timing sweep on gfx950 at
+// n = 2500):
+//  many columns (MT = 4, NT = 4, WK = 1): the waves own 4 consecutive
+//    64-row blocks of Q over the block's whole K slice;
+//  few columns (MT = 1, NT = 2, WK = 4): the waves split the K slice of one
+//    32-row block into 4 parts and wave 0 adds the parts from LDS, so that
+//    even one column keeps many blocks busy without many output slices.
+// UNR K steps of 64 per register stage; two stages alternate so that the
+// loads of the next stage are in flight while the current one multiplies.
+template <int MT, int NT, int WK, int UNR> struct DigitShape {
+    static constexpr int kMT = MT, kNT = NT, kWK = WK, kWR = 4 / WK, kUNR = UNR;
+    static constexpr int kRows = kWR * 16 * NT;  // Q rows per block
+};
+typedef DigitShape<4, 4, 1, 2> DigitMany;
+typedef DigitShape<1, 2, 4, 2> DigitFew;
 
 __device__ __forceinline__ int64_t combine4(const intx4 &a) {
     return (((int64_t)a[0] * 128 + (int64_t)a[1]) * 128 + (int64_t)a[2]) * 128 + (int64_t)a[3];
@@ -59,22 +72,33 @@ __device__ __forceinline__ int64_t combine4(const intx4 &a) {
 
 __device__ __forceinline__ intx4 ld16(const int8_t *p) { return *(const intx4 *)p; }
 
-template <int D, int MT>
+template <int D, typename S>
 __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
-    constexpr int NT = kDigitNT, UNR = kDigitUNR;
+    constexpr int MT = S::kMT, NT = S::kNT, WK = S::kWK, WR = S::kWR, UNR = S::kUNR;
     constexpr int RA = 16 * MT;  // digit rows per column group
     constexpr int CA = RA / D;   // columns per column group
+    __shared__ intx4 part[WK > 1 ? WK - 1 : 1][MT * NT][64];
     if (L >= da.AG * da.IB * da.KS) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index through readfirstlane: the K bounds and the loop
+    // control below are then scalar, and the loads need no exec masking
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wr = wv % WR, wk = wv / WR;
     const int m = lane & 15, g = lane >> 4;
     const int nact = *da.nactive;
     const int ag0 = L % da.AG;
     const int rest = L / da.AG;
     const int ib = rest % da.IB, kz = rest / da.IB;
     const int64_t ldq = da.ldq;
-    const int64_t i0 = ((int64_t)ib * 4 + wv) * (16 * NT);
-    const int64_t kb = (int64_t)kz * da.kchunk;
-    const int64_t ke = min(ldq, kb + da.kchunk);
+    const int64_t i0 = ((int64_t)ib * WR + wr) * (16 * NT);
+    // the block's K slice, split into WK parts of whole stages (UNR steps of
+    // 64); the last part may end with a few single steps
+    const int64_t kb0 = (int64_t)kz * da.kchunk;
+    const int64_t ke0 = min(ldq, kb0 + da.kchunk);
+    const int64_t nch = ke0 > kb0 ? (ke0 - kb0) / 64 : 0;
+    const int64_t per = ((nch + WK - 1) / WK + UNR - 1) / UNR * UNR;
+    const int64_t kb = kb0 + 64 * min(nch, per * wk);
+    const int64_t ke = kb0 + 64 * min(nch, per * (wk + 1));
+    const int64_t nstage = (ke - kb) / (64 * UNR);
     const int8_t *bq[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bq[t] = da.Q + (i0 + 16 * t + m) * ldq + 16 * g;
@@ -92,16 +116,21 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
         for (int s = 0; s < MT; ++s)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[s][t] = intx4{0, 0, 0, 0};
-        int64_t k0 = kb;
-        for (; k0 + 64 * UNR <= ke; k0 += 64 * UNR) {
-            intx4 a[UNR][MT], b[UNR][NT];
+        // two register stages: the next stage's loads are issued before the
+        // current stage multiplies. Every load is unconditional and in
+        // bounds (a prefetch past the last stage reloads the current one),
+        // so the code is straight-line and the waits count loads exactly.
+        intx4 a0[UNR][MT], b0[UNR][NT], a1[UNR][MT], b1[UNR][NT];
+        auto load = [&](intx4 (&a)[UNR][MT], intx4 (&b)[UNR][NT], int64_t k) {
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
 #pragma unroll
-                for (int s = 0; s < MT; ++s) a[u][s] = ld16(ap[s] + k0 + 64 * u);
+                for (int s = 0; s < MT; ++s) a[u][s] = ld16(ap[s] + k + 64 * u);
 #pragma unroll
-                for (int t = 0; t < NT; ++t) b[u][t] = ld16(bq[t] + k0 + 64 * u);
+                for (int t = 0; t < NT; ++t) b[u][t] = ld16(bq[t] + k + 64 * u);
             }
+        };
+        auto mult = [&](const intx4 (&a)[UNR][MT], const intx4 (&b)[UNR][NT]) {
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -109,33 +138,71 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
 #pragma unroll
                     for (int t = 0; t < NT; ++t)
                         acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][s], b[u][t], acc[s][t], 0, 0, 0);
+        };
+        int64_t k = kb;
+        if (nstage > 0) {
+            load(a0, b0, k);
+            for (int64_t st = 0; st < nstage; st += 2) {
+                const bool m1 = st + 1 < nstage;
+                load(a1, b1, m1 ? k + 64 * UNR : k);
+                mult(a0, b0);
+                if (!m1) {
+                    k += 64 * UNR;
+                    break;
+                }
+                const bool m2 = st + 2 < nstage;
+                load(a0, b0, m2 ? k + 128 * UNR : k);
+                mult(a1, b1);
+                k += 128 * UNR;
+            }
         }
-        for (; k0 < ke; k0 += 64) {
+        for (; k < ke; k += 64) {  // fewer than UNR single steps
             intx4 a[MT], b[NT];
 #pragma unroll
-            for (int s = 0; s < MT; ++s) a[s] = ld16(ap[s] + k0);
+            for (int s = 0; s < MT; ++s) a[s] = ld16(ap[s] + k);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = ld16(bq[t] + k0);
+            for (int t = 0; t < NT; ++t) b[t] = ld16(bq[t] + k);
 #pragma unroll
             for (int s = 0; s < MT; ++s)
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
                     acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], b[t], acc[s][t], 0, 0, 0);
         }
-        // lane group g holds digit rows 4 g .. 4 g + 3 of each tile: one column's
-        // 4 digits, or (D = 8) one half of one column's 8 digits
+        if constexpr (WK > 1) {
+            // integer partial sums: wave 0 adds the other K parts (exact in any order)
+            __syncthreads();  // the previous group's parts have been read
+            if (wk > 0) {
 #pragma unroll
-        for (int s = 0; s < MT; ++s) {
-            const int row0 = ag * RA + s * 16 + 4 * g;
-            const int slot = row0 / D;
-            if (slot >= nact) continue;
-            const int64_t c = da.active[slot];
-            int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
-            Uo += (int64_t)kz * da.slice + c * da.ldu;
+                for (int s = 0; s < MT; ++s)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int64_t i = i0 + 16 * t + m;
-                if (i < da.nrow) Uo[i] = combine4(acc[s][t]);
+                    for (int t = 0; t < NT; ++t) part[wk - 1][s * NT + t][lane] = acc[s][t];
+            }
+            __syncthreads();
+            if (wk == 0) {
+#pragma unroll
+                for (int q = 0; q < WK - 1; ++q)
+#pragma unroll
+                    for (int s = 0; s < MT; ++s)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) acc[s][t] += part[q][s * NT + t][lane];
+            }
+        }
+        if (wk == 0) {
+            // lane group g holds digit rows 4 g .. 4 g + 3 of each tile: one
+            // column's 4 digits, or (D = 8) one half of one column's 8 digits
+#pragma unroll
+            for (int s = 0; s < MT; ++s) {
+                const int row0 = ag * RA + s * 16 + 4 * g;
+                const int slot = row0 / D;
+                if (slot >= nact) continue;
+                const int64_t c = da.active[slot];
+                int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
+                Uo += (int64_t)kz * da.slice + c * da.ldu;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int64_t i = i0 + 16 * t + m;
+                    if (i < da.nrow) Uo[i] = combine4(acc[s][t]);
+                }
             }
         }
     }
@@ -147,20 +214,20 @@ __device__ __forceinline__ int xcd_order(int b, int nb) { return (b & 7) * (nb >
 
 // The 4-digit product (subproblem columns) in the first nb1 blocks, the
 // 8-digit product (lambda_min / CG columns) in the next nb2.
-template <int MT1, int MT2>
+template <typename S1, typename S2>
 __global__ void __launch_bounds__(kBlock) digit_kernel(DigitArgs a, DigitArgs b, int nb1, int nb2) {
     const int bx = blockIdx.x;
-    if (bx < nb1) digit_body<4, MT1>(a, xcd_order(bx, nb1));
-    else digit_body<8, MT2>(b, xcd_order(bx - nb1, nb2));
+    if (bx < nb1) digit_body<4, S1>(a, xcd_order(bx, nb1));
+    else digit_body<8, S2>(b, xcd_order(bx - nb1, nb2));
 }
 
-static int clamp_mt(int mt) { return mt <= 1 ? 1 : (mt == 2 ? 2 : 4); }
-
+// j.mt selects the layout: 1 = few columns (DigitFew), otherwise DigitMany.
 static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob &j, int D,
                             int *nb) {
     DigitArgs a{};
-    const int MT = clamp_mt(j.mt);
-    const int CA = 16 * MT / D;
+    const bool few = j.mt <= 1;
+    const int CA = 16 * (few ? DigitFew::kMT : DigitMany::kMT) / D;
+    const int rows = few ? DigitFew::kRows : DigitMany::kRows;
     const int ks = std::max(1, std::min(8, j.ks));
     int64_t kc = (ldq + ks - 1) / ks;
     kc = (kc + 63) / 64 * 64;
@@ -176,7 +243,7 @@ static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t
     a.nrow = nrow;
     a.kchunk = kc;
     a.AG = std::max(1, (j.est + CA - 1) / CA);
-    a.IB = (int)((ldq + 64 * kDigitNT - 1) / (64 * kDigitNT));
+    a.IB = (int)((ldq + rows - 1) / rows);
     a.KS = ks;  // a slice with an empty K range writes zeros
     a.zero_col = j.zero_col;
     const int total = a.AG * a.IB * a.KS;
@@ -184,17 +251,26 @@ static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t
     return a;
 }
 
-template <int MT1, int MT2>
-static void digit_go(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, hipStream_t st) {
-    hipLaunchKernelGGL((digit_kernel<MT1, MT2>), dim3((unsigned)(nb1 + nb2)), dim3(kBlock), 0, st, a, b, nb1,
-                       nb2);
+void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks) {
+    const bool few = est <= 32;
+    const int CA = 16 * (few ? DigitFew::kMT : DigitMany::kMT) / D;
+    const int rows = few ? DigitFew::kRows : DigitMany::kRows;
+    *mt = few ? 1 : 4;
+    *blocks = std::max(1, (est + CA - 1) / CA) * (int)((ldq + rows - 1) / rows);
 }
 
-template <int MT1>
-static void digit_go2(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, int mt2, hipStream_t st) {
-    if (mt2 == 1) digit_go<MT1, 1>(a, b, nb1, nb2, st);
-    else if (mt2 == 2) digit_go<MT1, 2>(a, b, nb1, nb2, st);
-    else digit_go<MT1, 4>(a, b, nb1, nb2, st);
+// Measured on gfx950: the many-column layout does best with about 512 blocks
+// in the launch and at most 4 slices, the few-column layout with 2 slices
+// unless the launch is already large.
+int digit_slices(int mt, int blocks_total) {
+    blocks_total = std::max(1, blocks_total);
+    if (mt <= 1) return std::max(1, std::min(2, (1024 + blocks_total / 2) / blocks_total));
+    return std::max(1, std::min(4, (512 + blocks_total / 2) / blocks_total));
+}
+
+template <typename S1, typename S2>
+static void digit_go(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, hipStream_t st) {
+    hipLaunchKernelGGL((digit_kernel<S1, S2>), dim3((unsigned)(nb1 + nb2)), dim3(kBlock), 0, st, a, b, nb1, nb2);
 }
 
 // Either job may be null or have est = 0 (then it is not launched). Rows of
@@ -203,19 +279,21 @@ hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu
                         const DigitJob *aux8, hipStream_t st) {
     if (ldq % 64 != 0 || nrow > ldu || nrow > ldq) return hipErrorInvalidValue;
     DigitArgs a{}, b{};
-    int nb1 = 0, nb2 = 0, mt1 = 1, mt2 = 1;
+    int nb1 = 0, nb2 = 0;
+    bool few1 = true, few2 = true;
     if (main4 && main4->est > 0) {
         a = digit_args(Q8, ldq, nrow, ldu, *main4, 4, &nb1);
-        mt1 = clamp_mt(main4->mt);
+        few1 = main4->mt <= 1;
     }
     if (aux8 && aux8->est > 0) {
         b = digit_args(Q8, ldq, nrow, ldu, *aux8, 8, &nb2);
-        mt2 = clamp_mt(aux8->mt);
+        few2 = aux8->mt <= 1;
     }
     if (nb1 + nb2 == 0) return hipSuccess;
-    if (mt1 == 1) digit_go2<1>(a, b, nb1, nb2, mt2, st);
-    else if (mt1 == 2) digit_go2<2>(a, b, nb1, nb2, mt2, st);
-    else digit_go2<4>(a, b, nb1, nb2, mt2, st);
+    if (few1 && few2) digit_go<DigitFew, DigitFew>(a, b, nb1, nb2, st);
+    else if (few1) digit_go<DigitFew, DigitMany>(a, b, nb1, nb2, st);
+    else if (few2) digit_go<DigitMany, DigitFew>(a, b, nb1, nb2, st);
+    else digit_go<DigitMany, DigitMany>(a, b, nb1, nb2, st);
     return hipGetLastError();
 }
 
