@@ -26,11 +26,30 @@
 
 namespace psdp {
 
-// Visits i = threadIdx.x + j * kSB (+ multiples of EPT * kSB) for i < n.
+// Visits i = threadIdx.x + j * kSB (+ multiples of EPT * kSB) for i < n
+// (set-up code; the per-sweep passes use the chunked form below).
 #define FOR_I(n)                                                       \
     for (int64_t _b = 0; _b < (n); _b += (int64_t)EPT * kSB)           \
         _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j)             \
             if (const int64_t i = _b + threadIdx.x + (int64_t)_j * kSB; i < (n))
+
+// Per-sweep passes work on chunks of EPT elements per thread: element j of
+// chunk _b is i = _b + threadIdx.x + j kSB. CHUNK_INDEX clamps it to n - 1
+// (ix[j]) and records whether it is real (ok[j]), so every load of a chunk is
+// unconditional and in bounds and all of them issue before the first wait; a
+// branch per element would make the loads wait element by element. Results
+// of clamped elements are discarded (selects, guarded stores), in the same
+// per-thread order as before, so the arithmetic is unchanged.
+#define CHUNKS(n) for (int64_t _b = 0; _b < (n); _b += (int64_t)EPT * kSB)
+#define CHUNK_INDEX(n)                                                 \
+    int64_t ix[EPT];                                                   \
+    bool ok[EPT];                                                      \
+    _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j) {               \
+        const int64_t _i = _b + threadIdx.x + (int64_t)_j * kSB;       \
+        ok[_j] = _i < (n);                                             \
+        ix[_j] = ok[_j] ? _i : (n) - 1;                                \
+    }
+#define FOR_J _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j)
 
 template <typename OpT> constexpr bool kDigits = std::is_same<OpT, int8_t>::value;
 
@@ -73,6 +92,62 @@ __device__ __forceinline__ double uaux(const Work &w, const Col &c, int64_t i) {
     }
 }
 
+// The products of one chunk (elements ix[j]): every slice's loads for all
+// elements issue together.
+template <typename UT, int EPT>
+__device__ __forceinline__ void uval_chunk(const Work &w, const Col &c, const int64_t (&ix)[EPT],
+                                           double (&u)[EPT]) {
+    if constexpr (std::is_same<UT, int64_t>::value) {
+        const int64_t *U = (const int64_t *)w.U + c.off;
+        int64_t s[EPT];
+        FOR_J s[_j] = U[ix[_j]];
+        for (int t = 1; t < w.ksplit; ++t) {
+            const int64_t *Ut = U + (int64_t)t * w.slice;
+            FOR_J s[_j] += Ut[ix[_j]];
+        }
+        FOR_J u[_j] = (double)s[_j] / kMainScale;
+    } else {
+        const UT *U = (const UT *)w.U + c.off;
+        FOR_J u[_j] = to_f64<UT>(U[ix[_j]]);
+        for (int t = 1; t < w.ksplit; ++t) {
+            const UT *Ut = U + (int64_t)t * w.slice;
+            FOR_J u[_j] += to_f64<UT>(Ut[ix[_j]]);
+        }
+    }
+}
+
+template <typename UT, int EPT>
+__device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const int64_t (&ix)[EPT],
+                                           double (&u)[EPT]) {
+    if constexpr (std::is_same<UT, int64_t>::value) {
+        const int64_t *H = (const int64_t *)w.U_aux + c.off, *L = w.U_lo + c.off;
+        int64_t hi[EPT], lo[EPT];
+        FOR_J {
+            hi[_j] = H[ix[_j]];
+            lo[_j] = L[ix[_j]];
+        }
+        for (int t = 1; t < w.ksplit_aux; ++t) {
+            const int64_t *Ht = H + (int64_t)t * w.slice_aux, *Lt = L + (int64_t)t * w.slice_aux;
+            FOR_J {
+                hi[_j] += Ht[ix[_j]];
+                lo[_j] += Lt[ix[_j]];
+            }
+        }
+        FOR_J u[_j] = digits8_value(hi[_j], lo[_j], c.escale);
+    } else {
+        if (!w.split) {
+            uval_chunk<UT, EPT>(w, c, ix, u);
+            return;
+        }
+        const double *U = w.U_aux + c.off;
+        FOR_J u[_j] = U[ix[_j]];
+        for (int t = 1; t < w.ksplit_aux; ++t) {
+            const double *Ut = U + (int64_t)t * w.slice_aux;
+            FOR_J u[_j] += Ut[ix[_j]];
+        }
+    }
+}
+
 // Next operand of a lambda_min / CG column. The integer path keeps the FP64
 // value; its digits follow in aux_digits once the column's largest
 // magnitude is known.
@@ -102,7 +177,12 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs)
         const int64_t n = c.n;
         const double *src = w.op_aux + c.off;
         int8_t *dst = w.dig_aux + (int64_t)c.id * 8 * c.ld;
-        FOR_I(n) put_digits8(dst, c.ld, i, src[i], e);
+        CHUNKS(n) {
+            CHUNK_INDEX(n)
+            double v[EPT];
+            FOR_J v[_j] = src[ix[_j]];
+            FOR_J if (ok[_j]) put_digits8(dst, c.ld, ix[_j], v[_j], e);
+        }
         __syncthreads();  // every thread has read c.escale for this sweep
         if (threadIdx.x == 0) c.escale = e;
     }
@@ -128,17 +208,28 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
     const double *b = w.b + in.off, *gam = w.gam + in.off, *R = w.R + in.off, *dq = w.dq + in.off;
     double mx[4] = {0.0, 0.0, 0.0, 0.0};  // binary gap, pinned-at-half flag, row term, |b_r + p|
     double sm[2] = {0.0, 0.0};            // sum of z over I, |I|
-    FOR_I(n) {
-        const double xi = x[i];
-        mx[0] = fmax(mx[0], fmin(xi, 1.0 - xi));
-        if (fabs(xi - 0.5) < 1e-9) mx[1] = 1.0;
-        if (interior(xi)) {
-            sm[0] += xi - xi * xi;
-            sm[1] += 1.0;
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], Av[EPT], Rv[EPT], bv[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = x[i];
+            Av[_j] = (dq[i] + gam[i]) - p[i];
+            Rv[_j] = R[i];
+            bv[_j] = (b[i] - gam[i]) + p[i];
         }
-        const double A = (dq[i] + gam[i]) - p[i];
-        mx[2] = fmax(mx[2], 2.0 * (R[i] + fabs(A)));
-        mx[3] = fmax(mx[3], fabs((b[i] - gam[i]) + p[i]));
+        FOR_J {
+            if (!ok[_j]) continue;
+            const double xi = xv[_j];
+            mx[0] = fmax(mx[0], fmin(xi, 1.0 - xi));
+            if (fabs(xi - 0.5) < 1e-9) mx[1] = 1.0;
+            if (interior(xi)) {
+                sm[0] += xi - xi * xi;
+                sm[1] += 1.0;
+            }
+            mx[2] = fmax(mx[2], 2.0 * (Rv[_j] + fabs(Av[_j])));
+            mx[3] = fmax(mx[3], fabs(bv[_j]));
+        }
     }
     block_maxsum<4, 2, kSB>(mx, sm, red);
     const double rho = fmax(1.0, fmax(mx[2], mx[3]));
@@ -164,10 +255,16 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
     // first LOBPCG vector: constant on I, normalized in the Z inner product
     const double v0 = 1.0 / sqrt(sm[0]);
     double *v = w.v + c.off;
-    FOR_I(n) {
-        const double vi = interior(x[i]) ? v0 : 0.0;
-        v[i] = vi;
-        put_aux<OpT>(w, c, i, vi);
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT];
+        FOR_J xv[_j] = x[ix[_j]];
+        FOR_J {
+            if (!ok[_j]) continue;
+            const double vi = interior(xv[_j]) ? v0 : 0.0;
+            v[ix[_j]] = vi;
+            put_aux<OpT>(w, c, ix[_j], vi);
+        }
     }
     aux_digits<OpT, EPT>(w, c, v0);
 }
@@ -184,17 +281,31 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
     const double *b = w.b + in.off, *gam = w.gam + in.off, *R = w.R + in.off, *dq = w.dq + in.off;
     const double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
     double mx[2] = {0.0, 0.0};
-    FOR_I(n) {
-        const double xi = x[i];
-        double pi = p[i];
-        if (interior(xi)) {
-            pi = pi + alpha * (xi - xi * xi);
-            p[i] = pi;
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], pv[EPT], dg[EPT], Rv[EPT], bg[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = x[i];
+            pv[_j] = p[i];
+            dg[_j] = dq[i] + gam[i];
+            Rv[_j] = R[i];
+            bg[_j] = b[i] - gam[i];
         }
-        const double A = (dq[i] + gam[i]) - pi;
-        mx[0] = fmax(mx[0], 2.0 * (R[i] + fabs(A)));
-        mx[1] = fmax(mx[1], fabs((b[i] - gam[i]) + pi));
-        put_main<OpT>(w, c, i, xi);
+        FOR_J {
+            if (!ok[_j]) continue;
+            const int64_t i = ix[_j];
+            const double xi = xv[_j];
+            double pi = pv[_j];
+            if (interior(xi)) {
+                pi = pi + alpha * (xi - xi * xi);
+                p[i] = pi;
+            }
+            const double A = dg[_j] - pi;
+            mx[0] = fmax(mx[0], 2.0 * (Rv[_j] + fabs(A)));
+            mx[1] = fmax(mx[1], fabs(bg[_j] + pi));
+            put_main<OpT>(w, c, i, xi);
+        }
     }
     bmax<2>(mx, red);
     if (threadIdx.x == 0) {
@@ -245,29 +356,41 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
     double mx[2] = {0.0, 0.0};       // cret, any nonzero step component
     double sm[3] = {0.0, 0.0, 0.0};  // s's, s'y, y'y
     double xr[EPT], gr[EPT];         // register copies when one pass covers the column
-    FOR_I(n) {
-        const double xi = x[i];
-        const double A = (dq[i] + gam[i]) - p[i];
-        const double bbar = (b[i] - gam[i]) + p[i];
-        const double gi = 2.0 * (uval<UT>(w, c, i) + A * xi) + bbar;
-        if (CACHE) {
-            xr[_j] = xi;
-            gr[_j] = gi;
-        } else {
-            g[i] = gi;
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], Av[EPT], bv[EPT], xpv[EPT], gpv[EPT], u[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = x[i];
+            Av[_j] = (dq[i] + gam[i]) - p[i];
+            bv[_j] = (b[i] - gam[i]) + p[i];
+            xpv[_j] = xp[i];  // stale but unused when k == 0
+            gpv[_j] = gp[i];
         }
-        double viol;
-        if (interior(xi)) viol = fabs(gi);
-        else if (xi == 0.0) viol = fmax(-gi, 0.0);
-        else viol = fmax(gi, 0.0);
-        mx[0] = fmax(mx[0], viol);
-        if (k > 0) {
-            const double s = xi - xp[i];
-            const double y = gi - gp[i];
-            sm[0] += s * s;
-            sm[1] += s * y;
-            sm[2] += y * y;
-            if (s != 0.0) mx[1] = 1.0;
+        uval_chunk<UT, EPT>(w, c, ix, u);
+        FOR_J {
+            const double xi = xv[_j];
+            const double gi = 2.0 * (u[_j] + Av[_j] * xi) + bv[_j];
+            if (CACHE) {
+                xr[_j] = xi;
+                gr[_j] = gi;
+            } else if (ok[_j]) {
+                g[ix[_j]] = gi;
+            }
+            if (!ok[_j]) continue;
+            double viol;
+            if (interior(xi)) viol = fabs(gi);
+            else if (xi == 0.0) viol = fmax(-gi, 0.0);
+            else viol = fmax(gi, 0.0);
+            mx[0] = fmax(mx[0], viol);
+            if (k > 0) {
+                const double s = xi - xpv[_j];
+                const double y = gi - gpv[_j];
+                sm[0] += s * s;
+                sm[1] += s * y;
+                sm[2] += y * y;
+                if (s != 0.0) mx[1] = 1.0;
+            }
         }
     }
     block_maxsum<2, 3, kSB>(mx, sm, red);  // sm is zero when k == 0
@@ -297,20 +420,28 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
             alpha = fmin(fmax(a, w.alpha_min), w.alpha_max);
         }
     }
-    FOR_I(n) {
-        const double xi = CACHE ? xr[_j] : x[i];
-        const double gi = CACHE ? gr[_j] : g[i];
-        double xn;
-        if (w.inner == PSDP_INNER_PABB) {
-            xn = fmin(fmax(xi - alpha * gi, 0.0), 1.0);
-        } else {
-            const double hp = fmax((R[i] + fabs(dq[i] + gam[i])) - p[i], w.eps_hp);
-            xn = fmin(fmax(xi + (-gi / (2.0 * hp)), 0.0), 1.0);
+    const bool pabb = w.inner == PSDP_INNER_PABB;
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], gv[EPT], hp[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = CACHE ? xr[_j] : x[i];
+            gv[_j] = CACHE ? gr[_j] : g[i];
+            if (!pabb) hp[_j] = fmax((R[i] + fabs(dq[i] + gam[i])) - p[i], w.eps_hp);
         }
-        xp[i] = xi;
-        gp[i] = gi;
-        x[i] = xn;
-        put_main<OpT>(w, c, i, xn);
+        FOR_J {
+            if (!ok[_j]) continue;
+            const int64_t i = ix[_j];
+            const double xi = xv[_j], gi = gv[_j];
+            double xn;
+            if (pabb) xn = fmin(fmax(xi - alpha * gi, 0.0), 1.0);
+            else xn = fmin(fmax(xi + (-gi / (2.0 * hp[_j])), 0.0), 1.0);
+            xp[i] = xi;
+            gp[i] = gi;
+            x[i] = xn;
+            put_main<OpT>(w, c, i, xn);
+        }
     }
     if (k + 1 >= w.max_inner) {
         __syncthreads();
@@ -468,33 +599,57 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
     const double *gam = w.gam + in.off, *dq = w.dq + in.off;
     double *v = w.v + c.off, *Av = w.Av + c.off, *wv = w.w + c.off;
     double sm[2] = {0.0, 0.0};  // v'Av, v'Zv
-    FOR_I(n) {
-        const double xi = x[i];
-        double av = 0.0;
-        if (interior(xi)) {
-            const double A = (dq[i] + gam[i]) - p[i];
-            av = uaux<UT>(w, c, i) + A * v[i];
-            sm[0] += v[i] * av;
-            sm[1] += (xi - xi * xi) * v[i] * v[i];
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], Ad[EPT], vv[EPT], u[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = x[i];
+            Ad[_j] = (dq[i] + gam[i]) - p[i];
+            vv[_j] = v[i];
         }
-        Av[i] = av;
+        uaux_chunk<UT, EPT>(w, c, ix, u);
+        FOR_J {
+            if (!ok[_j]) continue;
+            const double xi = xv[_j], vi = vv[_j];
+            double av = 0.0;
+            if (interior(xi)) {
+                av = u[_j] + Ad[_j] * vi;
+                sm[0] += vi * av;
+                sm[1] += (xi - xi * xi) * vi * vi;
+            }
+            Av[ix[_j]] = av;
+        }
     }
     bsum<2>(sm, red);
     const double lam = sm[0] / sm[1];
     double rn[1] = {0.0}, mw[1] = {0.0};
-    FOR_I(n) {
-        const double xi = x[i];
-        double wi = 0.0;
-        if (interior(xi)) {
-            const double z = xi - xi * xi;
-            const double A = (dq[i] + gam[i]) - p[i];
-            const double r = Av[i] - lam * z * v[i];
-            rn[0] += r * r / z;
-            wi = r / (A != 0.0 ? fabs(A) : 1.0);
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], Ad[EPT], vv[EPT], av[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = x[i];
+            Ad[_j] = (dq[i] + gam[i]) - p[i];
+            vv[_j] = v[i];
+            av[_j] = Av[i];
         }
-        wv[i] = wi;
-        mw[0] = fmax(mw[0], fabs(wi));
-        put_aux<OpT>(w, c, i, wi);
+        FOR_J {
+            if (!ok[_j]) continue;
+            const int64_t i = ix[_j];
+            const double xi = xv[_j];
+            double wi = 0.0;
+            if (interior(xi)) {
+                const double z = xi - xi * xi;
+                const double A = Ad[_j];
+                const double r = av[_j] - lam * z * vv[_j];
+                rn[0] += r * r / z;
+                wi = r / (A != 0.0 ? fabs(A) : 1.0);
+            }
+            wv[i] = wi;
+            mw[0] = fmax(mw[0], fabs(wi));
+            put_aux<OpT>(w, c, i, wi);
+        }
     }
     block_maxsum<1, 1, kSB>(mw, rn, red);
     if (threadIdx.x == 0) {
@@ -530,42 +685,58 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     for (int j = 0; j < 12; ++j) sm[j] = 0.0;
     // register copies when one pass covers the column (z = 0 marks i outside I)
     double zr[EPT], Ar[EPT], vr[EPT], wr[EPT], awr[EPT], avr[EPT], pr[EPT], apr[EPT];
-    FOR_I(n) {
-        const double xi = x[i];
-        double aw = 0.0;
-        if (CACHE) zr[_j] = 0.0;
-        if (interior(xi)) {
-            const double z = xi - xi * xi;
-            const double A = (dq[i] + gam[i]) - p[i];
-            const double wi = wv[i], vi = v[i];
-            aw = uaux<UT>(w, c, i) + A * wi;
-            if (CACHE) {
-                zr[_j] = z;
-                Ar[_j] = A;
-                vr[_j] = vi;
-                wr[_j] = wi;
-                awr[_j] = aw;
-                avr[_j] = Av[i];
-                pr[_j] = hasP ? P[i] : 0.0;
-                apr[_j] = hasP ? AP[i] : 0.0;
-            }
-            sm[0] += z * vi * vi;
-            sm[1] += z * vi * wi;
-            sm[2] += z * wi * wi;
-            sm[6] += vi * Av[i];
-            sm[7] += vi * aw;
-            sm[8] += wi * aw;
-            if (hasP) {
-                const double pi = P[i];
-                sm[3] += z * vi * pi;
-                sm[4] += z * wi * pi;
-                sm[5] += z * pi * pi;
-                sm[9] += vi * AP[i];
-                sm[10] += wi * AP[i];
-                sm[11] += pi * AP[i];
-            }
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], Ad[EPT], vv[EPT], wvv[EPT], avv[EPT], pv[EPT], apv[EPT], u[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = x[i];
+            Ad[_j] = (dq[i] + gam[i]) - p[i];
+            vv[_j] = v[i];
+            wvv[_j] = wv[i];
+            avv[_j] = Av[i];
+            pv[_j] = hasP ? P[i] : 0.0;
+            apv[_j] = hasP ? AP[i] : 0.0;
         }
-        if (!CACHE) Aw[i] = aw;
+        uaux_chunk<UT, EPT>(w, c, ix, u);
+        FOR_J {
+            const double xi = xv[_j];
+            const bool in_I = ok[_j] && interior(xi);
+            double aw = 0.0;
+            if (CACHE) zr[_j] = 0.0;
+            if (in_I) {
+                const double z = xi - xi * xi;
+                const double A = Ad[_j];
+                const double wi = wvv[_j], vi = vv[_j];
+                aw = u[_j] + A * wi;
+                if (CACHE) {
+                    zr[_j] = z;
+                    Ar[_j] = A;
+                    vr[_j] = vi;
+                    wr[_j] = wi;
+                    awr[_j] = aw;
+                    avr[_j] = avv[_j];
+                    pr[_j] = pv[_j];
+                    apr[_j] = apv[_j];
+                }
+                sm[0] += z * vi * vi;
+                sm[1] += z * vi * wi;
+                sm[2] += z * wi * wi;
+                sm[6] += vi * avv[_j];
+                sm[7] += vi * aw;
+                sm[8] += wi * aw;
+                if (hasP) {
+                    const double pi = pv[_j];
+                    sm[3] += z * vi * pi;
+                    sm[4] += z * wi * pi;
+                    sm[5] += z * pi * pi;
+                    sm[9] += vi * apv[_j];
+                    sm[10] += wi * apv[_j];
+                    sm[11] += pi * apv[_j];
+                }
+            }
+            if (!CACHE && ok[_j]) Aw[ix[_j]] = aw;
+        }
     }
     bsum<12>(sm, red);
     // Rayleigh-Ritz on thread 0; the coefficients go through shared memory
@@ -584,7 +755,25 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     double rn[2] = {0.0, 0.0};  // ||r||^2_{Z^-1}, v'Zv
     double mw[1] = {0.0};       // max |w| (scale of the integer operand)
-    FOR_I(n) {
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], Ad[EPT], vv[EPT], wvv[EPT], awv[EPT], avv[EPT], pv[EPT], apv[EPT];
+        if (!CACHE) {
+            FOR_J {
+                const int64_t i = ix[_j];
+                xv[_j] = x[i];
+                Ad[_j] = (dq[i] + gam[i]) - p[i];
+                vv[_j] = v[i];
+                wvv[_j] = wv[i];
+                awv[_j] = Aw[i];
+                avv[_j] = Av[i];
+                pv[_j] = hasP ? P[i] : 0.0;
+                apv[_j] = hasP ? AP[i] : 0.0;
+            }
+        }
+      FOR_J {
+        if (!ok[_j]) continue;
+        const int64_t i = ix[_j];
         double z, A, vi, wi, awi, avi, pi, api;
         bool in_I;
         if (CACHE) {
@@ -592,13 +781,13 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
             in_I = z > 0.0;  // for 0 < x < 1, x - x*x rounds to a positive double
             A = Ar[_j]; vi = vr[_j]; wi = wr[_j]; awi = awr[_j]; avi = avr[_j]; pi = pr[_j]; api = apr[_j];
         } else {
-            const double xi = x[i];
+            const double xi = xv[_j];
             in_I = interior(xi);
             z = xi - xi * xi;
-            A = (dq[i] + gam[i]) - p[i];
-            vi = v[i]; wi = wv[i]; awi = Aw[i]; avi = Av[i];
-            pi = hasP ? P[i] : 0.0;
-            api = hasP ? AP[i] : 0.0;
+            A = Ad[_j];
+            vi = vv[_j]; wi = wvv[_j]; awi = awv[_j]; avi = avv[_j];
+            pi = pv[_j];
+            api = apv[_j];
         }
         double wn = 0.0;
         if (in_I) {
@@ -618,6 +807,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         wv[i] = wn;
         mw[0] = fmax(mw[0], fabs(wn));
         put_aux<OpT>(w, c, i, wn);
+      }
     }
     block_maxsum<1, 2, kSB>(mw, rn, red);
     const int it = c.it + 1;
@@ -645,21 +835,46 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
     double *r = w.v + c.off, *d = w.w + c.off, *Kd = w.Av + c.off;
     const double *gam = w.gam + in.off, *dq = w.dq + in.off;
     double s1[1] = {0.0};
-    FOR_I(n) {
-        const double kd = 2.0 * (uaux<UT>(w, c, i) + (dq[i] + gam[i]) * d[i]);
-        Kd[i] = kd;
-        s1[0] += d[i] * kd;
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double dg[EPT], dv[EPT], u[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            dg[_j] = dq[i] + gam[i];
+            dv[_j] = d[i];
+        }
+        uaux_chunk<UT, EPT>(w, c, ix, u);
+        FOR_J {
+            if (!ok[_j]) continue;
+            const double kd = 2.0 * (u[_j] + dg[_j] * dv[_j]);
+            Kd[ix[_j]] = kd;
+            s1[0] += dv[_j] * kd;
+        }
     }
     bsum<1>(s1, red);
     const double a = c.rz / s1[0];
     double s2[2] = {0.0, 0.0};  // r'M^-1 r, r'r
-    FOR_I(n) {
-        x[i] = x[i] + a * d[i];
-        const double ri = r[i] - a * Kd[i];
-        r[i] = ri;
-        const double zz = ri / (2.0 * (dq[i] + gam[i]));
-        s2[0] += ri * zz;
-        s2[1] += ri * ri;
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double xv[EPT], dv[EPT], rv[EPT], kv[EPT], dg[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            xv[_j] = x[i];
+            dv[_j] = d[i];
+            rv[_j] = r[i];
+            kv[_j] = Kd[i];
+            dg[_j] = dq[i] + gam[i];
+        }
+        FOR_J {
+            if (!ok[_j]) continue;
+            const int64_t i = ix[_j];
+            x[i] = xv[_j] + a * dv[_j];
+            const double ri = rv[_j] - a * kv[_j];
+            r[i] = ri;
+            const double zz = ri / (2.0 * dg[_j]);
+            s2[0] += ri * zz;
+            s2[1] += ri * ri;
+        }
     }
     bsum<2>(s2, red);
     const int it = c.it + 1;
@@ -674,12 +889,24 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     const double beta = s2[0] / c.rz;
     double md[1] = {0.0};
-    FOR_I(n) {
-        const double zz = r[i] / (2.0 * (dq[i] + gam[i]));
-        const double dn = zz + beta * d[i];
-        d[i] = dn;
-        md[0] = fmax(md[0], fabs(dn));
-        put_aux<OpT>(w, c, i, dn);
+    CHUNKS(n) {
+        CHUNK_INDEX(n)
+        double rv[EPT], dv[EPT], dg[EPT];
+        FOR_J {
+            const int64_t i = ix[_j];
+            rv[_j] = r[i];
+            dv[_j] = d[i];
+            dg[_j] = dq[i] + gam[i];
+        }
+        FOR_J {
+            if (!ok[_j]) continue;
+            const int64_t i = ix[_j];
+            const double zz = rv[_j] / (2.0 * dg[_j]);
+            const double dn = zz + beta * dv[_j];
+            d[i] = dn;
+            md[0] = fmax(md[0], fabs(dn));
+            put_aux<OpT>(w, c, i, dn);
+        }
     }
     if constexpr (kDigits<OpT>) {
         bmax<1>(md, red);
@@ -859,18 +1086,19 @@ static hipError_t step_launch(const Work &w, hipStream_t st) {
     return hipGetLastError();
 }
 
-// EPT elements per thread. When EPT * kSB covers the longest column the
-// subproblem step keeps x and g in registers between its two passes, and for
-// short columns the LOBPCG step keeps its eight vectors there too (beyond
-// two elements per thread they would not fit in the register file).
+// EPT elements per thread and chunk. When one chunk covers the longest
+// column the subproblem step keeps x and g in registers between its two
+// passes, and for short columns the LOBPCG step keeps its eight vectors there
+// too (beyond two elements per thread they would not fit in the register
+// file). Longer columns take several chunks of 4 (6 or more elements per
+// chunk would spill the gathered loads).
 template <typename OpT, typename UT>
 static hipError_t step_ept(const Work &w, int64_t nmax, hipStream_t st) {
     if (nmax <= 1 * kSB) return step_launch<OpT, UT, 1, true, true>(w, st);
     if (nmax <= 2 * kSB) return step_launch<OpT, UT, 2, true, true>(w, st);
     if (nmax <= 4 * kSB) return step_launch<OpT, UT, 4, true, false>(w, st);
     if (nmax <= 6 * kSB) return step_launch<OpT, UT, 6, true, false>(w, st);
-    if (nmax <= 8 * kSB) return step_launch<OpT, UT, 8, true, false>(w, st);
-    return step_launch<OpT, UT, 8, false, false>(w, st);
+    return step_launch<OpT, UT, 4, false, false>(w, st);
 }
 
 hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax, hipStream_t st) {

@@ -35,9 +35,13 @@ def test_plain_solve_bruteforce_set_bit_exact(P, qdt):
         r = P.solve(_t(Q), _t(b), qx_dtype=qdt)
         ref = O.solve(Q, b)
         got = int(r.obj[0].item())
+        st = r.stats[0]
         if got != ref.obj or not np.array_equal(r.xhat.cpu().numpy(), ref.xhat):
             mism.append((seed, got, ref.obj))
-        st = r.stats[0]
+            print(f"mismatch seed {seed}: outer {st['outer_iters']} (oracle {ref.outer_iters}) inner "
+                  f"{st['inner_iters']} (oracle {ref.inner_iters}) aux {st['aux_matvecs']} exit "
+                  f"{st['exit_reason']} sweeps {st['sweeps']} xhat {r.xhat.cpu().numpy().tolist()} "
+                  f"X {np.round(r.X.cpu().numpy(), 6).tolist()}", flush=True)
         assert st["exit_reason"] == ref.exit_reason
     print(f"bruteforce set {qdt}: {len(cases) - len(mism)}/{len(cases)} bit-exact; mismatches {mism}", flush=True)
     assert not mism
