@@ -182,50 +182,52 @@ void fill_work_params(Work &w, const psdp_params &p) {
 }
 
 // Allocates the per-column vectors for `total` doubles of column storage.
-psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, int64_t ld = 0) {
+// Every buffer is cleared on the solve stream: that stream does not wait for
+// the null stream, so a plain hipMemset could land after the first kernels.
+psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, hipStream_t st, int64_t ld = 0) {
     Work &w = S.w;
     double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w};
     for (double **v : vecs) {
         HIPCHK(S.ar.get((void **)v, total * sizeof(double)));
-        HIPCHK(hipMemset(*v, 0, total * sizeof(double)));
+        HIPCHK(hipMemsetAsync(*v, 0, total * sizeof(double), st));
     }
     // integer path: int64 product slices; the operands are digit planes
     const size_t oe = w.i8 ? 0 : esize(S.optype), ue = w.i8 ? sizeof(int64_t) : esize(S.utype);
     if (oe) {
         HIPCHK(S.ar.get(&w.op, total * oe));
-        HIPCHK(hipMemset(w.op, 0, total * oe));
+        HIPCHK(hipMemsetAsync(w.op, 0, total * oe, st));
     }
     w.ksplit = 1;
     w.slice = total;
     HIPCHK(S.ar.get(&w.U, ksplit * total * ue));
-    HIPCHK(hipMemset(w.U, 0, ksplit * total * ue));
+    HIPCHK(hipMemsetAsync(w.U, 0, ksplit * total * ue, st));
     if (w.i8) {
         // one extra all-zero column stands in for the unused rows of a digit tile
         const int64_t pl = (int64_t)(ncol + 1) * ld;
         HIPCHK(S.ar.get((void **)&w.dig, 4 * pl));
-        HIPCHK(hipMemset(w.dig, 0, 4 * pl));
+        HIPCHK(hipMemsetAsync(w.dig, 0, 4 * pl, st));
         HIPCHK(S.ar.get((void **)&w.dig_aux, 8 * pl));
-        HIPCHK(hipMemset(w.dig_aux, 0, 8 * pl));
+        HIPCHK(hipMemsetAsync(w.dig_aux, 0, 8 * pl, st));
         HIPCHK(S.ar.get((void **)&w.U_lo, ksplit * total * sizeof(int64_t)));
-        HIPCHK(hipMemset(w.U_lo, 0, ksplit * total * sizeof(int64_t)));
+        HIPCHK(hipMemsetAsync(w.U_lo, 0, ksplit * total * sizeof(int64_t), st));
     }
     HIPCHK(S.ar.get((void **)&w.active, (ncol + 1) * sizeof(int32_t)));
     HIPCHK(S.ar.get((void **)&w.nactive, 64));
-    HIPCHK(hipMemset(w.nactive, 0, 64));
+    HIPCHK(hipMemsetAsync(w.nactive, 0, 64, st));
     w.nactive_aux = w.nactive + 1;
     HIPCHK(S.ar.get((void **)&S.sweeps, 64));
-    HIPCHK(hipMemset(S.sweeps, 0, 64));
+    HIPCHK(hipMemsetAsync(S.sweeps, 0, 64, st));
     w.sweeps = S.sweeps;
     HIPCHK(S.ar.get((void **)&w.done_count, 64));
-    HIPCHK(hipMemset(w.done_count, 0, 64));
+    HIPCHK(hipMemsetAsync(w.done_count, 0, 64, st));
     w.ncol = ncol;
     if (S.w.split) {
         w.ksplit_aux = 1;
         w.slice_aux = total;
         HIPCHK(S.ar.get((void **)&w.op_aux, total * sizeof(double)));
-        HIPCHK(hipMemset(w.op_aux, 0, total * sizeof(double)));
+        HIPCHK(hipMemsetAsync(w.op_aux, 0, total * sizeof(double), st));
         HIPCHK(S.ar.get((void **)&w.U_aux, ksplit * total * sizeof(double)));
-        HIPCHK(hipMemset(w.U_aux, 0, ksplit * total * sizeof(double)));
+        HIPCHK(hipMemsetAsync(w.U_aux, 0, ksplit * total * sizeof(double), st));
         HIPCHK(S.ar.get((void **)&w.active_aux, (ncol + 1) * sizeof(int32_t)));
     } else {
         w.ksplit_aux = w.ksplit;
@@ -563,7 +565,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
     // column data
     const int kmax = batched ? kMaxSplit : 1;
-    if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, ld)) return s2;
+    if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, st, ld)) return s2;
     const int MT = (int)((ld + 63) / 64);
     // Product kernel per live count (the count comes from the last host poll,
     // so it is an estimate; every kernel covers all B columns regardless):
@@ -708,7 +710,8 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     if (rs != PSDP_OK) return rs;
     if (phase_prof) {
         unsigned long long hp[16];
-        HIPCHK(hipMemcpy(hp, w.phase_prof, sizeof hp, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(hp, w.phase_prof, sizeof hp, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         int rate_khz = 100000;
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, 0);
         const char *nm[5] = {"done", "cg", "eig0", "eig", "inner"};
@@ -829,7 +832,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     w.dq = dq;
     HIPCHK(S.ar.get((void **)&w.inst, count * sizeof(Inst)));
     HIPCHK(hipMemcpyAsync(w.inst, hin.data(), count * sizeof(Inst), hipMemcpyHostToDevice, st));
-    if (psdp_status s2 = alloc_columns(S, total, count, 1)) return s2;
+    if (psdp_status s2 = alloc_columns(S, total, count, 1, st)) return s2;
     std::vector<Col> hcol(count);
     for (int i = 0; i < count; ++i) {
         Col &cc = hcol[i];

@@ -170,8 +170,10 @@ __device__ __forceinline__ void put_main(const Work &w, const Col &c, int64_t i,
 // Integer path: 8 digits of the lambda_min / CG operand just written by
 // put_aux (every thread rereads its own elements), scaled by 2^-e with e the
 // least integer above log2(maxabs). No-op on the floating-point paths.
+// regs: the operand's values when the column is one chunk and use_regs is set.
 template <typename OpT, int EPT>
-__device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs) {
+__device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs, const double (&regs)[EPT],
+                                           bool use_regs) {
     if constexpr (kDigits<OpT>) {
         const int e = digits8_exponent(maxabs);
         const int64_t n = c.n;
@@ -180,12 +182,22 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs)
         CHUNKS(n) {
             CHUNK_INDEX(n)
             double v[EPT];
-            FOR_J v[_j] = src[ix[_j]];
+            if (use_regs) {
+                FOR_J v[_j] = regs[_j];
+            } else {
+                FOR_J v[_j] = src[ix[_j]];
+            }
             FOR_J if (ok[_j]) put_digits8(dst, c.ld, ix[_j], v[_j], e);
         }
         __syncthreads();  // every thread has read c.escale for this sweep
         if (threadIdx.x == 0) c.escale = e;
     }
+}
+
+template <typename OpT, int EPT>
+__device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs) {
+    const double none[EPT] = {};
+    aux_digits<OpT, EPT>(w, c, maxabs, none, false);
 }
 
 __device__ __forceinline__ bool interior(double x) { return x > 0.0 && x < 1.0; }
@@ -576,11 +588,17 @@ __device__ __forceinline__ void rayleigh_ritz(const double *sm, bool hasP, doubl
         jacobi_rot<0, 2>(C, V);
         jacobi_rot<1, 2>(C, V);
     }
-    // smallest eigenpair (lowest index on ties)
-    double theta = C[0][0];
-    double y0 = V[0][0], y1 = V[1][0], y2 = V[2][0];
-    if (C[1][1] < theta) { theta = C[1][1]; y0 = V[0][1]; y1 = V[1][1]; y2 = V[2][1]; }
-    if (C[2][2] < theta) { theta = C[2][2]; y0 = V[0][2]; y1 = V[1][2]; y2 = V[2][2]; }
+    // smallest eigenpair (lowest index on ties), chosen with selects on
+    // scalars (an indexed choice would put V on the stack)
+    const double c0 = C[0][0], c1 = C[1][1], c2 = C[2][2];
+    const bool s1 = c1 < c0;
+    double theta = s1 ? c1 : c0;
+    double y0 = s1 ? V[0][1] : V[0][0], y1 = s1 ? V[1][1] : V[1][0], y2 = s1 ? V[2][1] : V[2][0];
+    const bool s2 = c2 < theta;
+    theta = s2 ? c2 : theta;
+    y0 = s2 ? V[0][2] : y0;
+    y1 = s2 ? V[1][2] : y1;
+    y2 = s2 ? V[2][2] : y2;
     // a = D L^-T y
     out[0] = (Li[0][0] * y0 + Li[1][0] * y1 + Li[2][0] * y2) * d[0];
     out[1] = (Li[1][1] * y1 + Li[2][1] * y2) * d[1];
@@ -740,6 +758,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     bsum<12>(sm, red);
     // Rayleigh-Ritz on thread 0; the coefficients go through shared memory
+    const bool one = n <= (int64_t)EPT * kSB;
     __shared__ double rr[5];  // a0, a1, a2, theta, ok
     if (threadIdx.x == 0) rayleigh_ritz(sm, hasP, rr);
     __syncthreads();
@@ -755,6 +774,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     double rn[2] = {0.0, 0.0};  // ||r||^2_{Z^-1}, v'Zv
     double mw[1] = {0.0};       // max |w| (scale of the integer operand)
+    double wnr[EPT];            // the new operand (one chunk: kept for its digits)
     CHUNKS(n) {
         CHUNK_INDEX(n)
         double xv[EPT], Ad[EPT], vv[EPT], wvv[EPT], awv[EPT], avv[EPT], pv[EPT], apv[EPT];
@@ -805,6 +825,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
             wn = r / (A != 0.0 ? fabs(A) : 1.0);
         }
         wv[i] = wn;
+        wnr[_j] = wn;
         mw[0] = fmax(mw[0], fabs(wn));
         put_aux<OpT>(w, c, i, wn);
       }
@@ -821,7 +842,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     if (sqrt(rn[0] / rn[1]) <= w.eig_tol * fabs(theta) || it >= w.eig_maxit) {
         eig_finish<OpT, EPT>(w, c, in, red, theta);
     } else {
-        aux_digits<OpT, EPT>(w, c, mw[0]);
+        aux_digits<OpT, EPT>(w, c, mw[0], wnr, one);
     }
 }
 
