@@ -260,12 +260,13 @@ void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks) {
 }
 
 // Measured on gfx950: the many-column layout does best with about 512 blocks
-// in the launch and at most 4 slices, the few-column layout with 2 slices
-// unless the launch is already large.
+// in the launch, the few-column layout with 2 slices unless the launch is
+// already large. At most 2 slices in either: the column kernel reads every
+// slice, and more than two cost it a dependent round of loads each.
 int digit_slices(int mt, int blocks_total) {
     blocks_total = std::max(1, blocks_total);
     if (mt <= 1) return std::max(1, std::min(2, (1024 + blocks_total / 2) / blocks_total));
-    return std::max(1, std::min(4, (512 + blocks_total / 2) / blocks_total));
+    return std::max(1, std::min(2, (512 + blocks_total / 2) / blocks_total));
 }
 
 template <typename S1, typename S2>

@@ -99,9 +99,13 @@ __device__ __forceinline__ void uval_chunk(const Work &w, const Col &c, const in
                                            double (&u)[EPT]) {
     if constexpr (std::is_same<UT, int64_t>::value) {
         const int64_t *U = (const int64_t *)w.U + c.off;
-        int64_t s[EPT];
+        int64_t s[EPT], s1[EPT];
         FOR_J s[_j] = U[ix[_j]];
-        for (int t = 1; t < w.ksplit; ++t) {
+        if (w.ksplit > 1) {  // slice 1 loads with slice 0
+            FOR_J s1[_j] = U[w.slice + ix[_j]];
+            FOR_J s[_j] += s1[_j];
+        }
+        for (int t = 2; t < w.ksplit; ++t) {
             const int64_t *Ut = U + (int64_t)t * w.slice;
             FOR_J s[_j] += Ut[ix[_j]];
         }
@@ -121,12 +125,23 @@ __device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const in
                                            double (&u)[EPT]) {
     if constexpr (std::is_same<UT, int64_t>::value) {
         const int64_t *H = (const int64_t *)w.U_aux + c.off, *L = w.U_lo + c.off;
-        int64_t hi[EPT], lo[EPT];
+        int64_t hi[EPT], lo[EPT], hi1[EPT], lo1[EPT];
+        const bool two = w.ksplit_aux > 1;  // slice 1 loads with slice 0
         FOR_J {
             hi[_j] = H[ix[_j]];
             lo[_j] = L[ix[_j]];
         }
-        for (int t = 1; t < w.ksplit_aux; ++t) {
+        if (two) {
+            FOR_J {
+                hi1[_j] = H[w.slice_aux + ix[_j]];
+                lo1[_j] = L[w.slice_aux + ix[_j]];
+            }
+            FOR_J {
+                hi[_j] += hi1[_j];
+                lo[_j] += lo1[_j];
+            }
+        }
+        for (int t = 2; t < w.ksplit_aux; ++t) {
             const int64_t *Ht = H + (int64_t)t * w.slice_aux, *Lt = L + (int64_t)t * w.slice_aux;
             FOR_J {
                 hi[_j] += Ht[ix[_j]];
@@ -189,7 +204,8 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs,
             }
             FOR_J if (ok[_j]) put_digits8(dst, c.ld, ix[_j], v[_j], e);
         }
-        __syncthreads();  // every thread has read c.escale for this sweep
+        // every read of c.escale this sweep (the first pass) precedes the
+        // block reductions that the callers ran since
         if (threadIdx.x == 0) c.escale = e;
     }
 }
