@@ -616,6 +616,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         cc.n = n;
         cc.ld = ld;
         cc.off = (int64_t)c * ld;
+        cc.ioff = 0;
         cc.id = c;
         cc.phase = PH_INNER;  // placeholder, set by the init kernel
     }
@@ -841,6 +842,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         cc.n = n[i];
         cc.ld = ld[i];
         cc.off = off[i];
+        cc.ioff = off[i];
         cc.id = i;
         cc.phase = PH_INNER;
     }

@@ -62,6 +62,8 @@ struct Col {
     int64_t inner_start; // evals at the start of the current subproblem
     int32_t nI;          // |I| of the current penalty update
     int32_t escale;      // integer path: lambda_min / CG operand scaled by 2^-escale
+    int64_t ioff;        // offset of the instance vectors (Inst::off), so that
+                         // the column kernel reads no Inst record
 };
 
 // Flat solver workspace (device pointers), passed to every solver kernel.

@@ -504,7 +504,9 @@ __device__ __forceinline__ bool chol3(const double (&G)[3][3], double (&L)[3][3]
 
 // One Jacobi rotation annihilating C[p][q] (p < q) of a symmetric 3 x 3 C,
 // accumulated into V: t = tan of the angle from the stable quadratic root,
-// c = 1/sqrt(1 + t^2), s = t c.
+// c = 1/sqrt(1 + t^2), s = t c (correctly rounded operations: cheaper
+// estimates move the Ritz values by ulps, which the solve's trajectories
+// amplify).
 template <int PP, int QQ>
 __device__ __forceinline__ void jacobi_rot(double (&C)[3][3], double (&V)[3][3]) {
     const double apq = C[PP][QQ];
@@ -1025,14 +1027,16 @@ template <typename OpT, typename UT, int EPT, bool CI, bool CE>
 __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     const int ci = blockIdx.x;
     __shared__ Col c;
-    __shared__ Inst in;
     __shared__ double red[12 * kSWaves];
     __shared__ int last;
     if (threadIdx.x == 0) c = w.col[ci];
     __syncthreads();
     if (c.phase != PH_DONE) {
-        if (threadIdx.x == 0) in = w.inst[c.inst];
-        __syncthreads();
+        Inst in;  // only the instance offset is used, and the column carries it
+        in.n = c.n;
+        in.ld = c.ld;
+        in.off = c.ioff;
+        in.Qop = nullptr;
         const int ph0 = c.phase;
         const unsigned long long t0 = w.phase_prof ? wall_clock64() : 0ull;
         switch (c.phase) {
@@ -1073,13 +1077,14 @@ template <typename OpT, int EPT>
 __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *X0, int use_cg) {
     const int ci = blockIdx.x;
     __shared__ Col c;
-    __shared__ Inst in;
     __shared__ double red[12 * kSWaves];
-    if (threadIdx.x == 0) {
-        c = w.col[ci];
-        in = w.inst[c.inst];
-    }
+    if (threadIdx.x == 0) c = w.col[ci];
     __syncthreads();
+    Inst in;
+    in.n = c.n;
+    in.ld = c.ld;
+    in.off = c.ioff;
+    in.Qop = nullptr;
     const int64_t n = c.n;
     double *x = w.x + c.off;
     if (!use_cg) {
