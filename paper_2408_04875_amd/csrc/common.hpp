@@ -337,7 +337,7 @@ struct DigitJob {
     int64_t slice;
     int zero_col;            // index of the all-zero column
     int ks;                  // K slices (1..8)
-    int mt;                  // 16-row digit tiles per wave (1, 2 or 4)
+    int mt;                  // block layout: 1 few columns, 2 middle, 4 many (digit_layout)
     int est;                 // live count the grid is sized for (0: no launch)
 };
 constexpr int kDigitRowsAlign = 256;  // Q8 rows are allocated up to a multiple of this

@@ -55,9 +55,10 @@ struct DigitArgs {
 //    slice of one 32-row block into 4 parts and wave 0 adds the parts from
 //    LDS, so that even one column keeps many blocks busy without many output
 //    slices;
-//  many columns (DigitLdsShape MT = 8, NT = 2, below): the digit tile is
-//    shared through LDS; 1.4-1.7x faster than the register-only layout
-//    (MT = 4, NT = 4) with 40 to 256 live columns.
+//  more columns (DigitLdsShape, below): the digit tile is shared through
+//    LDS; MT = 4, NT = 1 (64-row blocks) up to about 48 live columns, then
+//    MT = 8, NT = 2 (128-row blocks); 1.2-1.7x faster than register-only
+//    layouts from 8 to 256 live columns.
 // UNR K steps of 64 per register stage; two stages alternate so that the
 // loads of the next stage are in flight while the current one multiplies.
 template <int MT, int NT, int WK, int UNR> struct DigitShape {
@@ -314,7 +315,17 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
     }
 }
 
+typedef DigitLdsShape<4, 1> DigitMid;
 typedef DigitLdsShape<8, 2> DigitMany;
+
+// DigitJob.mt codes of the three layouts
+constexpr int kLayoutFew = 1, kLayoutMid = 2, kLayoutMany = 4;
+static int layout_ca(int mt, int D) {
+    return 16 * (mt <= kLayoutFew ? DigitFew::kMT : mt == kLayoutMid ? DigitMid::kMT : DigitMany::kMT) / D;
+}
+static int layout_rows(int mt) {
+    return mt <= kLayoutFew ? DigitFew::kRows : mt == kLayoutMid ? DigitMid::kRows : DigitMany::kRows;
+}
 
 template <int D, typename S> struct DigitBody {
     static __device__ __forceinline__ void run(const DigitArgs &da, int L) { digit_body<D, S>(da, L); }
@@ -338,13 +349,12 @@ __global__ void __launch_bounds__(kBlock) digit_kernel(DigitArgs a, DigitArgs b,
     else DigitBody<8, S2>::run(b, xcd_order(bx - nb1, nb2));
 }
 
-// j.mt selects the layout: 1 = few columns (DigitFew), otherwise DigitMany.
+// j.mt selects the layout (kLayoutFew, kLayoutMid, kLayoutMany).
 static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob &j, int D,
                             int *nb) {
     DigitArgs a{};
-    const bool few = j.mt <= 1;
-    const int CA = 16 * (few ? DigitFew::kMT : DigitMany::kMT) / D;
-    const int rows = few ? DigitFew::kRows : DigitMany::kRows;
+    const int CA = layout_ca(j.mt, D);
+    const int rows = layout_rows(j.mt);
     const int ks = std::max(1, std::min(8, j.ks));
     int64_t kc = (ldq + ks - 1) / ks;
     kc = (kc + 63) / 64 * 64;
@@ -368,11 +378,12 @@ static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t
     return a;
 }
 
+// The estimate is the last polled live count plus 16: 20 means at most 4
+// live columns, 64 at most 48.
 void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks) {
-    const bool few = est <= 32;
-    const int CA = 16 * (few ? DigitFew::kMT : DigitMany::kMT) / D;
-    const int rows = few ? DigitFew::kRows : DigitMany::kRows;
-    *mt = few ? 1 : 4;
+    *mt = est <= 20 ? kLayoutFew : est <= 64 ? kLayoutMid : kLayoutMany;
+    const int CA = layout_ca(*mt, D);
+    const int rows = layout_rows(*mt);
     *blocks = std::max(1, (est + CA - 1) / CA) * (int)((ldq + rows - 1) / rows);
 }
 
@@ -382,7 +393,7 @@ void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks) {
 // slice, and more than two cost it a dependent round of loads each.
 int digit_slices(int mt, int blocks_total) {
     blocks_total = std::max(1, blocks_total);
-    if (mt <= 1) return std::max(1, std::min(2, (1024 + blocks_total / 2) / blocks_total));
+    if (mt <= kLayoutFew) return std::max(1, std::min(2, (1024 + blocks_total / 2) / blocks_total));
     return std::max(1, std::min(2, (512 + blocks_total / 2) / blocks_total));
 }
 
@@ -391,27 +402,32 @@ static void digit_go(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, h
     hipLaunchKernelGGL((digit_kernel<S1, S2>), dim3((unsigned)(nb1 + nb2)), dim3(kBlock), 0, st, a, b, nb1, nb2);
 }
 
+template <typename S1>
+static void digit_go2(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, int l2, hipStream_t st) {
+    if (l2 == kLayoutFew) digit_go<S1, DigitFew>(a, b, nb1, nb2, st);
+    else if (l2 == kLayoutMid) digit_go<S1, DigitMid>(a, b, nb1, nb2, st);
+    else digit_go<S1, DigitMany>(a, b, nb1, nb2, st);
+}
+
 // Either job may be null or have est = 0 (then it is not launched). Rows of
 // Q8 up to a multiple of kDigitRowsAlign must exist (zero past ldq).
 hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob *main4,
                         const DigitJob *aux8, hipStream_t st) {
     if (ldq % 64 != 0 || nrow > ldu || nrow > ldq) return hipErrorInvalidValue;
     DigitArgs a{}, b{};
-    int nb1 = 0, nb2 = 0;
-    bool few1 = true, few2 = true;
+    int nb1 = 0, nb2 = 0, l1 = kLayoutFew, l2 = kLayoutFew;
     if (main4 && main4->est > 0) {
         a = digit_args(Q8, ldq, nrow, ldu, *main4, 4, &nb1);
-        few1 = main4->mt <= 1;
+        l1 = main4->mt <= kLayoutFew ? kLayoutFew : main4->mt == kLayoutMid ? kLayoutMid : kLayoutMany;
     }
     if (aux8 && aux8->est > 0) {
         b = digit_args(Q8, ldq, nrow, ldu, *aux8, 8, &nb2);
-        few2 = aux8->mt <= 1;
+        l2 = aux8->mt <= kLayoutFew ? kLayoutFew : aux8->mt == kLayoutMid ? kLayoutMid : kLayoutMany;
     }
     if (nb1 + nb2 == 0) return hipSuccess;
-    if (few1 && few2) digit_go<DigitFew, DigitFew>(a, b, nb1, nb2, st);
-    else if (few1) digit_go<DigitFew, DigitMany>(a, b, nb1, nb2, st);
-    else if (few2) digit_go<DigitMany, DigitFew>(a, b, nb1, nb2, st);
-    else digit_go<DigitMany, DigitMany>(a, b, nb1, nb2, st);
+    if (l1 == kLayoutFew) digit_go2<DigitFew>(a, b, nb1, nb2, l2, st);
+    else if (l1 == kLayoutMid) digit_go2<DigitMid>(a, b, nb1, nb2, l2, st);
+    else digit_go2<DigitMany>(a, b, nb1, nb2, l2, st);
     return hipGetLastError();
 }
 
