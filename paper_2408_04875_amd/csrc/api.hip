@@ -142,7 +142,26 @@ struct Solver {
     int optype = PSDP_F64, utype = PSDP_F64;
     int64_t *sweeps = nullptr;
     int64_t nmax = 0;  // largest column length (selects the per-thread unroll)
+    // live-list buffers by sweep parity and their counters
+    // (cnt[2 p] main, cnt[2 p + 1] aux)
+    int32_t *act[2] = {nullptr, nullptr}, *act_aux[2] = {nullptr, nullptr};
+    int32_t *cnt = nullptr;
 };
+
+// Points the work record at the lists of a sweep of parity p: the products
+// read the lists of p, the column kernel fills those of 1 - p and clears the
+// counters of p.
+void set_parity(Solver &S, int p) {
+    Work &w = S.w;
+    w.active = S.act[p];
+    w.active_aux = S.act_aux[p];
+    w.nactive = S.cnt + 2 * p;
+    w.nactive_aux = w.nactive + 1;
+    w.next_active = S.act[1 - p];
+    w.next_active_aux = S.act_aux[1 - p];
+    w.next_cnt = S.cnt + 2 * (1 - p);
+    w.clear_cnt = S.cnt + 2 * p;
+}
 
 // One default-priority stream per device for the solve work: the caller's
 // stream may be the null stream, which cannot be captured into a graph.
@@ -211,15 +230,12 @@ psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, hi
         HIPCHK(S.ar.get((void **)&w.U_lo, ksplit * total * sizeof(int64_t)));
         HIPCHK(hipMemsetAsync(w.U_lo, 0, ksplit * total * sizeof(int64_t), st));
     }
-    HIPCHK(S.ar.get((void **)&w.active, (ncol + 1) * sizeof(int32_t)));
-    HIPCHK(S.ar.get((void **)&w.nactive, 64));
-    HIPCHK(hipMemsetAsync(w.nactive, 0, 64, st));
-    w.nactive_aux = w.nactive + 1;
+    for (int p = 0; p < 2; ++p) HIPCHK(S.ar.get((void **)&S.act[p], (ncol + 1) * sizeof(int32_t)));
+    HIPCHK(S.ar.get((void **)&S.cnt, 64));
+    HIPCHK(hipMemsetAsync(S.cnt, 0, 64, st));
     HIPCHK(S.ar.get((void **)&S.sweeps, 64));
     HIPCHK(hipMemsetAsync(S.sweeps, 0, 64, st));
     w.sweeps = S.sweeps;
-    HIPCHK(S.ar.get((void **)&w.done_count, 64));
-    HIPCHK(hipMemsetAsync(w.done_count, 0, 64, st));
     w.ncol = ncol;
     if (S.w.split) {
         w.ksplit_aux = 1;
@@ -228,12 +244,14 @@ psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, hi
         HIPCHK(hipMemsetAsync(w.op_aux, 0, total * sizeof(double), st));
         HIPCHK(S.ar.get((void **)&w.U_aux, ksplit * total * sizeof(double)));
         HIPCHK(hipMemsetAsync(w.U_aux, 0, ksplit * total * sizeof(double), st));
-        HIPCHK(S.ar.get((void **)&w.active_aux, (ncol + 1) * sizeof(int32_t)));
+        for (int p = 0; p < 2; ++p) HIPCHK(S.ar.get((void **)&S.act_aux[p], (ncol + 1) * sizeof(int32_t)));
     } else {
         w.ksplit_aux = w.ksplit;
         w.slice_aux = w.slice;
-        w.active_aux = w.active;
+        S.act_aux[0] = S.act[0];
+        S.act_aux[1] = S.act[1];
     }
+    set_parity(S, 0);
     return PSDP_OK;
 }
 
@@ -318,8 +336,10 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
             for (auto &kv : *m) (void)hipGraphExecDestroy(kv.second);
         }
     } xf{&execs};
+    // sweep s reads the lists of parity s % 2 (the initial lists are parity 0)
     auto enqueue_sweeps = [&](int nb) -> hipError_t {
         for (int q = 0; q < nb; ++q) {
+            set_parity(S, (int)((done_sweeps + q) & 1));
             hipError_t e;
             if ((e = tm.begin(st)) != hipSuccess) return e;
             if ((e = apply()) != hipSuccess) return e;
@@ -339,7 +359,7 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
         const int nb = (int)std::min<int64_t>(prm.poll_sweeps, cap - done_sweeps);
         if (nb <= 0) return fail(PSDP_E_DEVICE, "sweep bound exceeded");
         if (graphs && nb == prm.poll_sweeps) {
-            const int64_t key = S.config_key ? S.config_key() : 0;
+            const int64_t key = (S.config_key ? S.config_key() : 0) * 2 + (done_sweeps & 1);
             auto it = execs.find(key);
             if (it == execs.end()) {
                 hipGraph_t g;
@@ -359,6 +379,7 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
             HIPCHK(enqueue_sweeps(nb));
         }
         done_sweeps += nb;
+        set_parity(S, (int)(done_sweeps & 1));  // the lists the next sweep would read
         const int slot = batch & 1;
         HIPCHK(hipMemcpyAsync(host_cnt + 2 * slot, w.nactive, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(evs[slot], st));

@@ -99,7 +99,15 @@ struct Work {
     int8_t *dig;
     int8_t *dig_aux;
     int64_t *U_lo;
-    int32_t *done_count;  // blocks finished in the current sweep (last one compacts)
+    // live lists of the next sweep: the column kernel appends every live
+    // column (slot claimed with an atomic on next_cnt[0] for the main list,
+    // next_cnt[1] for the aux list) and clears clear_cnt[0..1], the counters
+    // of the lists this sweep's products consumed (they are filled again in
+    // the sweep after). The lists alternate between two buffers by sweep.
+    int32_t *next_active;
+    int32_t *next_active_aux;
+    int32_t *next_cnt;
+    int32_t *clear_cnt;
     int64_t *sweeps;      // sweep counter (nullable)
     unsigned long long *phase_prof;  // optional per-phase {sum, count, max} of step ticks
     double *trace;       // per column trace_cap records of 6 doubles, or null
@@ -140,23 +148,27 @@ template <> __device__ __forceinline__ __hip_bfloat16 from_f64<__hip_bfloat16>(d
 // Digit t of element i goes to p[t * plane + i].
 constexpr double kMainScale = 134217728.0;  // 2^27: iterate grid of the 4-digit operand
 constexpr int kAuxBits = 55;                // 8-digit operand: v 2^(55 - e) rounded
-__device__ __forceinline__ void put_digits4(int8_t *p, int64_t plane, int64_t i, int64_t T) {
+// The plane pointers are formed before the element offset is added, so with
+// a uniform p and plane every store takes a scalar base and one 32-bit
+// offset.
+__device__ __forceinline__ void put_digits4(int8_t *p, int64_t plane, uint32_t i, int64_t T) {
     const int64_t d0 = (T + (1ll << 20)) >> 21;
     T -= d0 << 21;
     const int64_t d1 = (T + (1ll << 13)) >> 14;
     T -= d1 << 14;
     const int64_t d2 = (T + (1ll << 6)) >> 7;
     T -= d2 << 7;
+    int8_t *p1 = p + plane, *p2 = p + 2 * plane, *p3 = p + 3 * plane;
     p[i] = (int8_t)d0;
-    p[plane + i] = (int8_t)d1;
-    p[2 * plane + i] = (int8_t)d2;
-    p[3 * plane + i] = (int8_t)T;
+    p1[i] = (int8_t)d1;
+    p2[i] = (int8_t)d2;
+    p3[i] = (int8_t)T;
 }
 
 // Eight digits of v scaled by 2^-e (|v| < 2^e): T = rint(v 2^(55 - e)),
 // split as T = T_hi 2^28 + T_lo with |T_hi|, |T_lo| <= 2^27, each in four
 // digits (planes 0-3 and 4-7).
-__device__ __forceinline__ void put_digits8(int8_t *p, int64_t plane, int64_t i, double v, int e) {
+__device__ __forceinline__ void put_digits8(int8_t *p, int64_t plane, uint32_t i, double v, int e) {
     const int64_t T = __double2ll_rn(ldexp(v, kAuxBits - e));
     const int64_t hi = (T + (1ll << 27)) >> 28;
     put_digits4(p, plane, i, hi);

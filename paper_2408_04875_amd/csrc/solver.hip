@@ -18,20 +18,55 @@
 // 2 (Q_r - Diag p) x + (b_r + p) with b_r = b - gamma.
 //
 // Element loops are unrolled EPT times per thread so that every load of a
-// pass is in flight at once; the last workgroup to finish a sweep rebuilds
-// the live-column lists for the next one.
+// pass is in flight at once; every live column appends itself to the
+// live-column lists of the next sweep.
 #include <type_traits>
 
 #include "common.hpp"
 
 namespace psdp {
 
+// Uniform operands. A column's sizes and offsets are read from its LDS
+// record; passing them through readfirstlane tells the compiler that every
+// lane holds the same value, so the vector base pointers stay in scalar
+// registers and each element costs one 32-bit offset register for all the
+// arrays it touches, instead of a 64-bit address per array.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A column or instance vector: uniform base, elements addressed by a 32-bit
+// byte offset (n <= 65536, so i * 8 never wraps).
+template <typename T>
+struct UVec {
+    T *p;
+    __device__ __forceinline__ T &operator[](uint32_t i) const {
+        return *reinterpret_cast<T *>(reinterpret_cast<char *>(const_cast<typename std::remove_const<T>::type *>(p)) +
+                                      i * (uint32_t)sizeof(T));
+    }
+};
+template <typename T> __device__ __forceinline__ UVec<T> uvec(T *base, int64_t off) { return UVec<T>{base + off}; }
+
+// The uniform facts of a column every pass needs.
+struct ColView {
+    uint32_t n;   // length
+    int64_t off;  // column vector offset
+    int64_t io;   // instance vector offset
+};
+__device__ __forceinline__ ColView view(const Col &c) {
+    return ColView{(uint32_t)uni((int32_t)c.n), uni(c.off), uni(c.ioff)};
+}
+
 // Visits i = threadIdx.x + j * kSB (+ multiples of EPT * kSB) for i < n
 // (set-up code; the per-sweep passes use the chunked form below).
 #define FOR_I(n)                                                       \
-    for (int64_t _b = 0; _b < (n); _b += (int64_t)EPT * kSB)           \
+    for (uint32_t _b = 0; _b < (n); _b += (uint32_t)(EPT * kSB))       \
         _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j)             \
-            if (const int64_t i = _b + threadIdx.x + (int64_t)_j * kSB; i < (n))
+            if (const uint32_t i = _b + threadIdx.x + (uint32_t)(_j * kSB); i < (n))
 
 // Per-sweep passes work on chunks of EPT elements per thread: element j of
 // chunk _b is i = _b + threadIdx.x + j kSB. CHUNK_INDEX clamps it to n - 1
@@ -39,13 +74,15 @@ namespace psdp {
 // unconditional and in bounds and all of them issue before the first wait; a
 // branch per element would make the loads wait element by element. Results
 // of clamped elements are discarded (selects, guarded stores), in the same
-// per-thread order as before, so the arithmetic is unchanged.
-#define CHUNKS(n) for (int64_t _b = 0; _b < (n); _b += (int64_t)EPT * kSB)
+// per-thread order as before, so the arithmetic is unchanged. Every element
+// is read and written by the same thread in every pass of a kernel, so the
+// threads of a block exchange nothing through global memory.
+#define CHUNKS(n) for (uint32_t _b = 0; _b < (n); _b += (uint32_t)(EPT * kSB))
 #define CHUNK_INDEX(n)                                                 \
-    int64_t ix[EPT];                                                   \
+    uint32_t ix[EPT];                                                  \
     bool ok[EPT];                                                      \
     _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j) {               \
-        const int64_t _i = _b + threadIdx.x + (int64_t)_j * kSB;       \
+        const uint32_t _i = _b + threadIdx.x + (uint32_t)(_j * kSB);   \
         ok[_j] = _i < (n);                                             \
         ix[_j] = ok[_j] ? _i : (n) - 1;                                \
     }
@@ -53,78 +90,45 @@ namespace psdp {
 
 template <typename OpT> constexpr bool kDigits = std::is_same<OpT, int8_t>::value;
 
-// Product for a subproblem column, element i.
-template <typename UT>
-__device__ __forceinline__ double uval(const Work &w, const Col &c, int64_t i) {
-    const int64_t idx = c.off + i;
-    if constexpr (std::is_same<UT, int64_t>::value) {
-        // integer path: Q x_q on the grid 2^-27, exact
-        const int64_t *U = (const int64_t *)w.U;
-        int64_t s = U[idx];
-        for (int t = 1; t < w.ksplit; ++t) s += U[(int64_t)t * w.slice + idx];
-        return (double)s / kMainScale;
-    } else {
-        const UT *U = (const UT *)w.U;
-        double s = to_f64<UT>(U[idx]);
-        for (int t = 1; t < w.ksplit; ++t) s += to_f64<UT>(U[(int64_t)t * w.slice + idx]);
-        return s;
-    }
-}
-
-// Product for a lambda_min / CG column (FP64 buffers when precision is split;
-// on the integer path the two int64 halves of the 8-digit product).
-template <typename UT>
-__device__ __forceinline__ double uaux(const Work &w, const Col &c, int64_t i) {
-    const int64_t idx = c.off + i;
-    if constexpr (std::is_same<UT, int64_t>::value) {
-        const int64_t *H = (const int64_t *)w.U_aux;
-        int64_t hi = H[idx], lo = w.U_lo[idx];
-        for (int t = 1; t < w.ksplit_aux; ++t) {
-            hi += H[(int64_t)t * w.slice_aux + idx];
-            lo += w.U_lo[(int64_t)t * w.slice_aux + idx];
-        }
-        return digits8_value(hi, lo, c.escale);
-    } else {
-        if (!w.split) return uval<UT>(w, c, i);
-        double s = w.U_aux[idx];
-        for (int t = 1; t < w.ksplit_aux; ++t) s += w.U_aux[(int64_t)t * w.slice_aux + idx];
-        return s;
-    }
-}
-
-// The products of one chunk (elements ix[j]): every slice's loads for all
-// elements issue together.
+// The products of one chunk (elements ix[j]) for a subproblem column: every
+// slice's loads for all elements issue together. Integer path: Q x_q on the
+// grid 2^-27, exact.
 template <typename UT, int EPT>
-__device__ __forceinline__ void uval_chunk(const Work &w, const Col &c, const int64_t (&ix)[EPT],
+__device__ __forceinline__ void uval_chunk(const Work &w, const ColView &cv, const uint32_t (&ix)[EPT],
                                            double (&u)[EPT]) {
     if constexpr (std::is_same<UT, int64_t>::value) {
-        const int64_t *U = (const int64_t *)w.U + c.off;
+        const UVec<const int64_t> U = uvec((const int64_t *)w.U, cv.off);
         int64_t s[EPT], s1[EPT];
         FOR_J s[_j] = U[ix[_j]];
         if (w.ksplit > 1) {  // slice 1 loads with slice 0
-            FOR_J s1[_j] = U[w.slice + ix[_j]];
+            const UVec<const int64_t> U1 = uvec(U.p, w.slice);
+            FOR_J s1[_j] = U1[ix[_j]];
             FOR_J s[_j] += s1[_j];
         }
         for (int t = 2; t < w.ksplit; ++t) {
-            const int64_t *Ut = U + (int64_t)t * w.slice;
+            const UVec<const int64_t> Ut = uvec(U.p, (int64_t)t * w.slice);
             FOR_J s[_j] += Ut[ix[_j]];
         }
         FOR_J u[_j] = (double)s[_j] / kMainScale;
     } else {
-        const UT *U = (const UT *)w.U + c.off;
+        const UVec<const UT> U = uvec((const UT *)w.U, cv.off);
         FOR_J u[_j] = to_f64<UT>(U[ix[_j]]);
         for (int t = 1; t < w.ksplit; ++t) {
-            const UT *Ut = U + (int64_t)t * w.slice;
+            const UVec<const UT> Ut = uvec(U.p, (int64_t)t * w.slice);
             FOR_J u[_j] += to_f64<UT>(Ut[ix[_j]]);
         }
     }
 }
 
+// The same for a lambda_min / CG column (FP64 buffers when precision is
+// split; on the integer path the two int64 halves of the 8-digit product,
+// scaled by 2^escale).
 template <typename UT, int EPT>
-__device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const int64_t (&ix)[EPT],
-                                           double (&u)[EPT]) {
+__device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const ColView &cv,
+                                           const uint32_t (&ix)[EPT], double (&u)[EPT]) {
     if constexpr (std::is_same<UT, int64_t>::value) {
-        const int64_t *H = (const int64_t *)w.U_aux + c.off, *L = w.U_lo + c.off;
+        const UVec<const int64_t> H = uvec((const int64_t *)w.U_aux, cv.off);
+        const UVec<const int64_t> L = uvec((const int64_t *)w.U_lo, cv.off);
         int64_t hi[EPT], lo[EPT], hi1[EPT], lo1[EPT];
         const bool two = w.ksplit_aux > 1;  // slice 1 loads with slice 0
         FOR_J {
@@ -132,9 +136,10 @@ __device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const in
             lo[_j] = L[ix[_j]];
         }
         if (two) {
+            const UVec<const int64_t> H1 = uvec(H.p, w.slice_aux), L1 = uvec(L.p, w.slice_aux);
             FOR_J {
-                hi1[_j] = H[w.slice_aux + ix[_j]];
-                lo1[_j] = L[w.slice_aux + ix[_j]];
+                hi1[_j] = H1[ix[_j]];
+                lo1[_j] = L1[ix[_j]];
             }
             FOR_J {
                 hi[_j] += hi1[_j];
@@ -142,22 +147,24 @@ __device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const in
             }
         }
         for (int t = 2; t < w.ksplit_aux; ++t) {
-            const int64_t *Ht = H + (int64_t)t * w.slice_aux, *Lt = L + (int64_t)t * w.slice_aux;
+            const UVec<const int64_t> Ht = uvec(H.p, (int64_t)t * w.slice_aux);
+            const UVec<const int64_t> Lt = uvec(L.p, (int64_t)t * w.slice_aux);
             FOR_J {
                 hi[_j] += Ht[ix[_j]];
                 lo[_j] += Lt[ix[_j]];
             }
         }
-        FOR_J u[_j] = digits8_value(hi[_j], lo[_j], c.escale);
+        const int e = uni(c.escale);
+        FOR_J u[_j] = digits8_value(hi[_j], lo[_j], e);
     } else {
         if (!w.split) {
-            uval_chunk<UT, EPT>(w, c, ix, u);
+            uval_chunk<UT, EPT>(w, cv, ix, u);
             return;
         }
-        const double *U = w.U_aux + c.off;
+        const UVec<const double> U = uvec((const double *)w.U_aux, cv.off);
         FOR_J u[_j] = U[ix[_j]];
         for (int t = 1; t < w.ksplit_aux; ++t) {
-            const double *Ut = U + (int64_t)t * w.slice_aux;
+            const UVec<const double> Ut = uvec(U.p, (int64_t)t * w.slice_aux);
             FOR_J u[_j] += Ut[ix[_j]];
         }
     }
@@ -167,19 +174,28 @@ __device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const in
 // value; its digits follow in aux_digits once the column's largest
 // magnitude is known.
 template <typename OpT>
-__device__ __forceinline__ void put_aux(const Work &w, const Col &c, int64_t i, double v) {
-    if (kDigits<OpT> || w.split) w.op_aux[c.off + i] = v;
-    else ((OpT *)w.op)[c.off + i] = from_f64<OpT>(v);
+__device__ __forceinline__ void put_aux(const Work &w, const ColView &cv, uint32_t i, double v) {
+    if (kDigits<OpT> || w.split) uvec(w.op_aux, cv.off)[i] = v;
+    else uvec((OpT *)w.op, cv.off)[i] = from_f64<OpT>(v);
+}
+
+// Digit planes of a column: [4][ld] int8 for the subproblem operand, [8][ld]
+// for the lambda_min / CG operand.
+__device__ __forceinline__ int8_t *main_planes(const Work &w, const Col &c) {
+    return w.dig + (int64_t)uni(c.id) * 4 * uni(c.ld);
+}
+__device__ __forceinline__ int8_t *aux_planes(const Work &w, const Col &c) {
+    return w.dig_aux + (int64_t)uni(c.id) * 8 * uni(c.ld);
 }
 
 // Next operand of a subproblem column (x in [0,1]; the integer path rounds
 // it to the grid 2^-27 and writes its 4 digits).
 template <typename OpT>
-__device__ __forceinline__ void put_main(const Work &w, const Col &c, int64_t i, double v) {
+__device__ __forceinline__ void put_main(const Work &w, const Col &c, const ColView &cv, uint32_t i, double v) {
     if constexpr (kDigits<OpT>)
-        put_digits4(w.dig + (int64_t)c.id * 4 * c.ld, c.ld, i, __double2ll_rn(v * kMainScale));
+        put_digits4(main_planes(w, c), uni(c.ld), i, __double2ll_rn(v * kMainScale));
     else
-        ((OpT *)w.op)[c.off + i] = from_f64<OpT>(v);
+        uvec((OpT *)w.op, cv.off)[i] = from_f64<OpT>(v);
 }
 
 // Integer path: 8 digits of the lambda_min / CG operand just written by
@@ -187,13 +203,14 @@ __device__ __forceinline__ void put_main(const Work &w, const Col &c, int64_t i,
 // least integer above log2(maxabs). No-op on the floating-point paths.
 // regs: the operand's values when the column is one chunk and use_regs is set.
 template <typename OpT, int EPT>
-__device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs, const double (&regs)[EPT],
-                                           bool use_regs) {
+__device__ __forceinline__ void aux_digits(const Work &w, Col &c, const ColView &cv, double maxabs,
+                                           const double (&regs)[EPT], bool use_regs) {
     if constexpr (kDigits<OpT>) {
         const int e = digits8_exponent(maxabs);
-        const int64_t n = c.n;
-        const double *src = w.op_aux + c.off;
-        int8_t *dst = w.dig_aux + (int64_t)c.id * 8 * c.ld;
+        const uint32_t n = cv.n;
+        const UVec<const double> src = uvec((const double *)w.op_aux, cv.off);
+        int8_t *dst = aux_planes(w, c);
+        const int64_t ld = uni(c.ld);
         CHUNKS(n) {
             CHUNK_INDEX(n)
             double v[EPT];
@@ -202,7 +219,7 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs,
             } else {
                 FOR_J v[_j] = src[ix[_j]];
             }
-            FOR_J if (ok[_j]) put_digits8(dst, c.ld, ix[_j], v[_j], e);
+            FOR_J if (ok[_j]) put_digits8(dst, ld, ix[_j], v[_j], e);
         }
         // every read of c.escale this sweep (the first pass) precedes the
         // block reductions that the callers ran since
@@ -211,9 +228,9 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs,
 }
 
 template <typename OpT, int EPT>
-__device__ __forceinline__ void aux_digits(const Work &w, Col &c, double maxabs) {
+__device__ __forceinline__ void aux_digits(const Work &w, Col &c, const ColView &cv, double maxabs) {
     const double none[EPT] = {};
-    aux_digits<OpT, EPT>(w, c, maxabs, none, false);
+    aux_digits<OpT, EPT>(w, c, cv, maxabs, none, false);
 }
 
 __device__ __forceinline__ bool interior(double x) { return x > 0.0 && x < 1.0; }
@@ -229,18 +246,18 @@ template <int N> __device__ __forceinline__ void bmax(double (&v)[N], double *re
 // Outer loop head (Algorithm 3): exit tests, then start lambda_min.
 
 template <typename OpT, int EPT>
-__device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) {
-    const int64_t n = c.n;
-    const double *x = w.x + c.off;
-    const double *p = w.p + c.off;
-    const double *b = w.b + in.off, *gam = w.gam + in.off, *R = w.R + in.off, *dq = w.dq + in.off;
+__device__ void outer_begin(const Work &w, Col &c, const ColView &cv, double *red) {
+    const uint32_t n = cv.n;
+    const UVec<const double> x = uvec((const double *)w.x, cv.off), p = uvec((const double *)w.p, cv.off);
+    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
+    const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
     double mx[4] = {0.0, 0.0, 0.0, 0.0};  // binary gap, pinned-at-half flag, row term, |b_r + p|
     double sm[2] = {0.0, 0.0};            // sum of z over I, |I|
     CHUNKS(n) {
         CHUNK_INDEX(n)
         double xv[EPT], Av[EPT], Rv[EPT], bv[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = x[i];
             Av[_j] = (dq[i] + gam[i]) - p[i];
             Rv[_j] = R[i];
@@ -282,7 +299,7 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
     if (exitr >= 0) return;
     // first LOBPCG vector: constant on I, normalized in the Z inner product
     const double v0 = 1.0 / sqrt(sm[0]);
-    double *v = w.v + c.off;
+    const UVec<double> v = uvec(w.v, cv.off);
     CHUNKS(n) {
         CHUNK_INDEX(n)
         double xv[EPT];
@@ -291,10 +308,10 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
             if (!ok[_j]) continue;
             const double vi = interior(xv[_j]) ? v0 : 0.0;
             v[ix[_j]] = vi;
-            put_aux<OpT>(w, c, ix[_j], vi);
+            put_aux<OpT>(w, cv, ix[_j], vi);
         }
     }
-    aux_digits<OpT, EPT>(w, c, v0);
+    aux_digits<OpT, EPT>(w, c, cv, v0);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,18 +319,19 @@ __device__ void outer_begin(const Work &w, Col &c, const Inst &in, double *red) 
 // (eqs. (pp1), (alpha1)); then the next subproblem starts from the same x.
 
 template <typename OpT, int EPT>
-__device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, double lam) {
-    const int64_t n = c.n;
-    const double *x = w.x + c.off;
-    double *p = w.p + c.off;
-    const double *b = w.b + in.off, *gam = w.gam + in.off, *R = w.R + in.off, *dq = w.dq + in.off;
+__device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red, double lam) {
+    const uint32_t n = cv.n;
+    const UVec<const double> x = uvec((const double *)w.x, cv.off);
+    const UVec<double> p = uvec(w.p, cv.off);
+    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
+    const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
     const double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
     double mx[2] = {0.0, 0.0};
     CHUNKS(n) {
         CHUNK_INDEX(n)
         double xv[EPT], pv[EPT], dg[EPT], Rv[EPT], bg[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = x[i];
             pv[_j] = p[i];
             dg[_j] = dq[i] + gam[i];
@@ -322,7 +340,7 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
         }
         FOR_J {
             if (!ok[_j]) continue;
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             const double xi = xv[_j];
             double pi = pv[_j];
             if (interior(xi)) {
@@ -332,7 +350,7 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
             const double A = dg[_j] - pi;
             mx[0] = fmax(mx[0], 2.0 * (Rv[_j] + fabs(A)));
             mx[1] = fmax(mx[1], fabs(bg[_j] + pi));
-            put_main<OpT>(w, c, i, xi);
+            put_main<OpT>(w, c, cv, i, xi);
         }
     }
     bmax<2>(mx, red);
@@ -351,7 +369,7 @@ __device__ void eig_finish(const Work &w, Col &c, const Inst &in, double *red, d
 // End of a subproblem (Algorithm 3 after line 6).
 
 template <typename OpT, int EPT>
-__device__ void end_subproblem(const Work &w, Col &c, const Inst &in, double *red, int ci,
+__device__ void end_subproblem(const Work &w, Col &c, const ColView &cv, double *red, int ci,
                                bool moved, double rel) {
     if (threadIdx.x == 0) {
         c.stall = moved ? 0 : c.stall + 1;
@@ -368,18 +386,19 @@ __device__ void end_subproblem(const Work &w, Col &c, const Inst &in, double *re
         c.s += 1;
     }
     __syncthreads();
-    outer_begin<OpT, EPT>(w, c, in, red);
+    outer_begin<OpT, EPT>(w, c, cv, red);
 }
 
 // ---------------------------------------------------------------------------
 // Subproblem iteration (Algorithms 1 and 2).
 
 template <typename OpT, typename UT, int EPT, bool CACHE>
-__device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, int ci) {
-    const int64_t n = c.n;
-    double *x = w.x + c.off, *xp = w.xp + c.off, *g = w.g + c.off, *gp = w.gp + c.off;
-    const double *p = w.p + c.off;
-    const double *b = w.b + in.off, *gam = w.gam + in.off, *R = w.R + in.off, *dq = w.dq + in.off;
+__device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red, int ci) {
+    const uint32_t n = cv.n;
+    const UVec<double> x = uvec(w.x, cv.off), xp = uvec(w.xp, cv.off), g = uvec(w.g, cv.off), gp = uvec(w.gp, cv.off);
+    const UVec<const double> p = uvec((const double *)w.p, cv.off);
+    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
+    const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
     const int k = c.k;
     double mx[2] = {0.0, 0.0};       // cret, any nonzero step component
     double sm[3] = {0.0, 0.0, 0.0};  // s's, s'y, y'y
@@ -388,14 +407,14 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
         CHUNK_INDEX(n)
         double xv[EPT], Av[EPT], bv[EPT], xpv[EPT], gpv[EPT], u[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = x[i];
             Av[_j] = (dq[i] + gam[i]) - p[i];
             bv[_j] = (b[i] - gam[i]) + p[i];
             xpv[_j] = xp[i];  // stale but unused when k == 0
             gpv[_j] = gp[i];
         }
-        uval_chunk<UT, EPT>(w, c, ix, u);
+        uval_chunk<UT, EPT>(w, cv, ix, u);
         FOR_J {
             const double xi = xv[_j];
             const double gi = 2.0 * (u[_j] + Av[_j] * xi) + bv[_j];
@@ -429,11 +448,11 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
     }
     __syncthreads();
     if (rel < w.tol_kkt) {
-        end_subproblem<OpT, EPT>(w, c, in, red, ci, k > 0, rel);
+        end_subproblem<OpT, EPT>(w, c, cv, red, ci, k > 0, rel);
         return;
     }
     if (k > 0 && mx[1] == 0.0) {
-        end_subproblem<OpT, EPT>(w, c, in, red, ci, true, rel);
+        end_subproblem<OpT, EPT>(w, c, cv, red, ci, true, rel);
         return;
     }
     double alpha = 0.0;
@@ -453,14 +472,14 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
         CHUNK_INDEX(n)
         double xv[EPT], gv[EPT], hp[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = CACHE ? xr[_j] : x[i];
             gv[_j] = CACHE ? gr[_j] : g[i];
             if (!pabb) hp[_j] = fmax((R[i] + fabs(dq[i] + gam[i])) - p[i], w.eps_hp);
         }
         FOR_J {
             if (!ok[_j]) continue;
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             const double xi = xv[_j], gi = gv[_j];
             double xn;
             if (pabb) xn = fmin(fmax(xi - alpha * gi, 0.0), 1.0);
@@ -468,12 +487,12 @@ __device__ void inner_step(const Work &w, Col &c, const Inst &in, double *red, i
             xp[i] = xi;
             gp[i] = gi;
             x[i] = xn;
-            put_main<OpT>(w, c, i, xn);
+            put_main<OpT>(w, c, cv, i, xn);
         }
     }
     if (k + 1 >= w.max_inner) {
         __syncthreads();
-        end_subproblem<OpT, EPT>(w, c, in, red, ci, true, rel);
+        end_subproblem<OpT, EPT>(w, c, cv, red, ci, true, rel);
         return;
     }
     if (threadIdx.x == 0) c.k = k + 1;
@@ -629,22 +648,22 @@ __device__ __forceinline__ void rayleigh_ritz(const double *sm, bool hasP, doubl
 // lambda_min: first LOBPCG vector applied.
 
 template <typename OpT, typename UT, int EPT>
-__device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
-    const int64_t n = c.n;
-    const double *x = w.x + c.off, *p = w.p + c.off;
-    const double *gam = w.gam + in.off, *dq = w.dq + in.off;
-    double *v = w.v + c.off, *Av = w.Av + c.off, *wv = w.w + c.off;
+__device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red) {
+    const uint32_t n = cv.n;
+    const UVec<const double> x = uvec((const double *)w.x, cv.off), p = uvec((const double *)w.p, cv.off);
+    const UVec<const double> gam = uvec((const double *)w.gam, cv.io), dq = uvec((const double *)w.dq, cv.io);
+    const UVec<double> v = uvec(w.v, cv.off), Av = uvec(w.Av, cv.off), wv = uvec(w.w, cv.off);
     double sm[2] = {0.0, 0.0};  // v'Av, v'Zv
     CHUNKS(n) {
         CHUNK_INDEX(n)
         double xv[EPT], Ad[EPT], vv[EPT], u[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = x[i];
             Ad[_j] = (dq[i] + gam[i]) - p[i];
             vv[_j] = v[i];
         }
-        uaux_chunk<UT, EPT>(w, c, ix, u);
+        uaux_chunk<UT, EPT>(w, c, cv, ix, u);
         FOR_J {
             if (!ok[_j]) continue;
             const double xi = xv[_j], vi = vv[_j];
@@ -664,7 +683,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
         CHUNK_INDEX(n)
         double xv[EPT], Ad[EPT], vv[EPT], av[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = x[i];
             Ad[_j] = (dq[i] + gam[i]) - p[i];
             vv[_j] = v[i];
@@ -672,7 +691,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
         }
         FOR_J {
             if (!ok[_j]) continue;
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             const double xi = xv[_j];
             double wi = 0.0;
             if (interior(xi)) {
@@ -684,7 +703,7 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
             }
             wv[i] = wi;
             mw[0] = fmax(mw[0], fabs(wi));
-            put_aux<OpT>(w, c, i, wi);
+            put_aux<OpT>(w, cv, i, wi);
         }
     }
     block_maxsum<1, 1, kSB>(mw, rn, red);
@@ -696,10 +715,10 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     __syncthreads();
     if (sqrt(rn[0] / sm[1]) <= w.eig_tol * fabs(lam) || w.eig_maxit <= 1) {
-        eig_finish<OpT, EPT>(w, c, in, red, lam);
+        eig_finish<OpT, EPT>(w, c, cv, red, lam);
         return;
     }
-    aux_digits<OpT, EPT>(w, c, mw[0]);
+    aux_digits<OpT, EPT>(w, c, cv, mw[0]);
     if (threadIdx.x == 0) c.phase = PH_EIG;
     __syncthreads();
 }
@@ -708,12 +727,12 @@ __device__ void eig0_step(const Work &w, Col &c, const Inst &in, double *red) {
 // lambda_min: one LOBPCG iteration (Rayleigh-Ritz on span{v, w, P}).
 
 template <typename OpT, typename UT, int EPT, bool CACHE>
-__device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
-    const int64_t n = c.n;
-    const double *x = w.x + c.off, *p = w.p + c.off;
-    const double *gam = w.gam + in.off, *dq = w.dq + in.off;
-    double *v = w.v + c.off, *Av = w.Av + c.off, *P = w.P + c.off, *AP = w.AP + c.off;
-    double *wv = w.w + c.off, *Aw = w.g + c.off;  // g is free during lambda_min
+__device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) {
+    const uint32_t n = cv.n;
+    const UVec<const double> x = uvec((const double *)w.x, cv.off), p = uvec((const double *)w.p, cv.off);
+    const UVec<const double> gam = uvec((const double *)w.gam, cv.io), dq = uvec((const double *)w.dq, cv.io);
+    const UVec<double> v = uvec(w.v, cv.off), Av = uvec(w.Av, cv.off), P = uvec(w.P, cv.off), AP = uvec(w.AP, cv.off);
+    const UVec<double> wv = uvec(w.w, cv.off), Aw = uvec(w.g, cv.off);  // g is free during lambda_min
     const bool hasP = c.hasP != 0;
     // Gram matrices: B = Z-inner products, A = Qbar-inner products
     double sm[12];
@@ -725,7 +744,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         CHUNK_INDEX(n)
         double xv[EPT], Ad[EPT], vv[EPT], wvv[EPT], avv[EPT], pv[EPT], apv[EPT], u[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = x[i];
             Ad[_j] = (dq[i] + gam[i]) - p[i];
             vv[_j] = v[i];
@@ -734,7 +753,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
             pv[_j] = hasP ? P[i] : 0.0;
             apv[_j] = hasP ? AP[i] : 0.0;
         }
-        uaux_chunk<UT, EPT>(w, c, ix, u);
+        uaux_chunk<UT, EPT>(w, c, cv, ix, u);
         FOR_J {
             const double xi = xv[_j];
             const bool in_I = ok[_j] && interior(xi);
@@ -776,7 +795,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     bsum<12>(sm, red);
     // Rayleigh-Ritz on thread 0; the coefficients go through shared memory
-    const bool one = n <= (int64_t)EPT * kSB;
+    const bool one = n <= (uint32_t)(EPT * kSB);
     __shared__ double rr[5];  // a0, a1, a2, theta, ok
     if (threadIdx.x == 0) rayleigh_ritz(sm, hasP, rr);
     __syncthreads();
@@ -787,7 +806,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         // the residual direction is numerically inside span{v}: converged
         if (threadIdx.x == 0) c.aux += 1;
         __syncthreads();
-        eig_finish<OpT, EPT>(w, c, in, red, c.lam);
+        eig_finish<OpT, EPT>(w, c, cv, red, c.lam);
         return;
     }
     double rn[2] = {0.0, 0.0};  // ||r||^2_{Z^-1}, v'Zv
@@ -798,7 +817,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         double xv[EPT], Ad[EPT], vv[EPT], wvv[EPT], awv[EPT], avv[EPT], pv[EPT], apv[EPT];
         if (!CACHE) {
             FOR_J {
-                const int64_t i = ix[_j];
+                const uint32_t i = ix[_j];
                 xv[_j] = x[i];
                 Ad[_j] = (dq[i] + gam[i]) - p[i];
                 vv[_j] = v[i];
@@ -811,7 +830,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         }
       FOR_J {
         if (!ok[_j]) continue;
-        const int64_t i = ix[_j];
+        const uint32_t i = ix[_j];
         double z, A, vi, wi, awi, avi, pi, api;
         bool in_I;
         if (CACHE) {
@@ -845,7 +864,7 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
         wv[i] = wn;
         wnr[_j] = wn;
         mw[0] = fmax(mw[0], fabs(wn));
-        put_aux<OpT>(w, c, i, wn);
+        put_aux<OpT>(w, cv, i, wn);
       }
     }
     block_maxsum<1, 2, kSB>(mw, rn, red);
@@ -858,9 +877,9 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     __syncthreads();
     if (sqrt(rn[0] / rn[1]) <= w.eig_tol * fabs(theta) || it >= w.eig_maxit) {
-        eig_finish<OpT, EPT>(w, c, in, red, theta);
+        eig_finish<OpT, EPT>(w, c, cv, red, theta);
     } else {
-        aux_digits<OpT, EPT>(w, c, mw[0], wnr, one);
+        aux_digits<OpT, EPT>(w, c, cv, mw[0], wnr, one);
     }
 }
 
@@ -868,21 +887,21 @@ __device__ void eig_step(const Work &w, Col &c, const Inst &in, double *red) {
 // x^0 by Jacobi-preconditioned CG on K = 2 (Q + Diag gamma).
 
 template <typename OpT, typename UT, int EPT>
-__device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
-    const int64_t n = c.n;
-    double *x = w.x + c.off;
-    double *r = w.v + c.off, *d = w.w + c.off, *Kd = w.Av + c.off;
-    const double *gam = w.gam + in.off, *dq = w.dq + in.off;
+__device__ void cg_step(const Work &w, Col &c, const ColView &cv, double *red) {
+    const uint32_t n = cv.n;
+    const UVec<double> x = uvec(w.x, cv.off);
+    const UVec<double> r = uvec(w.v, cv.off), d = uvec(w.w, cv.off), Kd = uvec(w.Av, cv.off);
+    const UVec<const double> gam = uvec((const double *)w.gam, cv.io), dq = uvec((const double *)w.dq, cv.io);
     double s1[1] = {0.0};
     CHUNKS(n) {
         CHUNK_INDEX(n)
         double dg[EPT], dv[EPT], u[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             dg[_j] = dq[i] + gam[i];
             dv[_j] = d[i];
         }
-        uaux_chunk<UT, EPT>(w, c, ix, u);
+        uaux_chunk<UT, EPT>(w, c, cv, ix, u);
         FOR_J {
             if (!ok[_j]) continue;
             const double kd = 2.0 * (u[_j] + dg[_j] * dv[_j]);
@@ -897,7 +916,7 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
         CHUNK_INDEX(n)
         double xv[EPT], dv[EPT], rv[EPT], kv[EPT], dg[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             xv[_j] = x[i];
             dv[_j] = d[i];
             rv[_j] = r[i];
@@ -906,7 +925,7 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
         }
         FOR_J {
             if (!ok[_j]) continue;
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             x[i] = xv[_j] + a * dv[_j];
             const double ri = rv[_j] - a * kv[_j];
             r[i] = ri;
@@ -923,7 +942,7 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
     }
     __syncthreads();
     if (sqrt(s2[1]) <= w.cg_tol * c.r0 || it >= w.cg_maxit) {
-        outer_begin<OpT, EPT>(w, c, in, red);
+        outer_begin<OpT, EPT>(w, c, cv, red);
         return;
     }
     const double beta = s2[0] / c.rz;
@@ -932,33 +951,34 @@ __device__ void cg_step(const Work &w, Col &c, const Inst &in, double *red) {
         CHUNK_INDEX(n)
         double rv[EPT], dv[EPT], dg[EPT];
         FOR_J {
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             rv[_j] = r[i];
             dv[_j] = d[i];
             dg[_j] = dq[i] + gam[i];
         }
         FOR_J {
             if (!ok[_j]) continue;
-            const int64_t i = ix[_j];
+            const uint32_t i = ix[_j];
             const double zz = rv[_j] / (2.0 * dg[_j]);
             const double dn = zz + beta * dv[_j];
             d[i] = dn;
             md[0] = fmax(md[0], fabs(dn));
-            put_aux<OpT>(w, c, i, dn);
+            put_aux<OpT>(w, cv, i, dn);
         }
     }
     if constexpr (kDigits<OpT>) {
         bmax<1>(md, red);
-        aux_digits<OpT, EPT>(w, c, md[0]);
+        aux_digits<OpT, EPT>(w, c, cv, md[0]);
     }
     if (threadIdx.x == 0) c.rz = s2[0];
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Live-column lists for the next sweep, in column order. Split precision:
-// `active` gets the subproblem columns and `active_aux` the lambda_min / CG
-// columns; otherwise `active` gets every live column. Run by one block.
+// Live-column lists for the first sweep, in column order (the column kernel
+// builds the later ones). Split precision: `active` gets the subproblem
+// columns and `active_aux` the lambda_min / CG columns; otherwise `active`
+// gets every live column. Run by one block.
 
 template <int NT>
 __device__ void compact_lists(const Work &w) {
@@ -1028,27 +1048,30 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     const int ci = blockIdx.x;
     __shared__ Col c;
     __shared__ double red[12 * kSWaves];
-    __shared__ int last;
     if (threadIdx.x == 0) c = w.col[ci];
     __syncthreads();
-    if (c.phase != PH_DONE) {
-        Inst in;  // only the instance offset is used, and the column carries it
-        in.n = c.n;
-        in.ld = c.ld;
-        in.off = c.ioff;
-        in.Qop = nullptr;
-        const int ph0 = c.phase;
+    const int ph0 = uni(c.phase);
+    if (ph0 != PH_DONE) {
+        const ColView cv = view(c);
         const unsigned long long t0 = w.phase_prof ? wall_clock64() : 0ull;
-        switch (c.phase) {
-            case PH_INNER: inner_step<OpT, UT, EPT, CI>(w, c, in, red, ci); break;
-            case PH_EIG0: eig0_step<OpT, UT, EPT>(w, c, in, red); break;
-            case PH_EIG: eig_step<OpT, UT, EPT, CE>(w, c, in, red); break;
-            case PH_CG: cg_step<OpT, UT, EPT>(w, c, in, red); break;
+        switch (ph0) {
+            case PH_INNER: inner_step<OpT, UT, EPT, CI>(w, c, cv, red, ci); break;
+            case PH_EIG0: eig0_step<OpT, UT, EPT>(w, c, cv, red); break;
+            case PH_EIG: eig_step<OpT, UT, EPT, CE>(w, c, cv, red); break;
+            case PH_CG: cg_step<OpT, UT, EPT>(w, c, cv, red); break;
             default: break;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             w.col[ci] = c;
+            // a live column takes a slot in the next sweep's list; the
+            // products read the lists after this kernel has ended, so the
+            // slots need no ordering with anything else written here
+            if (c.phase != PH_DONE) {
+                const int aux = (w.split && c.phase != PH_INNER) ? 1 : 0;
+                const int slot = atomicAdd(&w.next_cnt[aux], 1);
+                (aux ? w.next_active_aux : w.next_active)[slot] = ci;
+            }
             if (w.phase_prof) {
                 const unsigned long long dt = wall_clock64() - t0;
                 atomicAdd(&w.phase_prof[3 * ph0], dt);
@@ -1057,17 +1080,10 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
             }
         }
     }
-    // the last block of the sweep rebuilds the live lists
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int done = atomicAdd(w.done_count, 1);
-        last = (done == w.ncol - 1);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        compact_lists<kSB>(w);
-        if (threadIdx.x == 0) *w.done_count = 0;
+    if (ci == 0 && threadIdx.x == 0) {
+        w.clear_cnt[0] = 0;
+        w.clear_cnt[1] = 0;
+        if (w.sweeps) *w.sweeps += 1;
     }
 }
 
@@ -1080,20 +1096,17 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
     __shared__ double red[12 * kSWaves];
     if (threadIdx.x == 0) c = w.col[ci];
     __syncthreads();
-    Inst in;
-    in.n = c.n;
-    in.ld = c.ld;
-    in.off = c.ioff;
-    in.Qop = nullptr;
-    const int64_t n = c.n;
-    double *x = w.x + c.off;
+    const ColView cv = view(c);
+    const uint32_t n = cv.n;
+    const UVec<double> x = uvec(w.x, cv.off);
     if (!use_cg) {
         FOR_I(n) x[i] = X0[(int64_t)ci * n + i];
         __syncthreads();
-        outer_begin<OpT, EPT>(w, c, in, red);
+        outer_begin<OpT, EPT>(w, c, cv, red);
     } else {
-        const double *b = w.b + in.off, *gam = w.gam + in.off, *dq = w.dq + in.off;
-        double *r = w.v + c.off, *d = w.w + c.off;
+        const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
+        const UVec<const double> dq = uvec((const double *)w.dq, cv.io);
+        const UVec<double> r = uvec(w.v, cv.off), d = uvec(w.w, cv.off);
         double s[2] = {0.0, 0.0}, mz[1] = {0.0};
         FOR_I(n) {
             x[i] = 0.0;
@@ -1102,12 +1115,12 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
             r[i] = ri;
             d[i] = zz;
             mz[0] = fmax(mz[0], fabs(zz));
-            put_aux<OpT>(w, c, i, zz);
+            put_aux<OpT>(w, cv, i, zz);
             s[0] += ri * zz;
             s[1] += ri * ri;
         }
         block_maxsum<1, 2, kSB>(mz, s, red);
-        aux_digits<OpT, EPT>(w, c, mz[0]);
+        aux_digits<OpT, EPT>(w, c, cv, mz[0]);
         if (threadIdx.x == 0) {
             c.rz = s[0];
             c.r0 = sqrt(s[1]);
