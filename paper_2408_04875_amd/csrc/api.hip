@@ -205,7 +205,7 @@ void fill_work_params(Work &w, const psdp_params &p) {
 // the null stream, so a plain hipMemset could land after the first kernels.
 psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, hipStream_t st, int64_t ld = 0) {
     Work &w = S.w;
-    double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w};
+    double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w, &w.diag, &w.lin, &w.zx};
     for (double **v : vecs) {
         HIPCHK(S.ar.get((void **)v, total * sizeof(double)));
         HIPCHK(hipMemsetAsync(*v, 0, total * sizeof(double), st));

@@ -77,6 +77,11 @@ struct Work {
     double *b, *gam, *R, *dq;
     // column vectors
     double *x, *xp, *g, *gp, *p, *v, *Av, *P, *AP, *w;
+    // per-column terms that change only with p or between subproblems:
+    // diag = (Q_ii + gamma_i) - p_i and lin = (b_i - gamma_i) + p_i (written
+    // at set-up and by every penalty update), zx = x_i - x_i^2 (written at
+    // every outer-loop head, constant while lambda_min runs)
+    double *diag, *lin, *zx;
     void *op;            // operand buffer (OpT), column layout as the vectors
     void *U;             // Q.X output (UT), ksplit slices
     int32_t *active;     // live column list for the next sweep (split: PH_INNER only)

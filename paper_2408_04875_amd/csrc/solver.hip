@@ -248,9 +248,8 @@ template <int N> __device__ __forceinline__ void bmax(double (&v)[N], double *re
 template <typename OpT, int EPT>
 __device__ void outer_begin(const Work &w, Col &c, const ColView &cv, double *red) {
     const uint32_t n = cv.n;
-    const UVec<const double> x = uvec((const double *)w.x, cv.off), p = uvec((const double *)w.p, cv.off);
-    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
-    const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
+    const UVec<const double> x = uvec((const double *)w.x, cv.off), dg = uvec((const double *)w.diag, cv.off);
+    const UVec<const double> ln = uvec((const double *)w.lin, cv.off), R = uvec((const double *)w.R, cv.io);
     double mx[4] = {0.0, 0.0, 0.0, 0.0};  // binary gap, pinned-at-half flag, row term, |b_r + p|
     double sm[2] = {0.0, 0.0};            // sum of z over I, |I|
     CHUNKS(n) {
@@ -259,9 +258,9 @@ __device__ void outer_begin(const Work &w, Col &c, const ColView &cv, double *re
         FOR_J {
             const uint32_t i = ix[_j];
             xv[_j] = x[i];
-            Av[_j] = (dq[i] + gam[i]) - p[i];
+            Av[_j] = dg[i];
             Rv[_j] = R[i];
-            bv[_j] = (b[i] - gam[i]) + p[i];
+            bv[_j] = ln[i];
         }
         FOR_J {
             if (!ok[_j]) continue;
@@ -298,16 +297,20 @@ __device__ void outer_begin(const Work &w, Col &c, const ColView &cv, double *re
     __syncthreads();
     if (exitr >= 0) return;
     // first LOBPCG vector: constant on I, normalized in the Z inner product
+    // z = x - x^2 for lambda_min (positive exactly on I: for 0 < x < 1 it
+    // rounds to a positive double)
     const double v0 = 1.0 / sqrt(sm[0]);
-    const UVec<double> v = uvec(w.v, cv.off);
+    const UVec<double> v = uvec(w.v, cv.off), zx = uvec(w.zx, cv.off);
     CHUNKS(n) {
         CHUNK_INDEX(n)
         double xv[EPT];
         FOR_J xv[_j] = x[ix[_j]];
         FOR_J {
             if (!ok[_j]) continue;
-            const double vi = interior(xv[_j]) ? v0 : 0.0;
+            const double xi = xv[_j];
+            const double vi = interior(xi) ? v0 : 0.0;
             v[ix[_j]] = vi;
+            zx[ix[_j]] = xi - xi * xi;
             put_aux<OpT>(w, cv, ix[_j], vi);
         }
     }
@@ -322,7 +325,7 @@ template <typename OpT, int EPT>
 __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red, double lam) {
     const uint32_t n = cv.n;
     const UVec<const double> x = uvec((const double *)w.x, cv.off);
-    const UVec<double> p = uvec(w.p, cv.off);
+    const UVec<double> p = uvec(w.p, cv.off), dgo = uvec(w.diag, cv.off), lno = uvec(w.lin, cv.off);
     const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
     const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
     const double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
@@ -347,9 +350,11 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
                 pi = pi + alpha * (xi - xi * xi);
                 p[i] = pi;
             }
-            const double A = dg[_j] - pi;
+            const double A = dg[_j] - pi, lb = bg[_j] + pi;
+            dgo[i] = A;
+            lno[i] = lb;
             mx[0] = fmax(mx[0], 2.0 * (Rv[_j] + fabs(A)));
-            mx[1] = fmax(mx[1], fabs(bg[_j] + pi));
+            mx[1] = fmax(mx[1], fabs(lb));
             put_main<OpT>(w, c, cv, i, xi);
         }
     }
@@ -396,9 +401,9 @@ template <typename OpT, typename UT, int EPT, bool CACHE>
 __device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red, int ci) {
     const uint32_t n = cv.n;
     const UVec<double> x = uvec(w.x, cv.off), xp = uvec(w.xp, cv.off), g = uvec(w.g, cv.off), gp = uvec(w.gp, cv.off);
-    const UVec<const double> p = uvec((const double *)w.p, cv.off);
-    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
+    const UVec<const double> p = uvec((const double *)w.p, cv.off), gam = uvec((const double *)w.gam, cv.io);
     const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
+    const UVec<const double> dg = uvec((const double *)w.diag, cv.off), ln = uvec((const double *)w.lin, cv.off);
     const int k = c.k;
     double mx[2] = {0.0, 0.0};       // cret, any nonzero step component
     double sm[3] = {0.0, 0.0, 0.0};  // s's, s'y, y'y
@@ -409,8 +414,8 @@ __device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red
         FOR_J {
             const uint32_t i = ix[_j];
             xv[_j] = x[i];
-            Av[_j] = (dq[i] + gam[i]) - p[i];
-            bv[_j] = (b[i] - gam[i]) + p[i];
+            Av[_j] = dg[i];
+            bv[_j] = ln[i];
             xpv[_j] = xp[i];  // stale but unused when k == 0
             gpv[_j] = gp[i];
         }
@@ -650,28 +655,27 @@ __device__ __forceinline__ void rayleigh_ritz(const double *sm, bool hasP, doubl
 template <typename OpT, typename UT, int EPT>
 __device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red) {
     const uint32_t n = cv.n;
-    const UVec<const double> x = uvec((const double *)w.x, cv.off), p = uvec((const double *)w.p, cv.off);
-    const UVec<const double> gam = uvec((const double *)w.gam, cv.io), dq = uvec((const double *)w.dq, cv.io);
+    const UVec<const double> zx = uvec((const double *)w.zx, cv.off), dg = uvec((const double *)w.diag, cv.off);
     const UVec<double> v = uvec(w.v, cv.off), Av = uvec(w.Av, cv.off), wv = uvec(w.w, cv.off);
     double sm[2] = {0.0, 0.0};  // v'Av, v'Zv
     CHUNKS(n) {
         CHUNK_INDEX(n)
-        double xv[EPT], Ad[EPT], vv[EPT], u[EPT];
+        double zv[EPT], Ad[EPT], vv[EPT], u[EPT];
         FOR_J {
             const uint32_t i = ix[_j];
-            xv[_j] = x[i];
-            Ad[_j] = (dq[i] + gam[i]) - p[i];
+            zv[_j] = zx[i];
+            Ad[_j] = dg[i];
             vv[_j] = v[i];
         }
         uaux_chunk<UT, EPT>(w, c, cv, ix, u);
         FOR_J {
             if (!ok[_j]) continue;
-            const double xi = xv[_j], vi = vv[_j];
+            const double z = zv[_j], vi = vv[_j];
             double av = 0.0;
-            if (interior(xi)) {
+            if (z > 0.0) {  // i in I
                 av = u[_j] + Ad[_j] * vi;
                 sm[0] += vi * av;
-                sm[1] += (xi - xi * xi) * vi * vi;
+                sm[1] += z * vi * vi;
             }
             Av[ix[_j]] = av;
         }
@@ -681,21 +685,20 @@ __device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red)
     double rn[1] = {0.0}, mw[1] = {0.0};
     CHUNKS(n) {
         CHUNK_INDEX(n)
-        double xv[EPT], Ad[EPT], vv[EPT], av[EPT];
+        double zv[EPT], Ad[EPT], vv[EPT], av[EPT];
         FOR_J {
             const uint32_t i = ix[_j];
-            xv[_j] = x[i];
-            Ad[_j] = (dq[i] + gam[i]) - p[i];
+            zv[_j] = zx[i];
+            Ad[_j] = dg[i];
             vv[_j] = v[i];
             av[_j] = Av[i];
         }
         FOR_J {
             if (!ok[_j]) continue;
             const uint32_t i = ix[_j];
-            const double xi = xv[_j];
+            const double z = zv[_j];
             double wi = 0.0;
-            if (interior(xi)) {
-                const double z = xi - xi * xi;
+            if (z > 0.0) {
                 const double A = Ad[_j];
                 const double r = av[_j] - lam * z * vv[_j];
                 rn[0] += r * r / z;
@@ -729,8 +732,7 @@ __device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red)
 template <typename OpT, typename UT, int EPT, bool CACHE>
 __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) {
     const uint32_t n = cv.n;
-    const UVec<const double> x = uvec((const double *)w.x, cv.off), p = uvec((const double *)w.p, cv.off);
-    const UVec<const double> gam = uvec((const double *)w.gam, cv.io), dq = uvec((const double *)w.dq, cv.io);
+    const UVec<const double> zx = uvec((const double *)w.zx, cv.off), dg = uvec((const double *)w.diag, cv.off);
     const UVec<double> v = uvec(w.v, cv.off), Av = uvec(w.Av, cv.off), P = uvec(w.P, cv.off), AP = uvec(w.AP, cv.off);
     const UVec<double> wv = uvec(w.w, cv.off), Aw = uvec(w.g, cv.off);  // g is free during lambda_min
     const bool hasP = c.hasP != 0;
@@ -742,11 +744,11 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
     double zr[EPT], Ar[EPT], vr[EPT], wr[EPT], awr[EPT], avr[EPT], pr[EPT], apr[EPT];
     CHUNKS(n) {
         CHUNK_INDEX(n)
-        double xv[EPT], Ad[EPT], vv[EPT], wvv[EPT], avv[EPT], pv[EPT], apv[EPT], u[EPT];
+        double zv[EPT], Ad[EPT], vv[EPT], wvv[EPT], avv[EPT], pv[EPT], apv[EPT], u[EPT];
         FOR_J {
             const uint32_t i = ix[_j];
-            xv[_j] = x[i];
-            Ad[_j] = (dq[i] + gam[i]) - p[i];
+            zv[_j] = zx[i];
+            Ad[_j] = dg[i];
             vv[_j] = v[i];
             wvv[_j] = wv[i];
             avv[_j] = Av[i];
@@ -755,12 +757,11 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
         }
         uaux_chunk<UT, EPT>(w, c, cv, ix, u);
         FOR_J {
-            const double xi = xv[_j];
-            const bool in_I = ok[_j] && interior(xi);
+            const double z = zv[_j];
+            const bool in_I = ok[_j] && z > 0.0;
             double aw = 0.0;
             if (CACHE) zr[_j] = 0.0;
             if (in_I) {
-                const double z = xi - xi * xi;
                 const double A = Ad[_j];
                 const double wi = wvv[_j], vi = vv[_j];
                 aw = u[_j] + A * wi;
@@ -814,12 +815,12 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
     double wnr[EPT];            // the new operand (one chunk: kept for its digits)
     CHUNKS(n) {
         CHUNK_INDEX(n)
-        double xv[EPT], Ad[EPT], vv[EPT], wvv[EPT], awv[EPT], avv[EPT], pv[EPT], apv[EPT];
+        double zv[EPT], Ad[EPT], vv[EPT], wvv[EPT], awv[EPT], avv[EPT], pv[EPT], apv[EPT];
         if (!CACHE) {
             FOR_J {
                 const uint32_t i = ix[_j];
-                xv[_j] = x[i];
-                Ad[_j] = (dq[i] + gam[i]) - p[i];
+                zv[_j] = zx[i];
+                Ad[_j] = dg[i];
                 vv[_j] = v[i];
                 wvv[_j] = wv[i];
                 awv[_j] = Aw[i];
@@ -835,12 +836,11 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
         bool in_I;
         if (CACHE) {
             z = zr[_j];
-            in_I = z > 0.0;  // for 0 < x < 1, x - x*x rounds to a positive double
+            in_I = z > 0.0;
             A = Ar[_j]; vi = vr[_j]; wi = wr[_j]; awi = awr[_j]; avi = avr[_j]; pi = pr[_j]; api = apr[_j];
         } else {
-            const double xi = xv[_j];
-            in_I = interior(xi);
-            z = xi - xi * xi;
+            z = zv[_j];
+            in_I = z > 0.0;
             A = Ad[_j];
             vi = vv[_j]; wi = wvv[_j]; awi = awv[_j]; avi = avv[_j];
             pi = pv[_j];
@@ -1099,13 +1099,20 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
     const ColView cv = view(c);
     const uint32_t n = cv.n;
     const UVec<double> x = uvec(w.x, cv.off);
+    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
+    const UVec<const double> dq = uvec((const double *)w.dq, cv.io), p = uvec((const double *)w.p, cv.off);
+    {  // the terms of the initial penalty (the same operations as the penalty update)
+        const UVec<double> dg = uvec(w.diag, cv.off), ln = uvec(w.lin, cv.off);
+        FOR_I(n) {
+            dg[i] = (dq[i] + gam[i]) - p[i];
+            ln[i] = (b[i] - gam[i]) + p[i];
+        }
+    }
     if (!use_cg) {
         FOR_I(n) x[i] = X0[(int64_t)ci * n + i];
         __syncthreads();
         outer_begin<OpT, EPT>(w, c, cv, red);
     } else {
-        const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
-        const UVec<const double> dq = uvec((const double *)w.dq, cv.io);
         const UVec<double> r = uvec(w.v, cv.off), d = uvec(w.w, cv.off);
         double s[2] = {0.0, 0.0}, mz[1] = {0.0};
         FOR_I(n) {
