@@ -589,12 +589,15 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, st, ld)) return s2;
     const int MT = (int)((ld + 63) / 64);
     // Product kernel per live count (the count comes from the last host poll,
-    // so it is an estimate; every kernel covers all B columns regardless):
+    // so it is an estimate; every kernel covers all B columns regardless).
+    // Columns move between the two lists from sweep to sweep but never come
+    // back to life, so neither list outgrows the total live count of the
+    // poll: the estimate is the list's count plus 16, at most that total.
     // up to 64 live columns the wave-streaming kernel (needs the FP32 copy of
     // Q), above that the LDS-tiled GEMM with enough split-K for ~512 tiles.
     struct Pick { bool stream; int nt; int ks; int est; };
-    auto pick = [&](int ncols, int gemm_dtype) {
-        Pick pk{false, 4, 1, std::min(B, ncols + 16)};
+    auto pick = [&](int ncols, int live, int gemm_dtype) {
+        Pick pk{false, 4, 1, std::min({B, ncols + 16, live})};
         if (!batched) return pk;
         if (prm.gemm_variant > 0) {
             pk.ks = std::min(kMaxSplit, prm.gemm_variant & 0xff);
@@ -618,15 +621,15 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     Pick8 p8m{}, p8a{};
     auto pick8 = [&](int cm, int ca) {
         int bm = 0, ba = 0;
-        p8m.est = std::min(B, cm + 16);
-        p8a.est = std::min(B, ca + 16);
+        p8m.est = std::min({B, cm + 16, cm + ca});
+        p8a.est = std::min({B, ca + 16, cm + ca});
         digit_layout(p8m.est, 4, ld, &p8m.mt, &bm);
         digit_layout(p8a.est, 8, ld, &p8a.mt, &ba);
         p8m.ks = digit_slices(p8m.mt, bm + ba);
         p8a.ks = digit_slices(p8a.mt, bm + ba);
     };
     pick8(B, B);
-    Pick pm = pick(B, main_gemm), pa = pick(B, aux_gemm);
+    Pick pm = pick(B, B, main_gemm), pa = pick(B, B, aux_gemm);
     w.ksplit = i8 ? p8m.ks : pm.ks;
     w.ksplit_aux = i8 ? p8a.ks : (w.split ? pa.ks : w.ksplit);
     std::vector<Col> hcol(B);
@@ -701,8 +704,8 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
                    ((int64_t)pa.est << 32);
         };
         S.repick = [&](int cm, int ca) {
-            pm = pick(cm, main_gemm);
-            pa = pick(ca, aux_gemm);
+            pm = pick(cm, cm + ca, main_gemm);
+            pa = pick(ca, cm + ca, aux_gemm);
             w.ksplit = pm.ks;
             w.ksplit_aux = w.split ? pa.ks : w.ksplit;
         };
