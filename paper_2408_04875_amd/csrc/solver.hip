@@ -728,9 +728,20 @@ __device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red)
 
 // ---------------------------------------------------------------------------
 // lambda_min: one LOBPCG iteration (Rayleigh-Ritz on span{v, w, P}).
+// CM says where the second pass finds the first pass's values: 0 reloads
+// them, 1 keeps all eight in registers (short columns), 2 keeps z and the
+// diagonal in registers and the other six in LDS (one chunk of up to 3072
+// elements: 144 KB of the 160 KB a workgroup may use).
 
-template <typename OpT, typename UT, int EPT, bool CACHE>
+template <int EPT, int CM> struct EigCache {
+    static constexpr int kSlots = CM == 2 ? EPT * kSB : 1;
+};
+
+template <typename OpT, typename UT, int EPT, int CM>
 __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) {
+    constexpr bool CACHE = CM != 0;
+    constexpr int NS = EigCache<EPT, CM>::kSlots;
+    __shared__ double lc[CM == 2 ? 6 : 1][NS];  // v, w, Aw, Av, P, AP
     const uint32_t n = cv.n;
     const UVec<const double> zx = uvec((const double *)w.zx, cv.off), dg = uvec((const double *)w.diag, cv.off);
     const UVec<double> v = uvec(w.v, cv.off), Av = uvec(w.Av, cv.off), P = uvec(w.P, cv.off), AP = uvec(w.AP, cv.off);
@@ -765,7 +776,7 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
                 const double A = Ad[_j];
                 const double wi = wvv[_j], vi = vv[_j];
                 aw = u[_j] + A * wi;
-                if (CACHE) {
+                if (CM == 1) {
                     zr[_j] = z;
                     Ar[_j] = A;
                     vr[_j] = vi;
@@ -774,6 +785,16 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
                     avr[_j] = avv[_j];
                     pr[_j] = pv[_j];
                     apr[_j] = apv[_j];
+                } else if (CM == 2) {
+                    const int s = _j * kSB + threadIdx.x;
+                    zr[_j] = z;
+                    Ar[_j] = A;
+                    lc[0][s] = vi;
+                    lc[1][s] = wi;
+                    lc[2][s] = aw;
+                    lc[3][s] = avv[_j];
+                    lc[4][s] = pv[_j];
+                    lc[5][s] = apv[_j];
                 }
                 sm[0] += z * vi * vi;
                 sm[1] += z * vi * wi;
@@ -834,10 +855,16 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
         const uint32_t i = ix[_j];
         double z, A, vi, wi, awi, avi, pi, api;
         bool in_I;
-        if (CACHE) {
+        if (CM == 1) {
             z = zr[_j];
             in_I = z > 0.0;
             A = Ar[_j]; vi = vr[_j]; wi = wr[_j]; awi = awr[_j]; avi = avr[_j]; pi = pr[_j]; api = apr[_j];
+        } else if (CM == 2) {
+            const int s = _j * kSB + threadIdx.x;
+            z = zr[_j];
+            in_I = z > 0.0;
+            A = Ar[_j];
+            vi = lc[0][s]; wi = lc[1][s]; awi = lc[2][s]; avi = lc[3][s]; pi = lc[4][s]; api = lc[5][s];
         } else {
             z = zv[_j];
             in_I = z > 0.0;
@@ -1043,7 +1070,7 @@ __device__ void compact_lists(const Work &w) {
 // ---------------------------------------------------------------------------
 // Kernels.
 
-template <typename OpT, typename UT, int EPT, bool CI, bool CE>
+template <typename OpT, typename UT, int EPT, bool CI, int CE>
 __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     const int ci = blockIdx.x;
     __shared__ Col c;
@@ -1142,7 +1169,7 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
 
 __global__ void __launch_bounds__(kSB) compact_kernel(Work w) { compact_lists<kSB>(w); }
 
-template <typename OpT, typename UT, int EPT, bool CI, bool CE>
+template <typename OpT, typename UT, int EPT, bool CI, int CE>
 static hipError_t step_launch(const Work &w, hipStream_t st) {
     hipLaunchKernelGGL((solver_step_kernel<OpT, UT, EPT, CI, CE>), dim3(w.ncol), dim3(kSB), 0, st, w);
     return hipGetLastError();
@@ -1150,17 +1177,17 @@ static hipError_t step_launch(const Work &w, hipStream_t st) {
 
 // EPT elements per thread and chunk. When one chunk covers the longest
 // column the subproblem step keeps x and g in registers between its two
-// passes, and for short columns the LOBPCG step keeps its eight vectors there
-// too (beyond two elements per thread they would not fit in the register
-// file). Longer columns take several chunks of 4 (6 or more elements per
+// passes, and the LOBPCG step keeps its eight vectors for the second pass:
+// in registers for short columns, beyond two elements per thread six of them
+// in LDS. Longer columns take several chunks of 4 (6 or more elements per
 // chunk would spill the gathered loads).
 template <typename OpT, typename UT>
 static hipError_t step_ept(const Work &w, int64_t nmax, hipStream_t st) {
-    if (nmax <= 1 * kSB) return step_launch<OpT, UT, 1, true, true>(w, st);
-    if (nmax <= 2 * kSB) return step_launch<OpT, UT, 2, true, true>(w, st);
-    if (nmax <= 4 * kSB) return step_launch<OpT, UT, 4, true, false>(w, st);
-    if (nmax <= 6 * kSB) return step_launch<OpT, UT, 6, true, false>(w, st);
-    return step_launch<OpT, UT, 4, false, false>(w, st);
+    if (nmax <= 1 * kSB) return step_launch<OpT, UT, 1, true, 1>(w, st);
+    if (nmax <= 2 * kSB) return step_launch<OpT, UT, 2, true, 1>(w, st);
+    if (nmax <= 4 * kSB) return step_launch<OpT, UT, 4, true, 2>(w, st);
+    if (nmax <= 6 * kSB) return step_launch<OpT, UT, 6, true, 2>(w, st);
+    return step_launch<OpT, UT, 4, false, 0>(w, st);
 }
 
 hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax, hipStream_t st) {

@@ -208,3 +208,36 @@ def test_integer_path_batched_invariants_n1000(P):
           flush=True)
     # different rounding, different trajectories: same quality on average (within 1%)
     assert abs(gi.mean() - gf.mean()) <= 0.01 * abs(gf.mean())
+
+
+_DENSE_LAM = {}
+
+
+def _dense_first_lambda(Q, b, x):
+    """lambda_min of eq. (alpha) at x with p = 0, on the oracle's Q_r."""
+    prm = O.Params()
+    n = len(b)
+    Qt = Q.astype(np.float64) + O.perturbation(n, prm.sigma, prm.seed, prm.perturb)
+    gam = O.reformation_gamma(Qt, b.astype(np.float64))
+    return O.lambda_min_scaled(Qt + np.diag(gam), np.zeros(n), x)
+
+
+@pytest.mark.parametrize("n,B,qdt", [(1500, 4, "i8"), (2500, 2, "i8"), (2500, 2, "f64"), (4000, 2, "i8")])
+def test_batched_lobpcg_long_columns_match_dense_eigensolver(P, n, B, qdt):
+    """The first penalty update of each start (x = its own start, p = 0):
+    the batched LOBPCG value agrees with the dense eigensolver. Covers the
+    column kernel's long-column paths (second LOBPCG pass from LDS at 4 and
+    6 elements per thread, several chunks beyond 3072)."""
+    Q, b, X0 = gen.sparse_2500_starts(n=n, B=B)
+    r = P.solve(_t(Q), _t(b), X0=_t(X0), trace_cap=2, max_outer=1, qx_dtype=qdt)
+    _invariants(Q, b, r)
+    for c in range(B):
+        key = (n, c)
+        if key not in _DENSE_LAM:
+            _DENSE_LAM[key] = _dense_first_lambda(Q, b, X0[c])
+        lam, I, _ = _DENSE_LAM[key]
+        got = r.trace[c, 0, 2]
+        print(f"n={n} {qdt} start {c}: lobpcg {got:.12e} dense {lam:.12e} rel {abs(got - lam) / abs(lam):.1e}",
+              flush=True)
+        assert r.trace[c, 0, 1] == I.sum()
+        assert abs(got - lam) <= 1e-5 * abs(lam)
