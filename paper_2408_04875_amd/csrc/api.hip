@@ -585,7 +585,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(S.ar.get((void **)&w.inst, sizeof(Inst)));
     HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
     // column data
-    const int kmax = batched ? kMaxSplit : 1;
+    const int kmax = (batched && !i8) ? kMaxSplit : 1;  // integer slices add into one buffer
     if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, st, ld)) return s2;
     const int MT = (int)((ld + 63) / 64);
     // Product kernel per live count (the count comes from the last host poll,
@@ -630,8 +630,10 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     };
     pick8(B, B);
     Pick pm = pick(B, B, main_gemm), pa = pick(B, B, aux_gemm);
-    w.ksplit = i8 ? p8m.ks : pm.ks;
-    w.ksplit_aux = i8 ? p8a.ks : (w.split ? pa.ks : w.ksplit);
+    // integer path: the column kernel reads one buffer, whatever the
+    // product's K slices
+    w.ksplit = i8 ? 1 : pm.ks;
+    w.ksplit_aux = i8 ? 1 : (w.split ? pa.ks : w.ksplit);
     std::vector<Col> hcol(B);
     for (int c = 0; c < B; ++c) {
         Col &cc = hcol[c];
@@ -668,23 +670,18 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     psdp_status rs;
     if (i8) {
         auto job_main = [&]() {
-            return DigitJob{w.dig, w.active, w.nactive, (int64_t *)w.U, nullptr, w.slice, B,
-                            p8m.ks, p8m.mt, p8m.est};
+            return DigitJob{w.dig, w.active, w.nactive, (int64_t *)w.U, nullptr, B, p8m.ks, p8m.mt, p8m.est};
         };
         auto job_aux = [&]() {
-            return DigitJob{w.dig_aux, w.active_aux, w.nactive_aux, (int64_t *)w.U_aux, w.U_lo, w.slice_aux, B,
-                            p8a.ks, p8a.mt, p8a.est};
+            return DigitJob{w.dig_aux, w.active_aux, w.nactive_aux, (int64_t *)w.U_aux, w.U_lo, B, p8a.ks, p8a.mt,
+                            p8a.est};
         };
         const int8_t *Q8 = (const int8_t *)Qop;
         S.config_key = [&]() {
             return (int64_t)p8m.mt | ((int64_t)p8m.ks << 3) | ((int64_t)p8a.mt << 7) | ((int64_t)p8a.ks << 10) |
                    ((int64_t)p8m.est << 14) | ((int64_t)p8a.est << 34);
         };
-        S.repick = [&](int cm, int ca) {
-            pick8(cm, ca);
-            w.ksplit = p8m.ks;
-            w.ksplit_aux = p8a.ks;
-        };
+        S.repick = [&](int cm, int ca) { pick8(cm, ca); };
         // both products in one launch (timed as one launch when timing = 1)
         rs = run_sweeps(
             S, prm, tm, ta, ts, st,
@@ -1004,18 +1001,23 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     HIPCHK(hipMemsetAsync(dig, 0, (int64_t)(B + 1) * D * ld, st));
     HIPCHK(ar.get((void **)&esc, (int64_t)B * sizeof(int32_t)));
     HIPCHK(launch_digits_from_vectors(X, n, n, B, D, dig, ld, esc, st));
+    // the K slices add into one zeroed product buffer (two for 8 digits)
     const int64_t slice = (int64_t)B * ld;
-    HIPCHK(ar.get((void **)&U0, ks * slice * sizeof(int64_t)));
-    if (D == 8) HIPCHK(ar.get((void **)&U1, ks * slice * sizeof(int64_t)));
+    HIPCHK(ar.get((void **)&U0, slice * sizeof(int64_t)));
+    HIPCHK(hipMemsetAsync(U0, 0, slice * sizeof(int64_t), st));
+    if (D == 8) {
+        HIPCHK(ar.get((void **)&U1, slice * sizeof(int64_t)));
+        HIPCHK(hipMemsetAsync(U1, 0, slice * sizeof(int64_t), st));
+    }
     std::vector<int32_t> iota(B + 1);
     for (int c = 0; c < B; ++c) iota[c] = c;
     iota[B] = B;  // live count
     HIPCHK(ar.get((void **)&act, (B + 1) * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(act, iota.data(), (B + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
     cnt = act + B;
-    const DigitJob job{dig, act, cnt, U0, U1, slice, B, ks, mt, B};
+    const DigitJob job{dig, act, cnt, U0, U1, B, ks, mt, B};
     HIPCHK(launch_digit(Q8, ld, n, ld, D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
-    HIPCHK(launch_digit_combine(U0, U1, slice, ks, n, ld, B, D, esc, Y, st));
+    HIPCHK(launch_digit_combine(U0, U1, n, ld, B, D, esc, Y, st));
     HIPCHK(hipStreamSynchronize(st));
     return PSDP_OK;
 }

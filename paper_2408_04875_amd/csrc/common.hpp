@@ -343,15 +343,16 @@ hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, v
                        const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
                        int ncol_max, hipStream_t st);
 
-// Exact integer products: U[kz][c][i] = sum_k Q8[i][k] T[c][k] over the K
-// slice kz, where T is a column's value in base-128 digits (4 digits, or 8
-// digits whose two 4-digit halves go to U0 and U1).
+// Exact integer products: U[c][i] = sum_k Q8[i][k] T[c][k], where T is a
+// column's value in base-128 digits (4 digits, or 8 digits whose two 4-digit
+// halves go to U0 and U1). With ks > 1 the K slices add their parts with
+// atomic adds, so the live columns' outputs must be zero beforehand; with
+// ks = 1 they are overwritten.
 struct DigitJob {
     const int8_t *dig;       // digit planes [ncol + 1][D][ldq]; column ncol is zero
     const int32_t *active;   // live column list and its device count
     const int32_t *nactive;
-    int64_t *U0, *U1;        // outputs: column stride ldu, slice stride `slice`
-    int64_t slice;
+    int64_t *U0, *U1;        // outputs: column stride ldu
     int zero_col;            // index of the all-zero column
     int ks;                  // K slices (1..8)
     int mt;                  // block layout: 1 few columns, 2 middle, 4 many (digit_layout)
@@ -367,8 +368,8 @@ hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu
                         const DigitJob *aux8, hipStream_t st);
 hipError_t launch_digits_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int8_t *dig,
                                       int64_t ldq, int32_t *escale, hipStream_t st);
-hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t slice, int ks, int64_t n,
-                                int64_t ldu, int B, int D, const int32_t *escale, double *Y, hipStream_t st);
+hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t n, int64_t ldu, int B, int D,
+                                const int32_t *escale, double *Y, hipStream_t st);
 
 // Solver kernels.
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,

@@ -27,8 +27,9 @@
 // columns), one block of rows of Q and one K slice (DigitShape below); the
 // waves read the same digit rows (L1 hits).
 // Blocks are ordered so that the column groups sharing one Q block run on
-// one XCD (one L2). Partial sums are integers, so K slices are exact and
-// the consumer's sum over slices does not depend on their order. The grid
+// one XCD (one L2). Partial sums are integers, so K slices add exactly, in
+// any order, into the one product buffer (atomically when there are several
+// slices; the buffer is then zero beforehand). The grid
 // is sized for an estimate of the live count; blocks loop over further
 // column groups, so the estimate changes only the speed.
 #include <algorithm>
@@ -46,7 +47,7 @@ struct DigitArgs {
     const int32_t *active;
     const int32_t *nactive;
     int64_t *U0, *U1;
-    int64_t ldu, slice, nrow, kchunk;
+    int64_t ldu, nrow, kchunk;
     int AG, IB, KS, zero_col;
 };
 
@@ -72,6 +73,15 @@ __device__ __forceinline__ int64_t combine4(const intx4 &a) {
 }
 
 __device__ __forceinline__ intx4 ld16(const int8_t *p) { return *(const intx4 *)p; }
+
+// A K slice's part of one product element. With one slice it is the
+// product and overwrites the element; with several, every slice adds its
+// part with a 64-bit atomic add (integers: exact and independent of the
+// order), onto an element the consumer has left at zero.
+__device__ __forceinline__ void put_partial(const DigitArgs &da, int64_t *u, int64_t v) {
+    if (da.KS > 1) atomicAdd((unsigned long long *)u, (unsigned long long)v);
+    else *u = v;
+}
 
 template <int D, typename S>
 __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
@@ -198,11 +208,11 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
                 if (slot >= nact) continue;
                 const int64_t c = da.active[slot];
                 int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
-                Uo += (int64_t)kz * da.slice + c * da.ldu;
+                Uo += c * da.ldu;
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     const int64_t i = i0 + 16 * t + m;
-                    if (i < da.nrow) Uo[i] = combine4(acc[s][t]);
+                    if (i < da.nrow) put_partial(da, Uo + i, combine4(acc[s][t]));
                 }
             }
         }
@@ -304,11 +314,11 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
             if (slot >= nact) continue;
             const int64_t c = da.active[slot];
             int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
-            Uo += (int64_t)kz * da.slice + c * da.ldu;
+            Uo += c * da.ldu;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int64_t i = i0 + 16 * t + m;
-                if (i < da.nrow) Uo[i] = combine4(acc[s][t]);
+                if (i < da.nrow) put_partial(da, Uo + i, combine4(acc[s][t]));
             }
         }
         __syncthreads();  // LDS is refilled by the next column group
@@ -366,12 +376,11 @@ static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t
     a.U0 = j.U0;
     a.U1 = j.U1;
     a.ldu = ldu;
-    a.slice = j.slice;
     a.nrow = nrow;
     a.kchunk = kc;
     a.AG = std::max(1, (j.est + CA - 1) / CA);
     a.IB = (int)((ldq + rows - 1) / rows);
-    a.KS = ks;  // a slice with an empty K range writes zeros
+    a.KS = ks;  // a slice with an empty K range adds zeros
     a.zero_col = j.zero_col;
     const int total = a.AG * a.IB * a.KS;
     *nb = (total + 7) / 8 * 8;
@@ -389,8 +398,7 @@ void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks) {
 
 // Measured on gfx950: the many-column layout does best with about 512 blocks
 // in the launch, the few-column layout with 2 slices unless the launch is
-// already large. At most 2 slices in either: the column kernel reads every
-// slice, and more than two cost it a dependent round of loads each.
+// already large. At most 2 slices in either (the range timed on gfx950).
 int digit_slices(int mt, int blocks_total) {
     blocks_total = std::max(1, blocks_total);
     if (mt <= kLayoutFew) return std::max(1, std::min(2, (1024 + blocks_total / 2) / blocks_total));
@@ -467,25 +475,20 @@ hipError_t launch_digits_from_vectors(const double *X, int64_t n, int64_t ldx, i
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(kBlock) digit_combine_kernel(const int64_t *U0, const int64_t *U1, int64_t slice,
-                                                               int ks, int64_t n, int64_t ldu, int D,
-                                                               const int32_t *escale, double *Y) {
+__global__ void __launch_bounds__(kBlock) digit_combine_kernel(const int64_t *U0, const int64_t *U1, int64_t n,
+                                                               int64_t ldu, int D, const int32_t *escale,
+                                                               double *Y) {
     const int64_t c = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int64_t idx = c * ldu + i;
-    int64_t s0 = 0, s1 = 0;
-    for (int t = 0; t < ks; ++t) {
-        s0 += U0[(int64_t)t * slice + idx];
-        if (D == 8) s1 += U1[(int64_t)t * slice + idx];
-    }
-    Y[c * n + i] = D == 4 ? (double)s0 / kMainScale : digits8_value(s0, s1, escale[c]);
+    Y[c * n + i] = D == 4 ? (double)U0[idx] / kMainScale : digits8_value(U0[idx], U1[idx], escale[c]);
 }
 
-hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t slice, int ks, int64_t n,
-                                int64_t ldu, int B, int D, const int32_t *escale, double *Y, hipStream_t st) {
+hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t n, int64_t ldu, int B, int D,
+                                const int32_t *escale, double *Y, hipStream_t st) {
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)B);
-    hipLaunchKernelGGL(digit_combine_kernel, grid, dim3(kBlock), 0, st, U0, U1, slice, ks, n, ldu, D, escale, Y);
+    hipLaunchKernelGGL(digit_combine_kernel, grid, dim3(kBlock), 0, st, U0, U1, n, ldu, D, escale, Y);
     return hipGetLastError();
 }
 

@@ -92,23 +92,16 @@ template <typename OpT> constexpr bool kDigits = std::is_same<OpT, int8_t>::valu
 
 // The products of one chunk (elements ix[j]) for a subproblem column: every
 // slice's loads for all elements issue together. Integer path: Q x_q on the
-// grid 2^-27, exact.
+// grid 2^-27, exact, in one buffer that the product's K slices add into;
+// each real element is cleared once read, for the next product.
 template <typename UT, int EPT>
 __device__ __forceinline__ void uval_chunk(const Work &w, const ColView &cv, const uint32_t (&ix)[EPT],
-                                           double (&u)[EPT]) {
+                                           const bool (&ok)[EPT], double (&u)[EPT]) {
     if constexpr (std::is_same<UT, int64_t>::value) {
-        const UVec<const int64_t> U = uvec((const int64_t *)w.U, cv.off);
-        int64_t s[EPT], s1[EPT];
+        const UVec<int64_t> U = uvec((int64_t *)w.U, cv.off);
+        int64_t s[EPT];
         FOR_J s[_j] = U[ix[_j]];
-        if (w.ksplit > 1) {  // slice 1 loads with slice 0
-            const UVec<const int64_t> U1 = uvec(U.p, w.slice);
-            FOR_J s1[_j] = U1[ix[_j]];
-            FOR_J s[_j] += s1[_j];
-        }
-        for (int t = 2; t < w.ksplit; ++t) {
-            const UVec<const int64_t> Ut = uvec(U.p, (int64_t)t * w.slice);
-            FOR_J s[_j] += Ut[ix[_j]];
-        }
+        FOR_J if (ok[_j]) U[ix[_j]] = 0;
         FOR_J u[_j] = (double)s[_j] / kMainScale;
     } else {
         const UVec<const UT> U = uvec((const UT *)w.U, cv.off);
@@ -125,40 +118,23 @@ __device__ __forceinline__ void uval_chunk(const Work &w, const ColView &cv, con
 // scaled by 2^escale).
 template <typename UT, int EPT>
 __device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const ColView &cv,
-                                           const uint32_t (&ix)[EPT], double (&u)[EPT]) {
+                                           const uint32_t (&ix)[EPT], const bool (&ok)[EPT], double (&u)[EPT]) {
     if constexpr (std::is_same<UT, int64_t>::value) {
-        const UVec<const int64_t> H = uvec((const int64_t *)w.U_aux, cv.off);
-        const UVec<const int64_t> L = uvec((const int64_t *)w.U_lo, cv.off);
-        int64_t hi[EPT], lo[EPT], hi1[EPT], lo1[EPT];
-        const bool two = w.ksplit_aux > 1;  // slice 1 loads with slice 0
+        const UVec<int64_t> H = uvec((int64_t *)w.U_aux, cv.off), L = uvec(w.U_lo, cv.off);
+        int64_t hi[EPT], lo[EPT];
         FOR_J {
             hi[_j] = H[ix[_j]];
             lo[_j] = L[ix[_j]];
         }
-        if (two) {
-            const UVec<const int64_t> H1 = uvec(H.p, w.slice_aux), L1 = uvec(L.p, w.slice_aux);
-            FOR_J {
-                hi1[_j] = H1[ix[_j]];
-                lo1[_j] = L1[ix[_j]];
-            }
-            FOR_J {
-                hi[_j] += hi1[_j];
-                lo[_j] += lo1[_j];
-            }
-        }
-        for (int t = 2; t < w.ksplit_aux; ++t) {
-            const UVec<const int64_t> Ht = uvec(H.p, (int64_t)t * w.slice_aux);
-            const UVec<const int64_t> Lt = uvec(L.p, (int64_t)t * w.slice_aux);
-            FOR_J {
-                hi[_j] += Ht[ix[_j]];
-                lo[_j] += Lt[ix[_j]];
-            }
+        FOR_J if (ok[_j]) {
+            H[ix[_j]] = 0;
+            L[ix[_j]] = 0;
         }
         const int e = uni(c.escale);
         FOR_J u[_j] = digits8_value(hi[_j], lo[_j], e);
     } else {
         if (!w.split) {
-            uval_chunk<UT, EPT>(w, cv, ix, u);
+            uval_chunk<UT, EPT>(w, cv, ix, ok, u);
             return;
         }
         const UVec<const double> U = uvec((const double *)w.U_aux, cv.off);
@@ -419,7 +395,7 @@ __device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red
             xpv[_j] = xp[i];  // stale but unused when k == 0
             gpv[_j] = gp[i];
         }
-        uval_chunk<UT, EPT>(w, cv, ix, u);
+        uval_chunk<UT, EPT>(w, cv, ix, ok, u);
         FOR_J {
             const double xi = xv[_j];
             const double gi = 2.0 * (u[_j] + Av[_j] * xi) + bv[_j];
@@ -667,7 +643,7 @@ __device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red)
             Ad[_j] = dg[i];
             vv[_j] = v[i];
         }
-        uaux_chunk<UT, EPT>(w, c, cv, ix, u);
+        uaux_chunk<UT, EPT>(w, c, cv, ix, ok, u);
         FOR_J {
             if (!ok[_j]) continue;
             const double z = zv[_j], vi = vv[_j];
@@ -766,7 +742,7 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
             pv[_j] = hasP ? P[i] : 0.0;
             apv[_j] = hasP ? AP[i] : 0.0;
         }
-        uaux_chunk<UT, EPT>(w, c, cv, ix, u);
+        uaux_chunk<UT, EPT>(w, c, cv, ix, ok, u);
         FOR_J {
             const double z = zv[_j];
             const bool in_I = ok[_j] && z > 0.0;
@@ -928,7 +904,7 @@ __device__ void cg_step(const Work &w, Col &c, const ColView &cv, double *red) {
             dg[_j] = dq[i] + gam[i];
             dv[_j] = d[i];
         }
-        uaux_chunk<UT, EPT>(w, c, cv, ix, u);
+        uaux_chunk<UT, EPT>(w, c, cv, ix, ok, u);
         FOR_J {
             if (!ok[_j]) continue;
             const double kd = 2.0 * (u[_j] + dg[_j] * dv[_j]);
