@@ -113,13 +113,43 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
     const int8_t *bq[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bq[t] = da.Q + (i0 + 16 * t + m) * ldq + 16 * g;
-    for (int ag = ag0; ag * CA < nact; ag += da.AG) {  // uniform over the block
-        const int8_t *ap[MT];
+    // two register stages: the next stage's loads are issued before the
+    // current stage multiplies. Every load is unconditional and in bounds (a
+    // prefetch past the last stage reloads the current one), so the code is
+    // straight-line and the waits count loads exactly.
+    intx4 a0[UNR][MT], b0[UNR][NT], a1[UNR][MT], b1[UNR][NT];
+    const int8_t *ap[MT];
+    auto load_b = [&](intx4 (&b)[UNR][NT], int64_t k) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[u][t] = ld16(bq[t] + k + 64 * u);
+    };
+    auto load = [&](intx4 (&a)[UNR][MT], intx4 (&b)[UNR][NT], int64_t k) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int s = 0; s < MT; ++s) a[u][s] = ld16(ap[s] + k + 64 * u);
+        load_b(b, k);
+    };
+    // The first stage's Q rows do not depend on the live list: they load
+    // while the live count and the list entries are in flight.
+    if (nstage > 0) load_b(b0, kb);
+    for (int ag = ag0;; ag += da.AG) {  // uniform over the block
+        // list entries read in the same round as the count (slots clamped
+        // to the list, which holds zero_col + 1 entries; entries past the
+        // count are replaced below)
+        int cr[MT], ce[MT];  // entries of the loaded rows and of the stored rows
+#pragma unroll
+        for (int s = 0; s < MT; ++s) {
+            cr[s] = da.active[min((ag * RA + s * 16 + m) / D, da.zero_col)];
+            ce[s] = da.active[min((ag * RA + s * 16 + 4 * g) / D, da.zero_col)];
+        }
+        if (ag * CA >= nact) break;
 #pragma unroll
         for (int s = 0; s < MT; ++s) {
             const int r = ag * RA + s * 16 + m;
-            const int slot = r / D;
-            const int64_t c = slot < nact ? (int64_t)da.active[slot] : (int64_t)da.zero_col;
+            const int64_t c = r / D < nact ? (int64_t)cr[s] : (int64_t)da.zero_col;
             ap[s] = da.dig + (c * D + (r % D)) * ldq + 16 * g;
         }
         intx4 acc[MT][NT];
@@ -127,20 +157,6 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
         for (int s = 0; s < MT; ++s)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[s][t] = intx4{0, 0, 0, 0};
-        // two register stages: the next stage's loads are issued before the
-        // current stage multiplies. Every load is unconditional and in
-        // bounds (a prefetch past the last stage reloads the current one),
-        // so the code is straight-line and the waits count loads exactly.
-        intx4 a0[UNR][MT], b0[UNR][NT], a1[UNR][MT], b1[UNR][NT];
-        auto load = [&](intx4 (&a)[UNR][MT], intx4 (&b)[UNR][NT], int64_t k) {
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-#pragma unroll
-                for (int s = 0; s < MT; ++s) a[u][s] = ld16(ap[s] + k + 64 * u);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) b[u][t] = ld16(bq[t] + k + 64 * u);
-            }
-        };
         auto mult = [&](const intx4 (&a)[UNR][MT], const intx4 (&b)[UNR][NT]) {
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
@@ -152,7 +168,14 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
         };
         int64_t k = kb;
         if (nstage > 0) {
-            load(a0, b0, k);
+            if (ag == ag0) {  // Q rows already loaded
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                    for (int s = 0; s < MT; ++s) a0[u][s] = ld16(ap[s] + k + 64 * u);
+            } else {
+                load(a0, b0, k);
+            }
             for (int64_t st = 0; st < nstage; st += 2) {
                 const bool m1 = st + 1 < nstage;
                 load(a1, b1, m1 ? k + 64 * UNR : k);
@@ -204,11 +227,9 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
 #pragma unroll
             for (int s = 0; s < MT; ++s) {
                 const int row0 = ag * RA + s * 16 + 4 * g;
-                const int slot = row0 / D;
-                if (slot >= nact) continue;
-                const int64_t c = da.active[slot];
+                if (row0 / D >= nact) continue;
                 int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
-                Uo += c * da.ldu;
+                Uo += (int64_t)ce[s] * da.ldu;
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     const int64_t i = i0 + 16 * t + m;
@@ -253,17 +274,33 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
     const int8_t *bq[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bq[t] = da.Q + (i0 + 16 * t + m) * ldq + 16 * g;
-    for (int ag = ag0; ag * CA < nact; ag += da.AG) {  // uniform over the block
+    // the first K step's Q rows do not depend on the live list: they load
+    // while the live count and the list entries are in flight
+    intx4 bpre[NT];
+    if (kb < ke) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bpre[t] = ld16(bq[t] + kb);
+    }
+    for (int ag = ag0;; ag += da.AG) {  // uniform over the block
         // this thread's pieces of the digit tile: piece p = threadIdx.x + 256 q
-        // is row p / 4, bytes 16 (p % 4) .. + 15 of the K step
+        // is row p / 4, bytes 16 (p % 4) .. + 15 of the K step. The list
+        // entries of its rows and of the stored rows are read in the same
+        // round as the count (slots clamped to the list, which holds
+        // zero_col + 1 entries; entries past the count are replaced below).
+        int cr[PC], ce[MT];
+#pragma unroll
+        for (int q = 0; q < PC; ++q)
+            cr[q] = da.active[min((ag * RA + ((int)threadIdx.x + 256 * q) / 4) / D, da.zero_col)];
+#pragma unroll
+        for (int s = 0; s < MT; ++s) ce[s] = da.active[min((ag * RA + s * 16 + 4 * g) / D, da.zero_col)];
+        if (ag * CA >= nact) break;
         const int8_t *af[PC];
         int ao[PC];
 #pragma unroll
         for (int q = 0; q < PC; ++q) {
             const int pce = threadIdx.x + 256 * q;
             const int r = pce >> 2, cb = pce & 3;
-            const int slot = (ag * RA + r) / D;
-            const int64_t c = slot < nact ? (int64_t)da.active[slot] : (int64_t)da.zero_col;
+            const int64_t c = (ag * RA + r) / D < nact ? (int64_t)cr[q] : (int64_t)da.zero_col;
             af[q] = da.dig + (c * D + ((ag * RA + r) % D)) * ldq + 16 * cb;
             ao[q] = r * ROWB + 16 * cb;
         }
@@ -277,7 +314,7 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
 #pragma unroll
             for (int q = 0; q < PC; ++q) an[q] = ld16(af[q] + kb);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = ld16(bq[t] + kb);
+            for (int t = 0; t < NT; ++t) b[t] = ag == ag0 ? bpre[t] : ld16(bq[t] + kb);
 #pragma unroll
             for (int q = 0; q < PC; ++q) *(intx4 *)&As[0][ao[q]] = an[q];
             __syncthreads();
@@ -310,11 +347,9 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
 #pragma unroll
         for (int s = 0; s < MT; ++s) {
             const int row0 = ag * RA + s * 16 + 4 * g;
-            const int slot = row0 / D;
-            if (slot >= nact) continue;
-            const int64_t c = da.active[slot];
+            if (row0 / D >= nact) continue;
             int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
-            Uo += c * da.ldu;
+            Uo += (int64_t)ce[s] * da.ldu;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int64_t i = i0 + 16 * t + m;
