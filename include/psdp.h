@@ -99,7 +99,7 @@ typedef struct {
     int32_t eig_maxit;         /* lambda_min iteration cap (LOBPCG) (500) */
     int32_t cg_maxit;          /* x^0 linear solve iteration cap (500) */
     int32_t timing;            /* 1: time every Q.X launch with HIP events (psdp_stats.qx_*) */
-    int32_t poll_sweeps;       /* sweeps enqueued between host polls of the done count (16) */
+    int32_t poll_sweeps;       /* sweeps enqueued between host polls of the live count (64) */
     int32_t gemm_variant;      /* batched Q.X kernel choice; -1 = chosen per live count */
     int32_t graph;             /* 1: replay batches of sweeps as HIP graphs (1); timing = 1
                                   launches eagerly */

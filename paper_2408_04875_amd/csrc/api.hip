@@ -448,7 +448,7 @@ void psdp_params_default(psdp_params *p) {
     p->eig_maxit = 500;
     p->cg_maxit = 500;
     p->timing = 0;
-    p->poll_sweeps = 16;
+    p->poll_sweeps = 64;
     p->gemm_variant = -1;
     p->graph = 1;
     p->tol_kkt = 1e-5;
