@@ -72,7 +72,12 @@ typedef enum { PSDP_INNER_PABB = 0, PSDP_INNER_PPA = 1 } psdp_inner;
  * is exactly Q_off x_q; a lambda_min or CG vector v is scaled by the power of
  * two 2^e > max|v| and rounded to the grid 2^(e-55) (8 digits), and its
  * product is Q_off v_q rounded once to FP64. psdp_qx_digits exposes this
- * product on its own. */
+ * product on its own.
+ *
+ * With I8 operands the same integers can also come from a compressed sparse
+ * row copy of Q_off (int8 values, int64 accumulation): see
+ * psdp_params.sparse and psdp_qx_sparse. Either product gives identical
+ * results, so the choice changes the speed only. */
 typedef enum { PSDP_F64 = 0, PSDP_F32 = 1, PSDP_BF16 = 2, PSDP_I8 = 3 } psdp_dtype;
 
 /* Random symmetric perturbation of Q before the reformation (Section 3.5,
@@ -103,6 +108,11 @@ typedef struct {
     int32_t gemm_variant;      /* batched Q.X kernel choice; -1 = chosen per live count */
     int32_t graph;             /* 1: replay batches of sweeps as HIP graphs (1); timing = 1
                                   launches eagerly */
+    int32_t sparse;            /* I8 only: -1 (default) builds a sparse copy of Q_off when
+                                  n >= 4096 and at most 1/64 of it is nonzero, and uses it for
+                                  the sweeps with nonzeros x 2 x live columns <= n^2 / 4 (the
+                                  range where it was measured faster on gfx950); 1 builds it
+                                  whatever the size and uses it for every sweep; 0 never */
     double tol_kkt;            /* delta of eq. (cret) (1e-5) */
     double tol_binary;         /* Algorithm 3 loop tolerance (1e-5) */
     double eta;                /* eq. (alpha1) scaling, 0 < eta < 1 (0.999) */
@@ -132,6 +142,7 @@ typedef struct {
     double step_seconds;       /* summed time of the per-column step kernel (timing = 1) */
     int64_t step_launches;     /* number of step launches timed */
     int64_t column_steps;      /* column updates performed by those launches (all columns) */
+    int64_t sparse_sweeps;     /* sweeps whose products used the sparse copy of Q (I8) */
 } psdp_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -300,6 +311,19 @@ psdp_status psdp_perturbation(int64_t n, double sigma, uint64_t seed, int32_t mo
  *         PSDP_E_DEVICE / PSDP_E_NOMEM.
  */
 psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t B,
+                           int32_t digits, double *Y, hipStream_t stream);
+
+/*
+ * psdp_qx_sparse - the same product as psdp_qx_digits (same arguments, same
+ * rounding, bit-identical Y), computed from a compressed sparse row copy of
+ * Q_off built on the device: one int32 word per operand entry (T, or T_hi
+ * and T_lo with T = T_hi 2^28 + T_lo for 8 digits) times the int8 nonzeros,
+ * accumulated exactly in int64. Work and time grow with the nonzeros; the
+ * solver uses this form for sparse Q (psdp_params.sparse).
+ * Errors: as psdp_qx_digits, and PSDP_E_UNSUPPORTED when Q_off has 2^31 or
+ * more nonzeros.
+ */
+psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t B,
                            int32_t digits, double *Y, hipStream_t stream);
 
 /* Releases the cached device workspace of every device (optional). */

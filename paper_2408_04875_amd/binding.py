@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("poll_sweeps", ctypes.c_int32),
         ("gemm_variant", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("sparse", ctypes.c_int32),
         ("tol_kkt", ctypes.c_double),
         ("tol_binary", ctypes.c_double),
         ("eta", ctypes.c_double),
@@ -68,6 +69,7 @@ class Stats(ctypes.Structure):
         ("step_seconds", ctypes.c_double),
         ("step_launches", ctypes.c_int64),
         ("column_steps", ctypes.c_int64),
+        ("sparse_sweeps", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -93,6 +95,7 @@ SIGNATURES = {
     "psdp_round_objective_i32": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
     "psdp_perturbation": (_I32, [_I64, _D, _U64, _I32, _P, _P]),
     "psdp_qx_digits": (_I32, [_P, _I64, _P, _I32, _I32, _P, _P]),
+    "psdp_qx_sparse": (_I32, [_P, _I64, _P, _I32, _I32, _P, _P]),
     "psdp_release": (None, []),
 }
 
@@ -320,11 +323,12 @@ def round_objective(Q, b, X):
     return xhat, obj
 
 
-def qx_digits(Q, X, digits: int = 4):
+def qx_digits(Q, X, digits: int = 4, sparse: bool = False):
     """Exact integer product of the I8 path: rows of X (shape (B, n) float64)
     times Q with a zero diagonal, returned as (B, n) float64. digits=4 needs
     X in [0,1] (grid 2^-27, exact result); digits=8 scales each row by a
-    power of two (grid 2^(e-55), result rounded once)."""
+    power of two (grid 2^(e-55), result rounded once). sparse=True computes
+    the same values from a sparse copy of Q (psdp_qx_sparse)."""
     torch = _torch()
     lib = load()
     _dev(Q, torch.int32, "Q")
@@ -333,7 +337,8 @@ def qx_digits(Q, X, digits: int = 4):
     X2 = X.reshape(-1, n)
     B = X2.shape[0]
     Y = torch.empty((B, n), dtype=torch.float64, device=X.device)
-    _check(lib.psdp_qx_digits(_ptr(Q), n, _ptr(X2), B, int(digits), _ptr(Y), _stream()))
+    fn = lib.psdp_qx_sparse if sparse else lib.psdp_qx_digits
+    _check(fn(_ptr(Q), n, _ptr(X2), B, int(digits), _ptr(Y), _stream()))
     return Y
 
 

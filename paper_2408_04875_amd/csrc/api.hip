@@ -71,13 +71,45 @@ psdp_status check_params(const psdp_params &p) {
         !(p.cg_tol > 0.0) || !(p.alpha_min > 0.0) || !(p.alpha_max >= p.alpha_min) ||
         !(p.lambda_floor_rel >= 0.0) || !(p.sigma >= 0.0) || !std::isfinite(p.sigma))
         return fail(PSDP_E_INVALID, "params: tolerance out of range");
+    if (p.sparse < -1 || p.sparse > 1) return fail(PSDP_E_INVALID, "params.sparse must be -1, 0 or 1");
+    if (p.sparse == 1 && p.qx_dtype != PSDP_I8)
+        return fail(PSDP_E_UNSUPPORTED, "sparse products need I8 operands");
     return PSDP_OK;
 }
 
+// Row starts of the compressed sparse rows of Q_off from per-row counts;
+// false when there are 2^31 or more nonzeros (int32 row starts).
+bool csr_rowptr(const std::vector<int64_t> &rownnz, std::vector<int32_t> *rowptr, int64_t *nnz) {
+    rowptr->assign(rownnz.size() + 1, 0);
+    int64_t s = 0;
+    for (size_t i = 0; i < rownnz.size(); ++i) {
+        s += rownnz[i];
+        if (s > 2147483647ll) return false;
+        (*rowptr)[i + 1] = (int32_t)s;
+    }
+    *nnz = s;
+    return true;
+}
+
+// When the sparse products pay (measured on gfx950 against the digit
+// products, whole solves): never at n <= 3000, even at 1% density (5-10%
+// slower per sweep: the digit products of Q with under 10^7 entries are
+// latency-bound and so are the gathers); at n = 8000 and 0.5% density 7%
+// faster with one start and 21% with 16. Automatic use therefore needs
+// n >= 4096 and a density of at most 1/64, and then takes a batch whose
+// nonzeros x 2 x live columns (every live column counted as a two-half
+// lambda_min column) stay within n^2 / 4.
+constexpr int64_t kSparseMinN = 4096;
+bool sparse_worth_building(int64_t n, int64_t nnz) { return n >= kSparseMinN && 64 * nnz <= n * n; }
+bool sparse_batch(int64_t n, int64_t nnz, int live) { return (double)nnz * 2.0 * live <= 0.25 * (double)n * (double)n; }
+
 // Host-side checks of one integer instance (Q and b already copied back).
+// rownnz (optional): the off-diagonal nonzeros of every row.
 psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int32_t> &b, int64_t n,
-                           const psdp_params &p, int64_t *offmax_out = nullptr) {
+                           const psdp_params &p, int64_t *offmax_out = nullptr,
+                           std::vector<int64_t> *rownnz = nullptr) {
     int64_t qmax = 0, bmax = 0, offmax = 0;
+    if (rownnz) rownnz->assign(n, 0);
     for (int64_t i = 0; i < n; ++i) {
         bmax = std::max<int64_t>(bmax, std::llabs((long long)b[i]));
         for (int64_t j = 0; j < n; ++j) {
@@ -90,7 +122,10 @@ psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int3
             }
             const int64_t a = std::llabs((long long)v);
             qmax = std::max(qmax, a);
-            if (i != j) offmax = std::max(offmax, a);
+            if (i != j) {
+                offmax = std::max(offmax, a);
+                if (rownnz && v != 0) ++(*rownnz)[i];
+            }
         }
     }
     // |f(x)| <= n^2 max|Q| + n max|b| must stay below 2^62
@@ -146,6 +181,12 @@ struct Solver {
     // (cnt[2 p] main, cnt[2 p + 1] aux)
     int32_t *act[2] = {nullptr, nullptr}, *act_aux[2] = {nullptr, nullptr};
     int32_t *cnt = nullptr;
+    // sparse copy of Q_off (I8) and whether the current batch uses it
+    const int32_t *rowptr = nullptr;
+    const uint32_t *pk = nullptr;
+    int64_t nnz = 0;
+    bool sparse_now = false;
+    int64_t sparse_sweeps = 0;
 };
 
 // Points the work record at the lists of a sweep of parity p: the products
@@ -379,6 +420,7 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
             HIPCHK(enqueue_sweeps(nb));
         }
         done_sweeps += nb;
+        if (S.sparse_now) S.sparse_sweeps += nb;
         set_parity(S, (int)(done_sweeps & 1));  // the lists the next sweep would read
         const int slot = batch & 1;
         HIPCHK(hipMemcpyAsync(host_cnt + 2 * slot, w.nactive, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -451,6 +493,7 @@ void psdp_params_default(psdp_params *p) {
     p->poll_sweeps = 64;
     p->gemm_variant = -1;
     p->graph = 1;
+    p->sparse = -1;
     p->tol_kkt = 1e-5;
     p->tol_binary = 1e-5;
     p->eta = 0.999;
@@ -516,7 +559,19 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     }
     HIPCHK(hipStreamSynchronize(st));
     int64_t offmax = 0;
-    if (psdp_status s = check_instance(hQ, hb, n, prm, &offmax)) return s;
+    std::vector<int64_t> rownnz;
+    const bool want_counts = prm.qx_dtype == PSDP_I8 && prm.sparse != 0;
+    if (psdp_status s = check_instance(hQ, hb, n, prm, &offmax, want_counts ? &rownnz : nullptr)) return s;
+    std::vector<int32_t> hrowptr;
+    bool csr = false;
+    int64_t csr_nnz = 0;
+    if (want_counts) {
+        int64_t nnz = 0;
+        const bool fits = csr_rowptr(rownnz, &hrowptr, &nnz);
+        if (!fits && prm.sparse == 1) return fail(PSDP_E_UNSUPPORTED, "sparse Q needs fewer than 2^31 nonzeros");
+        csr = fits && (prm.sparse == 1 || sparse_worth_building(n, nnz));
+        if (csr) csr_nnz = nnz;
+    }
     for (double v : hX0)
         if (!(v >= 0.0 && v <= 1.0)) return fail(PSDP_E_NONFINITE, "X0 entries must lie in [0,1]");
     for (double v : hp0)
@@ -569,6 +624,18 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     HIPCHK(S.ar.get((void **)&R, ld * 8));
     HIPCHK(S.ar.get((void **)&dq, ld * 8));
     HIPCHK(launch_prep_q(qtype, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qop, R, dq, st));
+    if (csr) {
+        // sparse rows of Q_off from the int8 copy (row starts counted on the host)
+        int32_t *drp;
+        uint32_t *dpk;
+        HIPCHK(S.ar.get((void **)&drp, (n + 1) * sizeof(int32_t)));
+        HIPCHK(S.ar.get((void **)&dpk, std::max<int64_t>(1, csr_nnz) * sizeof(uint32_t)));
+        HIPCHK(hipMemcpyAsync(drp, hrowptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_csr_fill((const int8_t *)Qop, ld, n, drp, dpk, st));
+        S.rowptr = drp;
+        S.pk = dpk;
+        S.nnz = csr_nnz;
+    }
     void *Qaux = Qop;
     if (w.split && !i8 && aux_gemm == PSDP_F64) {
         HIPCHK(S.ar.get(&Qaux, ld * ld * sizeof(double)));
@@ -587,6 +654,12 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     // column data
     const int kmax = (batched && !i8) ? kMaxSplit : 1;  // integer slices add into one buffer
     if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, st, ld)) return s2;
+    if (S.rowptr) {  // the operands' grid values as words, for the sparse products
+        for (int32_t **pw : {&w.tw, &w.tw_hi, &w.tw_lo}) {
+            HIPCHK(S.ar.get((void **)pw, ld * B * sizeof(int32_t)));
+            HIPCHK(hipMemsetAsync(*pw, 0, ld * B * sizeof(int32_t), st));
+        }
+    }
     const int MT = (int)((ld + 63) / 64);
     // Product kernel per live count (the count comes from the last host poll,
     // so it is an estimate; every kernel covers all B columns regardless).
@@ -627,6 +700,10 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         digit_layout(p8a.est, 8, ld, &p8a.mt, &ba);
         p8m.ks = digit_slices(p8m.mt, bm + ba);
         p8a.ks = digit_slices(p8a.mt, bm + ba);
+        // sparse products while they cost less than the digit products; the
+        // bound takes every live column as a two-half lambda_min column
+        const int live = std::min(B, cm + ca);
+        S.sparse_now = S.rowptr != nullptr && (prm.sparse == 1 || sparse_batch(n, S.nnz, live));
     };
     pick8(B, B);
     Pick pm = pick(B, B, main_gemm), pa = pick(B, B, aux_gemm);
@@ -678,14 +755,22 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         };
         const int8_t *Q8 = (const int8_t *)Qop;
         S.config_key = [&]() {
-            return (int64_t)p8m.mt | ((int64_t)p8m.ks << 3) | ((int64_t)p8a.mt << 7) | ((int64_t)p8a.ks << 10) |
-                   ((int64_t)p8m.est << 14) | ((int64_t)p8a.est << 34);
+            return ((int64_t)p8m.mt | ((int64_t)p8m.ks << 3) | ((int64_t)p8a.mt << 7) | ((int64_t)p8a.ks << 10) |
+                    ((int64_t)p8m.est << 14) | ((int64_t)p8a.est << 34)) * 2 +
+                   (S.sparse_now ? 1 : 0);
         };
         S.repick = [&](int cm, int ca) { pick8(cm, ca); };
         // both products in one launch (timed as one launch when timing = 1)
         rs = run_sweeps(
             S, prm, tm, ta, ts, st,
             [&]() {
+                if (S.sparse_now) {
+                    const SparseJob sm{p8m.est > 0, S.rowptr, S.pk, n, w.tw, nullptr, ld, w.active, w.nactive, B,
+                                       (int64_t *)w.U, nullptr, ld};
+                    const SparseJob sa{p8a.est > 0, S.rowptr, S.pk, n, w.tw_hi, w.tw_lo, ld, w.active_aux,
+                                       w.nactive_aux, B, (int64_t *)w.U_aux, w.U_lo, ld};
+                    return launch_sparse(&sm, &sa, st);
+                }
                 const DigitJob jm = job_main(), ja = job_aux();
                 return launch_digit(Q8, ld, n, ld, &jm, &ja, st);
             },
@@ -777,6 +862,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
             aflops += apart ? 2.0 * (double)n * (double)n * (double)cc.aux : 0.0;
         }
         fill_stats(hcol, nsweeps, tm, flops, ta, aflops, ts, stats);
+        for (int64_t c = 0; c < B; ++c) stats[c].sparse_sweeps = S.sparse_sweeps;
     }
     return PSDP_OK;
 }
@@ -961,10 +1047,10 @@ psdp_status psdp_perturbation(int64_t n, double sigma, uint64_t seed, int32_t mo
     return PSDP_OK;
 }
 
-psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits, double *Y,
-                           hipStream_t st) {
-    std::lock_guard<std::mutex> lk(g_lock);
-    g_err.clear();
+// Checks of the stand-alone integer products; rownnz gets the off-diagonal
+// nonzeros of every row.
+psdp_status qx_int_checks(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits, double *Y,
+                          hipStream_t st, std::vector<int64_t> *rownnz) {
     if (!Q || !X || !Y) return fail(PSDP_E_INVALID, "null pointer");
     if (n < 1 || n > 65536 || B < 1) return fail(PSDP_E_INVALID, "n must be in [1, 65536] and B >= 1");
     if (digits != 4 && digits != 8) return fail(PSDP_E_INVALID, "digits must be 4 or 8");
@@ -973,14 +1059,28 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     HIPCHK(hipMemcpyAsync(hQ.data(), Q, n * n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hX.data(), X, n * B * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    rownnz->assign(n, 0);
     for (int64_t i = 0; i < n; ++i)
-        for (int64_t j = 0; j < n; ++j)
-            if (i != j && std::llabs((long long)hQ[i * n + j]) > 127)
+        for (int64_t j = 0; j < n; ++j) {
+            const int32_t v = hQ[i * n + j];
+            if (i == j) continue;
+            if (std::llabs((long long)v) > 127)
                 return fail(PSDP_E_UNSUPPORTED, "int8 operands need |Q_ij| <= 127 off the diagonal");
+            if (v != 0) ++(*rownnz)[i];
+        }
     for (double v : hX) {
         if (!std::isfinite(v)) return fail(PSDP_E_NONFINITE, "X must be finite");
         if (digits == 4 && !(v >= 0.0 && v <= 1.0)) return fail(PSDP_E_NONFINITE, "digits 4 needs X in [0,1]");
     }
+    return PSDP_OK;
+}
+
+psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits, double *Y,
+                           hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    std::vector<int64_t> rownnz;
+    if (psdp_status s = qx_int_checks(Q, n, X, B, digits, Y, st, &rownnz)) return s;
     Arena ar;
     const int64_t ld = (n + 63) / 64 * 64;
     const int64_t rows = (ld + kDigitRowsAlign - 1) / kDigitRowsAlign * kDigitRowsAlign;
@@ -1017,6 +1117,51 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     cnt = act + B;
     const DigitJob job{dig, act, cnt, U0, U1, B, ks, mt, B};
     HIPCHK(launch_digit(Q8, ld, n, ld, D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
+    HIPCHK(launch_digit_combine(U0, U1, n, ld, B, D, esc, Y, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PSDP_OK;
+}
+
+psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits, double *Y,
+                           hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    std::vector<int64_t> rownnz;
+    if (psdp_status s = qx_int_checks(Q, n, X, B, digits, Y, st, &rownnz)) return s;
+    std::vector<int32_t> hrowptr;
+    int64_t nnz = 0;
+    if (!csr_rowptr(rownnz, &hrowptr, &nnz)) return fail(PSDP_E_UNSUPPORTED, "sparse Q needs fewer than 2^31 nonzeros");
+    Arena ar;
+    const int64_t ld = (n + 63) / 64 * 64;
+    const int D = digits;
+    int8_t *Q8;
+    double *R, *dq;
+    int32_t *rowptr, *w0, *w1 = nullptr, *act, *esc;
+    uint32_t *pk;
+    int64_t *U0, *U1 = nullptr;
+    HIPCHK(ar.get((void **)&Q8, ld * ld));
+    HIPCHK(hipMemsetAsync(Q8, 0, ld * ld, st));
+    HIPCHK(ar.get((void **)&R, ld * 8));
+    HIPCHK(ar.get((void **)&dq, ld * 8));
+    HIPCHK(launch_prep_q(PSDP_I8, Q, n, ld, PSDP_PERTURB_NONE, 0.0, 0, Q8, R, dq, st));
+    HIPCHK(ar.get((void **)&rowptr, (n + 1) * sizeof(int32_t)));
+    HIPCHK(ar.get((void **)&pk, std::max<int64_t>(1, nnz) * sizeof(uint32_t)));
+    HIPCHK(hipMemcpyAsync(rowptr, hrowptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_csr_fill(Q8, ld, n, rowptr, pk, st));
+    const int64_t slice = (int64_t)B * ld;
+    HIPCHK(ar.get((void **)&w0, slice * sizeof(int32_t)));
+    if (D == 8) HIPCHK(ar.get((void **)&w1, slice * sizeof(int32_t)));
+    HIPCHK(ar.get((void **)&esc, (int64_t)B * sizeof(int32_t)));
+    HIPCHK(launch_words_from_vectors(X, n, n, B, D, w0, w1, ld, esc, st));
+    HIPCHK(ar.get((void **)&U0, slice * sizeof(int64_t)));
+    if (D == 8) HIPCHK(ar.get((void **)&U1, slice * sizeof(int64_t)));
+    std::vector<int32_t> iota(B + 1);
+    for (int c = 0; c < B; ++c) iota[c] = c;
+    iota[B] = B;  // live count
+    HIPCHK(ar.get((void **)&act, (B + 1) * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(act, iota.data(), (B + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const SparseJob job{1, rowptr, pk, n, w0, w1, ld, act, act + B, B, U0, U1, ld};
+    HIPCHK(launch_sparse(D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
     HIPCHK(launch_digit_combine(U0, U1, n, ld, B, D, esc, Y, st));
     HIPCHK(hipStreamSynchronize(st));
     return PSDP_OK;

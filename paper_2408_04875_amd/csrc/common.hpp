@@ -104,6 +104,11 @@ struct Work {
     int8_t *dig;
     int8_t *dig_aux;
     int64_t *U_lo;
+    // integer path with a sparse copy of Q: the operands' grid values as
+    // int32 words too (tw: T of a subproblem iterate; tw_hi, tw_lo: the two
+    // halves of a lambda_min / CG vector), column layout as the vectors;
+    // null when no sparse copy exists
+    int32_t *tw, *tw_hi, *tw_lo;
     // live lists of the next sweep: the column kernel appends every live
     // column (slot claimed with an atomic on next_cnt[0] for the main list,
     // next_cnt[1] for the aux list) and clears clear_cnt[0..1], the counters
@@ -171,13 +176,19 @@ __device__ __forceinline__ void put_digits4(int8_t *p, int64_t plane, uint32_t i
 }
 
 // Eight digits of v scaled by 2^-e (|v| < 2^e): T = rint(v 2^(55 - e)),
-// split as T = T_hi 2^28 + T_lo with |T_hi|, |T_lo| <= 2^27, each in four
-// digits (planes 0-3 and 4-7).
-__device__ __forceinline__ void put_digits8(int8_t *p, int64_t plane, uint32_t i, double v, int e) {
+// split as T = T_hi 2^28 + T_lo with |T_hi|, |T_lo| <= 2^27 (split8), each in
+// four digits (planes 0-3 and 4-7).
+__device__ __forceinline__ void split8(double v, int e, int32_t *hi, int32_t *lo) {
     const int64_t T = __double2ll_rn(ldexp(v, kAuxBits - e));
-    const int64_t hi = (T + (1ll << 27)) >> 28;
+    const int64_t h = (T + (1ll << 27)) >> 28;
+    *hi = (int32_t)h;
+    *lo = (int32_t)(T - (h << 28));
+}
+__device__ __forceinline__ void put_digits8(int8_t *p, int64_t plane, uint32_t i, double v, int e) {
+    int32_t hi, lo;
+    split8(v, e, &hi, &lo);
     put_digits4(p, plane, i, hi);
-    put_digits4(p + 4 * plane, plane, i, T - (hi << 28));
+    put_digits4(p + 4 * plane, plane, i, lo);
 }
 
 // Value of an 8-digit product from its summed halves: (hi 2^28 + lo) 2^(e - 55),
@@ -370,6 +381,28 @@ hipError_t launch_digits_from_vectors(const double *X, int64_t n, int64_t ldx, i
                                       int64_t ldq, int32_t *escale, hipStream_t st);
 hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t n, int64_t ldu, int B, int D,
                                 const int32_t *escale, double *Y, hipStream_t st);
+
+// Exact integer products from the compressed sparse rows of Q_off (sparse.hip):
+// the same integers as the digit products, read from int32 operand words.
+struct SparseJob {
+    int on;                  // 0: not launched
+    const int32_t *rowptr;   // n + 1 row starts
+    const uint32_t *pk;      // packed nonzeros: column in bits 0-15, int8 value in bits 16-23
+    int64_t n;
+    const int32_t *w0, *w1;  // operand words: T, or T_hi and T_lo; column c at c * ldw
+    int64_t ldw;
+    const int32_t *active;   // live list (zero_col + 1 readable entries) and its device count
+    const int32_t *nactive;
+    int zero_col;            // an all-zero operand column
+    int64_t *U0, *U1;        // outputs (U1 for the low half), column c at c * ldu
+    int64_t ldu;
+};
+hipError_t launch_csr_count(const int8_t *Q8, int64_t ldq, int64_t n, int32_t *cnt, hipStream_t st);
+hipError_t launch_csr_fill(const int8_t *Q8, int64_t ldq, int64_t n, const int32_t *rowptr, uint32_t *pk,
+                           hipStream_t st);
+hipError_t launch_sparse(const SparseJob *main4, const SparseJob *aux8, hipStream_t st);
+hipError_t launch_words_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int32_t *w0,
+                                     int32_t *w1, int64_t ldw, int32_t *escale, hipStream_t st);
 
 // Solver kernels.
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,

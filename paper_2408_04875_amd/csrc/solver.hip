@@ -168,10 +168,13 @@ __device__ __forceinline__ int8_t *aux_planes(const Work &w, const Col &c) {
 // it to the grid 2^-27 and writes its 4 digits).
 template <typename OpT>
 __device__ __forceinline__ void put_main(const Work &w, const Col &c, const ColView &cv, uint32_t i, double v) {
-    if constexpr (kDigits<OpT>)
-        put_digits4(main_planes(w, c), uni(c.ld), i, __double2ll_rn(v * kMainScale));
-    else
+    if constexpr (kDigits<OpT>) {
+        const int64_t T = __double2ll_rn(v * kMainScale);
+        put_digits4(main_planes(w, c), uni(c.ld), i, T);
+        if (w.tw) uvec(w.tw, cv.off)[i] = (int32_t)T;
+    } else {
         uvec((OpT *)w.op, cv.off)[i] = from_f64<OpT>(v);
+    }
 }
 
 // Integer path: 8 digits of the lambda_min / CG operand just written by
@@ -187,6 +190,8 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, const ColView 
         const UVec<const double> src = uvec((const double *)w.op_aux, cv.off);
         int8_t *dst = aux_planes(w, c);
         const int64_t ld = uni(c.ld);
+        const bool words = w.tw_hi != nullptr;
+        const UVec<int32_t> wh{words ? w.tw_hi + cv.off : nullptr}, wl{words ? w.tw_lo + cv.off : nullptr};
         CHUNKS(n) {
             CHUNK_INDEX(n)
             double v[EPT];
@@ -195,7 +200,16 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, const ColView 
             } else {
                 FOR_J v[_j] = src[ix[_j]];
             }
-            FOR_J if (ok[_j]) put_digits8(dst, ld, ix[_j], v[_j], e);
+            FOR_J if (ok[_j]) {
+                int32_t hi, lo;
+                split8(v[_j], e, &hi, &lo);
+                put_digits4(dst, ld, ix[_j], hi);
+                put_digits4(dst + 4 * ld, ld, ix[_j], lo);
+                if (words) {
+                    wh[ix[_j]] = hi;
+                    wl[ix[_j]] = lo;
+                }
+            }
         }
         // every read of c.escale this sweep (the first pass) precedes the
         // block reductions that the callers ran since

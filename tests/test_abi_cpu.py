@@ -32,6 +32,7 @@ def test_params_defaults_and_struct_size(lib):
     assert p.struct_size == ctypes.sizeof(binding.Params)
     assert (p.max_inner, p.max_outer, p.tol_kkt) == (10000, 1000, 1e-5)   # Section 5
     assert p.eta == 0.999 and p.stall_outer == 2
+    assert p.poll_sweeps == 64 and p.sparse == -1 and p.graph == 1
     q = binding.default_params(inner="ppa", qx_dtype="f32", perturb="diag", sigma=0.5)
     assert (q.inner, q.qx_dtype, q.perturb, q.sigma) == (1, 1, 2, 0.5)
     with pytest.raises(TypeError):
@@ -62,6 +63,11 @@ def test_invalid_arguments_fail_before_device_work(lib):
     st = lib.psdp_solve_i32(dummy, dummy, 4, None, None, 1, ctypes.byref(wrong), dummy, dummy, None, None,
                             None, None)
     assert st == -1 and "struct_size" in lib.psdp_last_error().decode()
+    for kw, code, word in ((dict(sparse=2), -1, "sparse"), (dict(sparse=1, qx_dtype="f64"), -7, "I8")):
+        sp = binding.default_params(**kw)
+        st = lib.psdp_solve_i32(dummy, dummy, 4, None, None, 1, ctypes.byref(sp), dummy, dummy, None, None,
+                                None, None)
+        assert st == code and word in lib.psdp_last_error().decode()
     st = lib.psdp_eval_penalty_grad(7, 0, dummy, 4, dummy, dummy, dummy, 4, 1, dummy, None, None)
     assert st == -1
     st = lib.psdp_penalty_adjoint(2, 0, dummy, dummy, dummy, 4, 1, None, None, None, None, None)

@@ -1,0 +1,128 @@
+"""GPU parity of the sparse integer product path (compressed sparse rows of
+Q_off, int8 values, int64 accumulation).
+
+The sparse product must give the same integers as the dense digit product:
+bit for bit against oracle/fixed_point.py through psdp_qx_sparse, and whole
+solves with sparse products forced on must equal solves with them off
+(iterates, objectives, iteration counts)."""
+import numpy as np
+import pytest
+
+from oracle import fixed_point as F
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2408_04875_amd as P
+    assert torch.cuda.is_available()
+    P.load()
+    return P
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _sym(n, seed, density, lim=127):
+    rng = np.random.default_rng(seed)
+    Q = rng.integers(-lim, lim + 1, (n, n)) * (rng.random((n, n)) < density)
+    Q = np.triu(Q) + np.triu(Q, 1).T
+    np.fill_diagonal(Q, rng.integers(-10**5, 10**5, n))  # never enters the product
+    return Q.astype(np.int32)
+
+
+@pytest.mark.parametrize("n,B,density", [(1, 1, 1.0), (17, 3, 0.3), (64, 4, 1.0), (65, 5, 0.0),
+                                         (300, 9, 0.05), (777, 6, 0.001), (1000, 4, 0.1)])
+@pytest.mark.parametrize("digits", [4, 8])
+def test_sparse_product_bit_exact(P, n, B, density, digits):
+    Q = _sym(n, n * 3 + B, density)
+    rng = np.random.default_rng(n + B)
+    if digits == 4:
+        X = gen.random_box_points(n, B, 7 + n)
+        X[0, : min(n, 2)] = [1.0, 0.0][: min(n, 2)]
+    else:
+        X = rng.standard_normal((B, n)) * (2.0 ** rng.integers(-30, 30, (B, 1)))
+        if B > 2:
+            X[1] = 0.0
+    Y = P.qx_digits(_t(Q), _t(X), digits=digits, sparse=True).cpu().numpy()
+    ref = F.qx_fixed_point(Q, X, digits)
+    assert np.array_equal(Y, ref)
+    D = P.qx_digits(_t(Q), _t(X), digits=digits).cpu().numpy()
+    assert np.array_equal(Y, D)
+
+
+def test_sparse_product_rows_empty_and_full(P):
+    """A row with every entry nonzero next to rows with none."""
+    n = 200
+    Q = np.zeros((n, n), dtype=np.int32)
+    Q[5, :] = Q[:, 5] = -127
+    Q[7, :] = Q[:, 7] = 127
+    np.fill_diagonal(Q, 3)
+    X = np.ones((3, n))
+    X[1] = gen.random_box_points(n, 1, 2)[0]
+    Y = P.qx_digits(_t(Q), _t(X), digits=4, sparse=True).cpu().numpy()
+    assert np.array_equal(Y, F.qx_fixed_point(Q, X, 4))
+
+
+def _same_solve(a, b):
+    assert np.array_equal(a.X.cpu().numpy(), b.X.cpu().numpy())
+    assert np.array_equal(a.obj.cpu().numpy(), b.obj.cpu().numpy())
+    assert np.array_equal(a.xhat.cpu().numpy(), b.xhat.cpu().numpy())
+    for sa, sb in zip(a.stats, b.stats):
+        for key in ("inner_iters", "aux_matvecs", "outer_iters", "exit_reason", "sweeps"):
+            assert sa[key] == sb[key], key
+
+
+@pytest.mark.parametrize("case", ["dense64", "sparse1000", "maxcut400"])
+def test_solve_with_sparse_products_equals_dense(P, case):
+    kw = {}
+    if case == "dense64":
+        Q, b = gen.dense_int(64, 3)
+        X0 = gen.random_box_points(64, 6, 11)
+    elif case == "sparse1000":
+        Q, b, X0 = gen.sparse_2500_starts(n=1000, B=8)
+    else:
+        W = gen.maxcut_graph(400, 9)
+        Q, b = W, (-W.sum(axis=1)).astype(np.int32)
+        X0 = gen.random_box_points(400, 4, 5)
+        kw = dict(perturb="diag", sigma=0.5, seed=3)
+    on = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", sparse=1, **kw)
+    off = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", sparse=0, **kw)
+    print(f"{case}: sparse sweeps {on.stats[0]['sparse_sweeps']} of {on.stats[0]['sweeps']}; "
+          f"objectives {on.obj.cpu().numpy().tolist()}", flush=True)
+    assert on.stats[0]["sparse_sweeps"] == on.stats[0]["sweeps"] - 1  # every product sweep
+    assert off.stats[0]["sparse_sweeps"] == 0
+    _same_solve(on, off)
+
+
+def test_automatic_sparse_products(P):
+    """The default setting builds the sparse copy only where it was measured
+    faster (n >= 4096 and at most 1/64 nonzero): not for the n = 2500, 10%
+    workload; for a sparse Max-Cut graph at n = 4096 it is used, and the
+    solve is unchanged."""
+    Q, b, X0 = gen.sparse_2500_starts(B=4)
+    auto = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8")
+    assert auto.stats[0]["sparse_sweeps"] == 0
+    W = gen.maxcut_graph(4096, 9, 0.005)
+    bw = (-W.sum(axis=1)).astype(np.int32)
+    X0 = gen.random_box_points(4096, 4, 5)
+    kw = dict(perturb="diag", sigma=0.5, seed=3)
+    auto = P.solve(_t(W), _t(bw), X0=_t(X0), qx_dtype="i8", **kw)
+    off = P.solve(_t(W), _t(bw), X0=_t(X0), qx_dtype="i8", sparse=0, **kw)
+    s = auto.stats[0]
+    print(f"maxcut n=4096 p=0.005 B=4: sparse sweeps {s['sparse_sweeps']} of {s['sweeps']}", flush=True)
+    assert s["sparse_sweeps"] > 0
+    _same_solve(auto, off)
+
+
+def test_sparse_option_errors(P):
+    Q, b = gen.dense_int(20, 1)
+    with pytest.raises(P.PSDPError, match="I8"):
+        P.solve(_t(Q), _t(b), qx_dtype="f64", sparse=1)
+    with pytest.raises(P.PSDPError, match="sparse"):
+        P.solve(_t(Q), _t(b), qx_dtype="i8", sparse=3)
