@@ -23,6 +23,12 @@ plain single-instance comparison at equal objective on a subset of starts,
 and the FP64 oracle's rate on a bounded sample of the same workload on the
 host cores.
 
+With I8 operands the line also carries `sparse`: a sparse Max-Cut workload
+(n = 8000, G(n, 0.005) with +-1 weights, b = -We, 16 starts, diagonal
+perturbation) solved with the sparse-row products (the automatic choice at
+that size and density) and with the dense digit products, at equal
+objectives, with the sparse product kernel's average launch time and rate.
+
 `python bench.py --calibrate-copy` only copies 1 GiB between two device
 buffers (the reference kernel for the HBM byte counters).
 """
@@ -59,6 +65,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--qx", default="i8", choices=["i8", "f32", "f64"])
     ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
@@ -119,6 +126,49 @@ def cpu_baseline(Q, b, X0, budget_s=20.0):
     return {"value": evals / wall, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"start 0 of the n=2500 workload, {outer} penalty updates, {evals} evaluations "
                       f"(dense eigensolver and BLAS matvecs included), {wall:.1f} s"}
+
+
+def sparse_leg(P, gen, torch, dev, n=8000, p_edge=0.005, B=16):
+    """Sparse-row products against digit products on a sparse Max-Cut graph."""
+    import numpy as np
+    W = gen.maxcut_graph(n, 9, p_edge)
+    bw = (-W.sum(axis=1)).astype(np.int32)
+    X0 = gen.random_box_points(n, B, 5)
+    nnz = int(np.count_nonzero(W))
+    Wd, bd, Xd = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (W, bw, X0))
+    kw = dict(qx_dtype="i8", perturb="diag", sigma=0.5, seed=3)
+
+    def run(sparse, timing=0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = P.solve(Wd, bd, X0=Xd, sparse=sparse, timing=timing, **kw)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    run(-1)
+    auto, wa = run(-1)
+    dense, wd = run(0)
+    ev = sum(s["inner_iters"] for s in auto.stats)
+    same = int((auto.obj.cpu().numpy() == dense.obj.cpu().numpy()).sum())
+    timed_run, _ = run(-1, timing=1)
+    s0 = timed_run.stats[0]
+    halves = sum(s["inner_iters"] + 2 * s["aux_matvecs"] for s in timed_run.stats)
+    # per column half: the gathered operand words (4 B per nonzero), a share
+    # of the packed nonzeros (4 B per nonzero per group of 4 halves) and the
+    # int64 outputs
+    per_half = 4 * nnz + nnz + 8 * n
+    qs = s0["qx_seconds"] + s0["aux_seconds"]
+    return {"workload": f"maxcut n={n} G(n,{p_edge}) +-1 weights, b=-We, diag perturbation sigma 0.5, "
+                        f"{B} random starts, Q.X i8",
+            "nnz": nnz, "evals_per_s_sparse": ev / wa, "evals_per_s_dense": ev / wd,
+            "speedup_sparse_vs_dense": wd / wa, "equal_objective": same, "starts": B,
+            "sparse_sweeps": int(auto.stats[0]["sparse_sweeps"]), "sweeps": int(auto.stats[0]["sweeps"]),
+            "sparse_kernel": {"kernel": "sparse_kernel (CSR rows, int64 exact)", "launches": s0["qx_launches"],
+                              "avg_launch_us": qs / max(s0["qx_launches"], 1) * 1e6,
+                              "bytes_per_column_half": per_half,
+                              "achieved": halves * per_half / qs / 1e9 if qs > 0 else 0.0,
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": halves * per_half / qs / 1e9 / PEAK_HBM_GBS if qs > 0 else 0.0}}
 
 
 def main():
@@ -238,6 +288,8 @@ def main():
                         "speedup_batched_vs_plain": (evals / wall) / plain_rate,
                         "batched_evals_matching": int(be[same].sum()) if same else 0,
                         "plain_evals_matching": int(sum(pe[k] for k in same))}
+    if not args.no_sparse and args.qx == "i8":
+        out["sparse"] = sparse_leg(P, gen, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, b, X0)
     print(json.dumps(out), flush=True)
