@@ -83,7 +83,8 @@ struct Work {
     // every outer-loop head, constant while lambda_min runs)
     double *diag, *lin, *zx;
     void *op;            // operand buffer (OpT), column layout as the vectors
-    void *U;             // Q.X output (UT), ksplit slices
+    void *U;             // Q.X output (UT): ksplit slices; the integer path keeps one
+                         // int64 buffer that its K slices add into
     int32_t *active;     // live column list for the next sweep (split: PH_INNER only)
     int32_t *nactive;
     // split precision: lambda_min and CG products use their own FP64 operand
