@@ -71,11 +71,22 @@ def parse():
     return ap.parse_args()
 
 
+def code_only(text: str) -> str:
+    """Source text without // comments and blank lines (comments do not change
+    the kernel the traffic counters measured)."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            out.append(code)
+    return "\n".join(out)
+
+
 def step_source_hash():
     h = hashlib.sha256()
     for rel in STEP_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()
 
 
