@@ -244,10 +244,10 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
 // consecutive 16 NT-row blocks of Q and share MT digit tiles, which the whole
 // block copies into LDS once per K step of 64 (double-buffered, rows padded
 // to 80 bytes so that the 16-byte fragment reads do not collide in banks).
-// Each wave then loads only its own Q rows from global memory. The next K
-// step's digit pieces and Q rows are loaded into registers while the current
-// step multiplies. MT must be a multiple of 4 (each thread copies MT / 4
-// pieces of 16 bytes per step).
+// Each wave then loads only its own Q rows from global memory. The digit
+// pieces and Q rows of the next four K steps are in flight in registers
+// while the current step multiplies. MT must be a multiple of 4 (each thread
+// copies MT / 4 pieces of 16 bytes per step).
 template <int MT, int NT> struct DigitLdsShape {
     static constexpr int kMT = MT, kNT = NT, kWR = 4;
     static constexpr int kRows = 4 * 16 * NT;
@@ -310,38 +310,52 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[s][t] = intx4{0, 0, 0, 0};
         if (kb < ke) {
-            intx4 an[PC], b[NT], bn[NT];
+            // A ring of PF register stages: the loads of K step s + PF are
+            // issued while step s multiplies, and a step's digit pieces go to
+            // LDS (double buffer, one barrier per step) only when the step
+            // comes up. Loads past the last step reread it (in bounds).
+            constexpr int PF = 4;
+            const int nst = (int)((ke - kb) / 64);
+            intx4 ra[PF][PC], rb[PF][NT];
+            auto issue = [&](intx4 (&xa)[PC], intx4 (&xb)[NT], int s) {
+                const int64_t k = kb + 64 * (int64_t)min(s, nst - 1);
 #pragma unroll
-            for (int q = 0; q < PC; ++q) an[q] = ld16(af[q] + kb);
+                for (int q = 0; q < PC; ++q) xa[q] = ld16(af[q] + k);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = ag == ag0 ? bpre[t] : ld16(bq[t] + kb);
+                for (int t = 0; t < NT; ++t) xb[t] = ld16(bq[t] + k);
+            };
 #pragma unroll
-            for (int q = 0; q < PC; ++q) *(intx4 *)&As[0][ao[q]] = an[q];
-            __syncthreads();
-            int buf = 0;
-            for (int64_t k = kb; k < ke; k += 64) {
-                const bool more = k + 64 < ke;  // uniform
-                const int64_t kn = more ? k + 64 : k;
+            for (int u = 0; u < PF; ++u) {
+                if (u == 0 && ag == ag0) {  // the first step's Q rows are already loaded
 #pragma unroll
-                for (int q = 0; q < PC; ++q) an[q] = ld16(af[q] + kn);
+                    for (int q = 0; q < PC; ++q) ra[0][q] = ld16(af[q] + kb);
 #pragma unroll
-                for (int t = 0; t < NT; ++t) bn[t] = ld16(bq[t] + kn);
-                intx4 a[MT];
-#pragma unroll
-                for (int s = 0; s < MT; ++s) a[s] = *(const intx4 *)&As[buf][(s * 16 + m) * ROWB + 16 * g];
-#pragma unroll
-                for (int s = 0; s < MT; ++s)
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], b[t], acc[s][t], 0, 0, 0);
-                if (more) {
-#pragma unroll
-                    for (int q = 0; q < PC; ++q) *(intx4 *)&As[buf ^ 1][ao[q]] = an[q];
+                    for (int t = 0; t < NT; ++t) rb[0][t] = bpre[t];
+                } else {
+                    issue(ra[u], rb[u], u);
                 }
-                __syncthreads();
-                buf ^= 1;
+            }
+            for (int s0 = 0; s0 < nst; s0 += PF) {
 #pragma unroll
-                for (int t = 0; t < NT; ++t) b[t] = bn[t];
+                for (int u = 0; u < PF; ++u) {
+                    if (s0 + u >= nst) break;  // uniform
+                    // step s0 + u uses LDS buffer u & 1 (PF is even)
+#pragma unroll
+                    for (int q = 0; q < PC; ++q) *(intx4 *)&As[u & 1][ao[q]] = ra[u][q];
+                    __syncthreads();
+                    intx4 b[NT];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) b[t] = rb[u][t];
+                    issue(ra[u], rb[u], s0 + u + PF);
+                    intx4 a[MT];
+#pragma unroll
+                    for (int s = 0; s < MT; ++s) a[s] = *(const intx4 *)&As[u & 1][(s * 16 + m) * ROWB + 16 * g];
+#pragma unroll
+                    for (int s = 0; s < MT; ++s)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], b[t], acc[s][t], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
