@@ -241,3 +241,23 @@ def test_batched_lobpcg_long_columns_match_dense_eigensolver(P, n, B, qdt):
               flush=True)
         assert r.trace[c, 0, 1] == I.sum()
         assert abs(got - lam) <= 1e-5 * abs(lam)
+
+
+@pytest.mark.parametrize("qdt", ["f64", "i8"])
+def test_solutions_against_golden_optima(P, qdt):
+    """Every solution of the brute-force set (n = 16..20) is at least the
+    stored exact optimum (tests/golden), and the set as a whole stays in the
+    quality band the oracle meets; the group launch (F64) gives the same."""
+    from golden_data import bruteforce_optima
+    gold = bruteforce_optima()
+    cases = gen.bruteforce_set()
+    objs = [int(P.solve(_t(Q), _t(b), qx_dtype=qdt).obj[0]) for _, Q, b in cases]
+    if qdt == "f64":
+        _, gobj, _ = P.solve_group([_t(Q) for _, Q, _ in cases], [_t(b) for _, _, b in cases])
+        assert gobj.cpu().numpy().tolist() == objs
+    opts = [gold[seed][1] for seed, _, _ in cases]
+    assert all(o >= g for o, g in zip(objs, opts))
+    hits = sum(o == g for o, g in zip(objs, opts))
+    gap = np.mean([(o - g) / abs(g) * 100.0 for o, g in zip(objs, opts)])
+    print(f"{qdt}: {hits}/{len(cases)} optimal, mean GAP {gap:.3f}%", flush=True)
+    assert hits >= 35 and gap < 1.0
