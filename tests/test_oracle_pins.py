@@ -296,6 +296,32 @@ def test_lambda_shift_law_and_generalized_eig():
     assert abs(lam_after - (lam - alpha)) <= 1e-9 * abs(lam)
 
 
+def test_lambda_min_closed_form_tridiagonal():
+    # eq. (alpha): lambda_min(Z_II^{-1/2} Qbar_II Z_II^{-1/2}). With
+    # Qbar_II = Z^{1/2} T Z^{1/2} for the tridiagonal Toeplitz T = tridiag(c, a, c)
+    # the scaled matrix is T on each run of consecutive interior indices,
+    # whose eigenvalues are a + 2c cos(k pi / (m + 1)) (closed form, no LAPACK).
+    rng = np.random.default_rng(8)
+    n, a, c = 40, 3.0, -1.25
+    x = rng.uniform(0.05, 0.95, n)
+    x[[12, 13, 30]] = [0.0, 1.0, 0.0]          # runs of interior indices: 12, 16, 9
+    z = x - x * x
+    p = rng.uniform(-2.0, 2.0, n)
+    T = np.diag(np.full(n, a)) + np.diag(np.full(n - 1, c), 1) + np.diag(np.full(n - 1, c), -1)
+    sz = np.sqrt(np.where((x > 0) & (x < 1), z, 1.0))
+    Q_r = sz[:, None] * T * sz[None, :] + np.diag(p)   # so Q_r - Diag p = Z^{1/2} T Z^{1/2}
+    lam, I, zI = O.lambda_min_scaled(Q_r, p, x)
+    assert I.sum() == n - 3 and np.allclose(zI, z[I])
+    runs = [12, 16, 9]
+    expect = min(a + 2.0 * c * math.cos(math.pi / (m + 1)) for m in runs)  # c < 0: k = 1 is the least
+    assert abs(lam - expect) < 1e-12 * (abs(a) + 2 * abs(c))
+    # with every index interior the single run has length n
+    x2 = np.full(n, 0.5)
+    Q2 = 0.25 * T + np.diag(p)
+    lam2, _, _ = O.lambda_min_scaled(Q2, p, x2)
+    assert abs(lam2 - (a + 2.0 * c * math.cos(math.pi / (n + 1)))) < 1e-12 * (abs(a) + 2 * abs(c))
+
+
 def test_theorem3_large_penalty_gives_binary_local_minima():
     # Lemma 2 / Theorem 3: for p_i > (Q_r)_ii every local minimum is binary and
     # the global box minimum equals the binary optimum
