@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--qx", default="i8", choices=["i8", "f32", "f64"])
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--gemm-yardstick", action="store_true",
+                    help="time the library's digit product next to hipBLASLt's int8 GEMM of the same shape")
     return ap.parse_args()
 
 
@@ -113,6 +115,44 @@ def calibrate_copy():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
+
+
+def gemm_yardstick(n=2500, counts=(16, 64, 256), reps=10):
+    """The subproblem product of B columns (4 B digit rows of length ldq
+    against the int8 Q) through the library's stand-alone digit product,
+    next to hipBLASLt's int8 GEMM (torch._int_mm, int32 result) of the same
+    [4 B x ldq] x [ldq x ldq] shape. The stand-alone call also validates its
+    inputs on the host, so only a kernel trace (rocprofv3 --kernel-trace
+    --stats) compares the two kernels; the HIP events here time the GEMM."""
+    import numpy as np
+    import torch
+    import paper_2408_04875_amd as P
+    from workloads import gen
+
+    P.load()
+    ld = (n + 63) // 64 * 64
+    Q, _, X = gen.sparse_2500_starts(n=n, B=max(counts))
+    Qd = torch.from_numpy(Q).cuda()
+    out = []
+    for B in counts:
+        Xd = torch.from_numpy(np.ascontiguousarray(X[:B])).cuda()
+        for _ in range(reps):
+            P.qx_digits(Qd, Xd, digits=4)
+        g = torch.Generator(device="cuda").manual_seed(B)
+        A8 = torch.randint(-64, 65, (4 * B, ld), dtype=torch.int8, device="cuda", generator=g)
+        B8 = torch.randint(-127, 128, (ld, ld), dtype=torch.int8, device="cuda", generator=g)
+        torch._int_mm(A8, B8)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch._int_mm(A8, B8)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out.append({"columns": B, "digit_rows": 4 * B, "k": ld, "q_rows": ld,
+                    "int_mm_us_events": us, "int8_tops": 2.0 * 4 * B * ld * ld / us * 1e-6})
+    print(json.dumps({"gemm_yardstick": out, "n": n}), flush=True)
 
 
 def cpu_baseline(Q, b, X0, budget_s=20.0):
@@ -190,6 +230,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.gemm_yardstick:
+        gemm_yardstick(n=args.n)
         return
     import numpy as np
     import torch
