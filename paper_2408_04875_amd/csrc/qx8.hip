@@ -335,28 +335,37 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
                     issue(ra[u], rb[u], u);
                 }
             }
-            for (int s0 = 0; s0 < nst; s0 += PF) {
+            // step s uses ring stage s % PF and LDS buffer s & 1 (PF is even)
+            auto step = [&](int u, bool refill, int snext) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
-                    if (s0 + u >= nst) break;  // uniform
-                    // step s0 + u uses LDS buffer u & 1 (PF is even)
+                for (int q = 0; q < PC; ++q) *(intx4 *)&As[u & 1][ao[q]] = ra[u][q];
+                __syncthreads();
+                intx4 b[NT];
 #pragma unroll
-                    for (int q = 0; q < PC; ++q) *(intx4 *)&As[u & 1][ao[q]] = ra[u][q];
-                    __syncthreads();
-                    intx4 b[NT];
+                for (int t = 0; t < NT; ++t) b[t] = rb[u][t];
+                if (refill) issue(ra[u], rb[u], snext);
+                intx4 a[MT];
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) b[t] = rb[u][t];
-                    issue(ra[u], rb[u], s0 + u + PF);
-                    intx4 a[MT];
+                for (int s = 0; s < MT; ++s) a[s] = *(const intx4 *)&As[u & 1][(s * 16 + m) * ROWB + 16 * g];
 #pragma unroll
-                    for (int s = 0; s < MT; ++s) a[s] = *(const intx4 *)&As[u & 1][(s * 16 + m) * ROWB + 16 * g];
+                for (int s = 0; s < MT; ++s)
 #pragma unroll
-                    for (int s = 0; s < MT; ++s)
+                    for (int t = 0; t < NT; ++t)
+                        acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], b[t], acc[s][t], 0, 0, 0);
+            };
+            // whole groups of PF steps in a loop with a single path through
+            // its body (an early exit inside it made the compiler copy the
+            // ring registers at the back edge and wait for every load in
+            // flight), then the last nst % PF steps from the filled ring
+            const int nfull = nst / PF * PF;
+            for (int s0 = 0; s0 < nfull; s0 += PF) {
 #pragma unroll
-                        for (int t = 0; t < NT; ++t)
-                            acc[s][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], b[t], acc[s][t], 0, 0, 0);
-                }
+                for (int u = 0; u < PF; ++u) step(u, true, s0 + u + PF);
             }
+            const int rest = nst - nfull;  // uniform
+#pragma unroll
+            for (int u = 0; u < PF - 1; ++u)
+                if (u < rest) step(u, false, 0);
         }
 #pragma unroll
         for (int s = 0; s < MT; ++s) {
@@ -400,9 +409,12 @@ template <int D, int MT, int NT> struct DigitBody<D, DigitLdsShape<MT, NT>> {
 __device__ __forceinline__ int xcd_order(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
 // The 4-digit product (subproblem columns) in the first nb1 blocks, the
-// 8-digit product (lambda_min / CG columns) in the next nb2.
+// 8-digit product (lambda_min / CG columns) in the next nb2. At most 256
+// registers per lane, so that two blocks share a CU (the many-column layout
+// otherwise takes 312 with the accumulators and runs one wave per SIMD;
+// whole n = 2500 solves are 3% faster with two).
 template <typename S1, typename S2>
-__global__ void __launch_bounds__(kBlock) digit_kernel(DigitArgs a, DigitArgs b, int nb1, int nb2) {
+__global__ void __launch_bounds__(kBlock, 2) digit_kernel(DigitArgs a, DigitArgs b, int nb1, int nb2) {
     const int bx = blockIdx.x;
     if (bx < nb1) DigitBody<4, S1>::run(a, xcd_order(bx, nb1));
     else DigitBody<8, S2>::run(b, xcd_order(bx - nb1, nb2));
