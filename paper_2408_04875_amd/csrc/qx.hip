@@ -56,8 +56,41 @@ __device__ __forceinline__ double row_dot(const QT *q, const double *x, int64_t 
     return acc;
 }
 
-// grid (ceil(n / 4), ncol_max): block = 4 waves = 4 rows of one column.
-template <typename QT>
+// R rows of Q against one x per wave: the lane's x entries are loaded once
+// per K step and feed all R rows, so that x (FP64, two to four times the
+// bytes of a Q entry) is not read again for every row. Each row keeps the
+// summation of row_dot (same lanes, same two accumulators, same order), so
+// the result does not depend on R.
+template <typename QT, int R>
+__device__ __forceinline__ void rows_dot(const QT *q, const double *x, int64_t ld, int lane, double (&out)[R]) {
+    double acc0[R], acc1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc0[r] = acc1[r] = 0.0;
+    for (int64_t j = (int64_t)lane * 4; j < ld; j += 256) {
+        double xv[4];
+        load4(x + j, xv);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double qv[4];
+            load4(q + r * ld + j, qv);
+            acc0[r] = fma(qv[0], xv[0], acc0[r]);
+            acc1[r] = fma(qv[1], xv[1], acc1[r]);
+            acc0[r] = fma(qv[2], xv[2], acc0[r]);
+            acc1[r] = fma(qv[3], xv[3], acc1[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double acc = acc0[r] + acc1[r];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        out[r] = acc;
+    }
+}
+
+// grid (ceil(n / (4 R)), ncol_max): block = 4 waves, R consecutive rows each,
+// of one column; a wave with fewer than R rows left takes them one by one.
+template <typename QT, int R>
 __global__ void __launch_bounds__(kBlock) gemv_kernel(const QT *Qop, int64_t n, int64_t ld,
                                                       const double *op, double *U,
                                                       const int32_t *active,
@@ -66,10 +99,22 @@ __global__ void __launch_bounds__(kBlock) gemv_kernel(const QT *Qop, int64_t n, 
     if (slot >= *nactive) return;
     const int64_t ci = active[slot];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t row = (int64_t)blockIdx.x * kWaves + wv;
-    if (row >= n) return;
-    const double acc = row_dot<QT>(Qop + row * ld, op + ci * ld, ld, lane);
-    if (lane == 0) U[ci * ld + row] = acc;
+    const int64_t row0 = ((int64_t)blockIdx.x * kWaves + wv) * R;
+    if (row0 >= n) return;
+    if (R == 1 || row0 + R <= n) {
+        double acc[R];
+        rows_dot<QT, R>(Qop + row0 * ld, op + ci * ld, ld, lane, acc);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) U[ci * ld + row0 + r] = acc[r];
+        }
+    } else {  // fewer than R rows left: one at a time
+        for (int64_t row = row0; row < n; ++row) {
+            double acc[1];
+            rows_dot<QT, 1>(Qop + row * ld, op + ci * ld, ld, lane, acc);
+            if (lane == 0) U[ci * ld + row] = acc[0];
+        }
+    }
 }
 
 // Flat rows of all columns: rowstart[c] .. rowstart[c+1]-1 belong to column c.
@@ -510,21 +555,26 @@ hipError_t launch_stream2(const void *Qop, int64_t ld, const void *op1, void *U1
 // ---------------------------------------------------------------------------
 // Launchers.
 
+// Four rows per wave once Q no longer fits the caches (n >= 8192: 256 MB in
+// FP32), one row per wave below (more blocks for the smaller grids).
+template <typename QT, int R>
+static void gemv_go(const Inst *in, const Work &w, int ncol_max, hipStream_t st) {
+    const dim3 grid((unsigned)((in->n + kWaves * R - 1) / (kWaves * R)), (unsigned)ncol_max);
+    hipLaunchKernelGGL((gemv_kernel<QT, R>), grid, dim3(kBlock), 0, st, (const QT *)in->Qop, in->n, in->ld,
+                       (const double *)w.op, (double *)w.U, w.active, w.nactive);
+}
+
+template <typename QT>
+static void gemv_pick(const Inst *in, const Work &w, int ncol_max, hipStream_t st) {
+    if (in->n >= 8192) gemv_go<QT, 4>(in, w, ncol_max, st);
+    else gemv_go<QT, 1>(in, w, ncol_max, st);
+}
+
 hipError_t launch_gemv(int dtype, const Inst *in, int, const Work &w, int ncol_max,
                        hipStream_t st) {
-    const dim3 grid((unsigned)((in->n + kWaves - 1) / kWaves), (unsigned)ncol_max);
-    const double *op = (const double *)w.op;
-    double *U = (double *)w.U;
-    if (dtype == PSDP_F64)
-        hipLaunchKernelGGL(gemv_kernel<double>, grid, dim3(kBlock), 0, st, (const double *)in->Qop,
-                           in->n, in->ld, op, U, w.active, w.nactive);
-    else if (dtype == PSDP_F32)
-        hipLaunchKernelGGL(gemv_kernel<float>, grid, dim3(kBlock), 0, st, (const float *)in->Qop,
-                           in->n, in->ld, op, U, w.active, w.nactive);
-    else
-        hipLaunchKernelGGL(gemv_kernel<__hip_bfloat16>, grid, dim3(kBlock), 0, st,
-                           (const __hip_bfloat16 *)in->Qop, in->n, in->ld, op, U, w.active,
-                           w.nactive);
+    if (dtype == PSDP_F64) gemv_pick<double>(in, w, ncol_max, st);
+    else if (dtype == PSDP_F32) gemv_pick<float>(in, w, ncol_max, st);
+    else gemv_pick<__hip_bfloat16>(in, w, ncol_max, st);
     return hipGetLastError();
 }
 
