@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-gemv", action="store_true")
+    ap.add_argument("--gemv-only", action="store_true", help="only the large single-instance GEMV leg")
     ap.add_argument("--qx", default="i8", choices=["i8", "f32", "f64"])
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--gemm-yardstick", action="store_true",
@@ -223,6 +225,34 @@ def sparse_leg(P, gen, torch, dev, n=8000, p_edge=0.005, B=16):
                               "frac": halves * per_half / qs / 1e9 / PEAK_HBM_GBS if qs > 0 else 0.0}}
 
 
+def gemv_leg(P, gen, torch, dev, n=16384, outer=3):
+    """Single-instance solves (one start) on a Q too large for the caches
+    (n = 16384: 1.07 GB in FP32, 0.54 GB in BF16 against 256 MB of Infinity
+    Cache), a few penalty updates each: the product is the GEMV kernel
+    reading all of Q once per evaluation or lambda_min matvec."""
+    import numpy as np
+    Q, b = gen.sparse_int(n, 5)
+    Qd, bd = torch.from_numpy(Q).to(dev), torch.from_numpy(b).to(dev)
+    del Q
+    x0 = torch.from_numpy(gen.random_box_points(n, 1, 6)).to(dev)
+    ld = (n + 15) // 16 * 16
+    out = {"workload": f"one start, n={n}, 10% density ints +-[1,100], b=0, {outer} penalty updates"}
+    for qx, eb in (("f32", 4), ("bf16", 2)):
+        r = P.solve(Qd, bd, X0=x0, qx_dtype=qx, max_outer=outer, timing=1)
+        s0 = r.stats[0]
+        products = s0["inner_iters"] + s0["aux_matvecs"]
+        secs = s0["qx_seconds"] + s0["aux_seconds"]
+        launches = s0["qx_launches"]
+        per = n * ld * eb  # Q bytes per product (x, 8n bytes, stays in cache)
+        out[qx] = {"kernel": f"gemv_kernel<{'float' if qx == 'f32' else '__hip_bfloat16'}, 4>",
+                   "bound": "hbm", "products": int(products), "launches": int(launches),
+                   "avg_launch_us": secs / max(launches, 1) * 1e6, "bytes_per_product": per,
+                   "achieved": products * per / secs / 1e9 if secs > 0 else 0.0, "peak": PEAK_HBM_GBS,
+                   "unit": "GB/s", "frac": products * per / secs / 1e9 / PEAK_HBM_GBS if secs > 0 else 0.0,
+                   "note": "bytes of the launches that had a live column over the time of all launches"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -242,6 +272,9 @@ def main():
 
     dev = torch.device("cuda:0")
     P.load()
+    if args.gemv_only:
+        print(json.dumps({"gemv": gemv_leg(P, gen, torch, dev)}), flush=True)
+        return
     n, B = args.n, args.starts
     # Timed step j solves start set START_SEED + j on the same Q: the length
     # of a solve is set by its slowest start, which moves a lot between start
@@ -358,6 +391,8 @@ def main():
                         "plain_evals_matching": int(sum(pe[k] for k in same))}
     if not args.no_sparse and args.qx == "i8":
         out["sparse"] = sparse_leg(P, gen, torch, dev)
+    if not args.no_gemv:
+        out["gemv"] = gemv_leg(P, gen, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Q, b, X0)
     print(json.dumps(out), flush=True)
