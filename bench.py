@@ -136,6 +136,7 @@ def gemm_yardstick(n=2500, counts=(16, 64, 256), reps=10):
     ld = (n + 63) // 64 * 64
     Q, _, X = gen.sparse_2500_starts(n=n, B=max(counts))
     Qd = torch.from_numpy(Q).cuda()
+    del Q
     out = []
     for B in counts:
         Xd = torch.from_numpy(np.ascontiguousarray(X[:B])).cuda()
@@ -264,6 +265,7 @@ def main():
         return
     if args.gemm_yardstick:
         gemm_yardstick(n=args.n)
+        gemm_yardstick(n=16384, counts=(256,))
         return
     import numpy as np
     import torch
