@@ -288,3 +288,27 @@ def test_large_single_instance_gemv_matches_group_path(P, qdt):
     for key in ("inner_iters", "aux_matvecs", "outer_iters", "exit_reason"):
         assert s1[key] == s2[key], key
     assert one.stats[0]["inner_iters"] > 0
+
+
+def test_full_size_batched_workload(P):
+    """The benchmark's workload at full size (n = 2500, 10% density, 256
+    starts, I8 products, the default launch configuration): the exact
+    invariants of every column, the best-of-batch index, and three sampled
+    starts solved alone through the single-instance path with equal results
+    (the batched launch performs the same arithmetic per column)."""
+    Q, b, X0 = gen.sparse_2500_starts()
+    r = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8")
+    _invariants(Q, b, r)
+    obj = r.obj.cpu().numpy()
+    assert r.best == int(np.argmin(obj))
+    assert len({s["sweeps"] for s in r.stats}) == 1
+    assert all(s["inner_iters"] > 0 and s["outer_iters"] > 0 for s in r.stats)
+    xh = r.xhat.cpu().numpy()
+    for c in (0, 100, 255):
+        one = P.solve(_t(Q), _t(b), X0=_t(X0[c]), qx_dtype="i8")
+        assert int(one.obj[0]) == int(obj[c])
+        assert np.array_equal(one.xhat.cpu().numpy().reshape(-1), xh[c])
+        for key in ("inner_iters", "aux_matvecs", "outer_iters", "exit_reason"):
+            assert one.stats[0][key] == r.stats[c][key], (c, key)
+    print(f"n=2500 B=256: best {obj.min()} (start {r.best}), mean {obj.mean():.1f}, sweeps {r.stats[0]['sweeps']}",
+          flush=True)
