@@ -161,13 +161,13 @@ constexpr double kMainScale = 134217728.0;  // 2^27: iterate grid of the 4-digit
 constexpr int kAuxBits = 55;                // 8-digit operand: v 2^(55 - e) rounded
 // The plane pointers are formed before the element offset is added, so with
 // a uniform p and plane every store takes a scalar base and one 32-bit
-// offset.
-__device__ __forceinline__ void put_digits4(int8_t *p, int64_t plane, uint32_t i, int64_t T) {
-    const int64_t d0 = (T + (1ll << 20)) >> 21;
+// offset. The digit arithmetic is 32-bit (|T| + 2^20 < 2^31).
+__device__ __forceinline__ void put_digits4(int8_t *p, int64_t plane, uint32_t i, int32_t T) {
+    const int32_t d0 = (T + (1 << 20)) >> 21;
     T -= d0 << 21;
-    const int64_t d1 = (T + (1ll << 13)) >> 14;
+    const int32_t d1 = (T + (1 << 13)) >> 14;
     T -= d1 << 14;
-    const int64_t d2 = (T + (1ll << 6)) >> 7;
+    const int32_t d2 = (T + (1 << 6)) >> 7;
     T -= d2 << 7;
     int8_t *p1 = p + plane, *p2 = p + 2 * plane, *p3 = p + 3 * plane;
     p[i] = (int8_t)d0;

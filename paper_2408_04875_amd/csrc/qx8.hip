@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(kBlock) digits_from_vectors_kernel(const doubl
     const double *x = X + c * ldx;
     int8_t *p = dig + c * D * ldq;
     if constexpr (D == 4) {
-        for (int64_t i = threadIdx.x; i < n; i += kBlock) put_digits4(p, ldq, (uint32_t)i, __double2ll_rn(x[i] * kMainScale));
+        for (int64_t i = threadIdx.x; i < n; i += kBlock) put_digits4(p, ldq, (uint32_t)i, (int32_t)__double2ll_rn(x[i] * kMainScale));
     } else {
         __shared__ double red[kWaves];
         double mx[1] = {0.0};

@@ -170,7 +170,7 @@ template <typename OpT>
 __device__ __forceinline__ void put_main(const Work &w, const Col &c, const ColView &cv, uint32_t i, double v) {
     if constexpr (kDigits<OpT>) {
         const int64_t T = __double2ll_rn(v * kMainScale);
-        put_digits4(main_planes(w, c), uni(c.ld), i, T);
+        put_digits4(main_planes(w, c), uni(c.ld), i, (int32_t)T);
         if (w.tw) uvec(w.tw, cv.off)[i] = (int32_t)T;
     } else {
         uvec((OpT *)w.op, cv.off)[i] = from_f64<OpT>(v);
