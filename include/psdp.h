@@ -120,7 +120,7 @@ typedef struct {
     double lambda_floor_rel;   /* alpha uses max(lambda, lambda_floor_rel * rho) (1e-8) */
     double alpha_min, alpha_max; /* BB step clamp (1e-30, 1e30) */
     double sigma;              /* perturbation standard deviation (absolute) (0) */
-    double eig_tol;            /* LOBPCG relative residual tolerance (1e-9) */
+    double eig_tol;            /* LOBPCG relative residual tolerance (1e-7) */
     double cg_tol;             /* x^0 relative residual tolerance (1e-12) */
     uint64_t seed;             /* perturbation seed */
 } psdp_params;

@@ -502,7 +502,7 @@ void psdp_params_default(psdp_params *p) {
     p->alpha_min = 1e-30;
     p->alpha_max = 1e30;
     p->sigma = 0.0;
-    p->eig_tol = 1e-9;
+    p->eig_tol = 1e-7;
     p->cg_tol = 1e-12;
     p->seed = 0;
 }
