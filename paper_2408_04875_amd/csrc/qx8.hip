@@ -460,12 +460,15 @@ void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks) {
     *blocks = std::max(1, (est + CA - 1) / CA) * (int)((ldq + rows - 1) / rows);
 }
 
-// Measured on gfx950: the many-column layout does best with about 512 blocks
-// in the launch, the few-column layout with 2 slices unless the launch is
-// already large. At most 2 slices in either (the range timed on gfx950).
+// Measured on gfx950 over whole n = 2500 solves: the many-column layout does
+// best with about 512 blocks in the launch and at most 2 slices (3 or 4 were
+// slower), the mid layout with about 1024 blocks and at most 4 slices (1.7%
+// faster solves than 2; 6 or 8 were slower), the few-column layout with 2
+// slices unless the launch is already large.
 int digit_slices(int mt, int blocks_total) {
     blocks_total = std::max(1, blocks_total);
     if (mt <= kLayoutFew) return std::max(1, std::min(2, (1024 + blocks_total / 2) / blocks_total));
+    if (mt == kLayoutMid) return std::max(1, std::min(4, (1024 + blocks_total / 2) / blocks_total));
     return std::max(1, std::min(2, (512 + blocks_total / 2) / blocks_total));
 }
 
