@@ -227,7 +227,7 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
 #pragma unroll
             for (int s = 0; s < MT; ++s) {
                 const int row0 = ag * RA + s * 16 + 4 * g;
-                if (row0 / D >= nact) continue;
+                if (row0 / D >= nact || ce[s] == da.zero_col) continue;  // no store for an empty slot
                 int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
                 Uo += (int64_t)ce[s] * da.ldu;
 #pragma unroll
@@ -370,7 +370,7 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
 #pragma unroll
         for (int s = 0; s < MT; ++s) {
             const int row0 = ag * RA + s * 16 + 4 * g;
-            if (row0 / D >= nact) continue;
+            if (row0 / D >= nact || ce[s] == da.zero_col) continue;  // no store for an empty slot
             int64_t *Uo = (D == 8 && ((row0 >> 2) & 1)) ? da.U1 : da.U0;
             Uo += (int64_t)ce[s] * da.ldu;
 #pragma unroll

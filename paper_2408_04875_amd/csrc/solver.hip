@@ -1086,6 +1086,14 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     if (threadIdx.x == 0) c = w.col[ci];
     __syncthreads();
     const int ph0 = uni(c.phase);
+    // Integer path: the column claims its slot in the next sweep's list for
+    // its current product now, so that the atomic's round trip overlaps the
+    // step; if the step ends the column or moves it to the other product,
+    // the slot is filled with the all-zero column (its product is skipped
+    // on store) and, when still live, a slot of the other list is claimed.
+    const int aux0 = (w.split && ph0 != PH_INNER) ? 1 : 0;
+    int slot0 = 0;
+    if (kDigits<OpT> && ph0 != PH_DONE && threadIdx.x == 0) slot0 = atomicAdd(&w.next_cnt[aux0], 1);
     if (ph0 != PH_DONE) {
         const ColView cv = view(c);
         const unsigned long long t0 = w.phase_prof ? wall_clock64() : 0ull;
@@ -1102,8 +1110,15 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
             // a live column takes a slot in the next sweep's list; the
             // products read the lists after this kernel has ended, so the
             // slots need no ordering with anything else written here
-            if (c.phase != PH_DONE) {
-                const int aux = (w.split && c.phase != PH_INNER) ? 1 : 0;
+            const bool live = c.phase != PH_DONE;
+            const int aux = (w.split && c.phase != PH_INNER) ? 1 : 0;
+            if (kDigits<OpT>) {
+                (aux0 ? w.next_active_aux : w.next_active)[slot0] = (live && aux == aux0) ? ci : w.ncol;
+                if (live && aux != aux0) {
+                    const int slot = atomicAdd(&w.next_cnt[aux], 1);
+                    (aux ? w.next_active_aux : w.next_active)[slot] = ci;
+                }
+            } else if (live) {
                 const int slot = atomicAdd(&w.next_cnt[aux], 1);
                 (aux ? w.next_active_aux : w.next_active)[slot] = ci;
             }

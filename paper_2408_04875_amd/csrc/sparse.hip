@@ -128,6 +128,7 @@ __device__ __forceinline__ void sparse_row(const SparseArgs &a, int64_t i) {
 #pragma unroll
             for (int q = 0; q < kSparseGroup; ++q) {
                 if (c0 + q >= nact) break;
+                if (col[q] == a.zero_col) continue;  // an empty slot of the list
                 a.U0[col[q] * a.ldu + i] = s0[q];
                 if (H == 2) a.U1[col[q] * a.ldu + i] = s1[q];
             }
