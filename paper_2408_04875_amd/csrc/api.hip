@@ -914,7 +914,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     for (int i = 0; i < count; ++i) {
         ld[i] = padld(n[i]);
         off[i + 1] = off[i] + ld[i];
-        rowstart[i + 1] = rowstart[i] + n[i];
+        rowstart[i + 1] = rowstart[i] + (n[i] + 3) / 4;  // units of 4 rows of the group product
     }
     const int64_t total = off[count];
     double *bd, *gam, *R, *dq;

@@ -117,7 +117,9 @@ __global__ void __launch_bounds__(kBlock) gemv_kernel(const QT *Qop, int64_t n, 
     }
 }
 
-// Flat rows of all columns: rowstart[c] .. rowstart[c+1]-1 belong to column c.
+// Flat work list of all columns in units of 4 rows: units rowstart[c] ..
+// rowstart[c+1]-1 belong to column c (ceil(n_c / 4) of them); a wave takes
+// one unit, rows_dot over its rows (per-row sums as in row_dot).
 template <typename QT>
 __global__ void __launch_bounds__(kBlock) gemv_group_kernel(const Col *col, const Inst *inst,
                                                             const int64_t *rowstart, int ncol,
@@ -135,9 +137,22 @@ __global__ void __launch_bounds__(kBlock) gemv_group_kernel(const Col *col, cons
     const Col &c = col[lo];
     if (c.phase == PH_DONE) return;
     const Inst &in = inst[c.inst];
-    const int64_t row = r - rowstart[lo];
-    const double acc = row_dot<QT>((const QT *)in.Qop + row * in.ld, op + c.off, in.ld, lane);
-    if (lane == 0) U[c.off + row] = acc;
+    const int64_t row0 = (r - rowstart[lo]) * 4;
+    const QT *Q = (const QT *)in.Qop;
+    if (row0 + 4 <= in.n) {
+        double acc[4];
+        rows_dot<QT, 4>(Q + row0 * in.ld, op + c.off, in.ld, lane, acc);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) U[c.off + row0 + k] = acc[k];
+        }
+    } else {
+        for (int64_t row = row0; row < in.n; ++row) {
+            double acc[1];
+            rows_dot<QT, 1>(Q + row * in.ld, op + c.off, in.ld, lane, acc);
+            if (lane == 0) U[c.off + row] = acc[0];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -580,6 +595,7 @@ hipError_t launch_gemv(int dtype, const Inst *in, int, const Work &w, int ncol_m
 
 hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart, int64_t total_rows,
                              hipStream_t st) {
+    // total_rows counts units of 4 rows (rowstart in the same units)
     const dim3 grid((unsigned)((total_rows + kWaves - 1) / kWaves));
     const double *op = (const double *)w.op;
     double *U = (double *)w.U;
