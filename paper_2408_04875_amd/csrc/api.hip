@@ -103,31 +103,9 @@ constexpr int64_t kSparseMinN = 4096;
 bool sparse_worth_building(int64_t n, int64_t nnz) { return n >= kSparseMinN && 64 * nnz <= n * n; }
 bool sparse_batch(int64_t n, int64_t nnz, int live) { return (double)nnz * 2.0 * live <= 0.25 * (double)n * (double)n; }
 
-// Host-side checks of one integer instance (Q and b already copied back).
-// rownnz (optional): the off-diagonal nonzeros of every row.
-psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int32_t> &b, int64_t n,
-                           const psdp_params &p, int64_t *offmax_out = nullptr,
-                           std::vector<int64_t> *rownnz = nullptr) {
-    int64_t qmax = 0, bmax = 0, offmax = 0;
-    if (rownnz) rownnz->assign(n, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        bmax = std::max<int64_t>(bmax, std::llabs((long long)b[i]));
-        for (int64_t j = 0; j < n; ++j) {
-            const int32_t v = Q[i * n + j];
-            if (v != Q[j * n + i]) {
-                char buf[128];
-                snprintf(buf, sizeof buf, "Q[%lld][%lld] != Q[%lld][%lld]", (long long)i, (long long)j,
-                         (long long)j, (long long)i);
-                return fail(PSDP_E_NOT_SYMMETRIC, buf);
-            }
-            const int64_t a = std::llabs((long long)v);
-            qmax = std::max(qmax, a);
-            if (i != j) {
-                offmax = std::max(offmax, a);
-                if (rownnz && v != 0) ++(*rownnz)[i];
-            }
-        }
-    }
+// Limits of one integer instance from its largest magnitudes: the int64
+// objective bound and what each operand type represents exactly.
+psdp_status check_limits(int64_t n, uint64_t qmax, uint64_t offmax, uint64_t bmax, const psdp_params &p) {
     // |f(x)| <= n^2 max|Q| + n max|b| must stay below 2^62
     const long double bound = (long double)n * n * qmax + (long double)n * bmax;
     if (bound >= 4.611686018427388e18L) return fail(PSDP_E_OVERFLOW, "n^2 max|Q| + n max|b| >= 2^62");
@@ -135,13 +113,50 @@ psdp_status check_instance(const std::vector<int32_t> &Q, const std::vector<int3
         return fail(PSDP_E_UNSUPPORTED, "FULL perturbation is not exact in bfloat16 operands");
     if (p.qx_dtype == PSDP_BF16 && offmax > 256)
         return fail(PSDP_E_UNSUPPORTED, "bfloat16 operands need |Q_ij| <= 256 off the diagonal");
-    if (p.qx_dtype == PSDP_F32 && offmax > (1 << 24))
+    if (p.qx_dtype == PSDP_F32 && offmax > (1u << 24))
         return fail(PSDP_E_UNSUPPORTED, "float operands need |Q_ij| <= 2^24 off the diagonal");
     if (p.qx_dtype == PSDP_I8 && offmax > 127)
         return fail(PSDP_E_UNSUPPORTED, "int8 operands need |Q_ij| <= 127 off the diagonal");
     if (p.qx_dtype == PSDP_I8 && p.perturb == PSDP_PERTURB_FULL && p.sigma > 0.0)
         return fail(PSDP_E_UNSUPPORTED, "FULL perturbation is not integer (int8 operands)");
-    if (offmax_out) *offmax_out = offmax;
+    return PSDP_OK;
+}
+
+// Checks of one integer instance on the device (device pointers, stream
+// st), in this order: exact symmetry of Q, the limits above, X0 (nx
+// entries, nullable) in [0,1], p0 (nullable) finite. rownnz (optional): the
+// off-diagonal nonzeros of every row.
+psdp_status check_instance(const int32_t *Q, const int32_t *b, int64_t n, const double *X0, int64_t nx,
+                           const double *p0, const psdp_params &p, hipStream_t st, int64_t *offmax_out = nullptr,
+                           std::vector<int64_t> *rownnz = nullptr) {
+    Arena ar;
+    CheckOut *o;
+    int32_t *rn = nullptr;
+    HIPCHK(ar.get((void **)&o, sizeof(CheckOut)));
+    if (rownnz) {
+        HIPCHK(ar.get((void **)&rn, n * sizeof(int32_t)));
+        HIPCHK(hipMemsetAsync(rn, 0, n * sizeof(int32_t), st));
+    }
+    HIPCHK(launch_check(Q, b, n, X0, nx, p0, o, rn, st));
+    CheckOut h;
+    HIPCHK(hipMemcpyAsync(&h, o, sizeof h, hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> hr;
+    if (rownnz) {
+        hr.resize(n);
+        HIPCHK(hipMemcpyAsync(hr.data(), rn, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (h.first_asym != ~0ull) {
+        const long long i = (long long)(h.first_asym / (uint64_t)n), j = (long long)(h.first_asym % (uint64_t)n);
+        char buf[128];
+        snprintf(buf, sizeof buf, "Q[%lld][%lld] != Q[%lld][%lld]", i, j, j, i);
+        return fail(PSDP_E_NOT_SYMMETRIC, buf);
+    }
+    if (psdp_status s = check_limits(n, h.qmax, h.offmax, h.bmax, p)) return s;
+    if (h.x0_bad) return fail(PSDP_E_NONFINITE, "X0 entries must lie in [0,1]");
+    if (h.p0_bad) return fail(PSDP_E_NONFINITE, "p0 must be finite");
+    if (offmax_out) *offmax_out = (int64_t)h.offmax;
+    if (rownnz) rownnz->assign(hr.begin(), hr.end());
     return PSDP_OK;
 }
 
@@ -544,24 +559,14 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     if (!X0 && B != 1) return fail(PSDP_E_INVALID, "X0 = NULL needs B = 1");
     if (trace && trace_cap < 1) return fail(PSDP_E_INVALID, "trace_cap");
     if (n > 65536) return fail(PSDP_E_UNSUPPORTED, "n > 65536");
-    // validation: one copy of the inputs back to the host
-    std::vector<int32_t> hQ(n * n), hb(n);
-    HIPCHK(hipMemcpyAsync(hQ.data(), Q, n * n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hb.data(), b, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    std::vector<double> hX0, hp0;
-    if (X0) {
-        hX0.resize(n * B);
-        HIPCHK(hipMemcpyAsync(hX0.data(), X0, n * B * sizeof(double), hipMemcpyDeviceToHost, st));
-    }
-    if (p0) {
-        hp0.resize(n);
-        HIPCHK(hipMemcpyAsync(hp0.data(), p0, n * sizeof(double), hipMemcpyDeviceToHost, st));
-    }
-    HIPCHK(hipStreamSynchronize(st));
+    // validation on the device; a few words come back (the caller's stream is
+    // synchronized, so the inputs are ready for the solve stream too)
     int64_t offmax = 0;
     std::vector<int64_t> rownnz;
     const bool want_counts = prm.qx_dtype == PSDP_I8 && prm.sparse != 0;
-    if (psdp_status s = check_instance(hQ, hb, n, prm, &offmax, want_counts ? &rownnz : nullptr)) return s;
+    if (psdp_status s = check_instance(Q, b, n, X0, X0 ? n * B : 0, p0, prm, st, &offmax,
+                                       want_counts ? &rownnz : nullptr))
+        return s;
     std::vector<int32_t> hrowptr;
     bool csr = false;
     int64_t csr_nnz = 0;
@@ -572,10 +577,6 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         csr = fits && (prm.sparse == 1 || sparse_worth_building(n, nnz));
         if (csr) csr_nnz = nnz;
     }
-    for (double v : hX0)
-        if (!(v >= 0.0 && v <= 1.0)) return fail(PSDP_E_NONFINITE, "X0 entries must lie in [0,1]");
-    for (double v : hp0)
-        if (!std::isfinite(v)) return fail(PSDP_E_NONFINITE, "p0 must be finite");
     if (B > 1 && prm.qx_dtype == PSDP_BF16)
         return fail(PSDP_E_UNSUPPORTED, "batched starts support F64 and F32 operands");
     // the inputs are ready (the stream was synchronized above); the solve runs
@@ -894,11 +895,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         if (!Q[i] || !b[i] || !xhat[i]) return fail(PSDP_E_INVALID, "null instance pointer");
     }
     for (int i = 0; i < count; ++i) {
-        std::vector<int32_t> hQ(n[i] * n[i]), hb(n[i]);
-        HIPCHK(hipMemcpyAsync(hQ.data(), Q[i], n[i] * n[i] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(hb.data(), b[i], n[i] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (psdp_status s = check_instance(hQ, hb, n[i], prm)) {
+        if (psdp_status s = check_instance(Q[i], b[i], n[i], nullptr, 0, nullptr, prm, st)) {
             g_err = "instance " + std::to_string(i) + ": " + g_err;
             return s;
         }

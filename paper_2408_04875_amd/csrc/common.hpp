@@ -327,6 +327,16 @@ __device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
 // ---------------------------------------------------------------------------
 // Host-side launchers implemented in the kernel translation units.
 
+// Device-side input checks (check.hip): the first asymmetric entry as
+// i n + j (all ones when Q is symmetric), the largest |Q_ij|, off-diagonal
+// |Q_ij| and |b_i|, and the counts of X0 entries outside [0,1] and of
+// non-finite p0 entries. rownnz (nullable, zeroed beforehand) gets the
+// off-diagonal nonzeros of every row.
+struct CheckOut {
+    uint64_t qmax, offmax, bmax, x0_bad, p0_bad, first_asym;
+};
+hipError_t launch_check(const int32_t *Q, const int32_t *b, int64_t n, const double *X0, int64_t nx,
+                        const double *p0, CheckOut *o, int32_t *rownnz, hipStream_t st);
 hipError_t launch_prep_q(int dtype, const int32_t *Q, int64_t n, int64_t ld, int perturb,
                          double sigma, uint64_t seed, void *Qop, double *R, double *dq,
                          hipStream_t st);

@@ -312,3 +312,42 @@ def test_full_size_batched_workload(P):
             assert one.stats[0][key] == r.stats[c][key], (c, key)
     print(f"n=2500 B=256: best {obj.min()} (start {r.best}), mean {obj.mean():.1f}, sweeps {r.stats[0]['sweeps']}",
           flush=True)
+
+
+def test_input_checks_on_device(P):
+    """The entry points check their inputs on the device before solving:
+    the first asymmetric entry in row-major order (across tiles), X0 outside
+    [0,1] or NaN, a non-finite p0, and the same in the group launch."""
+    Q, b = gen.dense_int(40, 2)
+    bad = Q.copy()
+    bad[3, 17] += 1
+    with pytest.raises(P.PSDPError, match=r"Q\[3\]\[17\] != Q\[17\]\[3\]"):
+        P.solve(_t(bad), _t(b))
+    bad = Q.copy()
+    bad[20, 5] += 1
+    with pytest.raises(P.PSDPError, match=r"Q\[5\]\[20\] != Q\[20\]\[5\]"):
+        P.solve(_t(bad), _t(b))
+    Q2, b2 = gen.sparse_int(1000, 3)
+    bad = Q2.copy()
+    bad[999, 0] += 1
+    bad[700, 650] -= 1
+    with pytest.raises(P.PSDPError, match=r"Q\[0\]\[999\] != Q\[999\]\[0\]"):
+        P.solve(_t(bad), _t(b2), qx_dtype="i8")
+    X0 = gen.random_box_points(40, 3, 1)
+    X0[1, 7] = 1.5
+    with pytest.raises(P.PSDPError, match="X0"):
+        P.solve(_t(Q), _t(b), X0=_t(X0))
+    X0[1, 7] = np.nan
+    with pytest.raises(P.PSDPError, match="X0"):
+        P.solve(_t(Q), _t(b), X0=_t(X0))
+    p0 = np.zeros(40)
+    p0[3] = np.inf
+    with pytest.raises(P.PSDPError, match="p0"):
+        P.solve(_t(Q), _t(b), p0=_t(p0))
+    bad = Q.copy()
+    bad[0, 39] += 1
+    with pytest.raises(P.PSDPError, match=r"instance 1: Q\[0\]\[39\]"):
+        P.solve_group([_t(Q), _t(bad)], [_t(b), _t(b)])
+    # a valid instance still solves, with the same result as before the checks moved
+    r = P.solve(_t(Q), _t(b))
+    assert int(r.obj[0]) == O.solve(Q, b).obj
