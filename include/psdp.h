@@ -165,7 +165,7 @@ int32_t psdp_version(void);
  * X0      device, double, n x B column-major, entries in [0,1]; NULL means
  *         every column starts from x^0 of eq. (gamma) (then B must be 1).
  * p0      device, double, length n, initial penalty of the reformulated
- *         problem (Algorithm 3 line 3 sets 0); NULL means 0.
+ *         problem (Algorithm 3 starts from 0); NULL means 0.
  * B       number of starts (>= 1). B = 1 runs the single-instance path
  *         (GEMV Q.x, FP64 accumulation, Q stored in qx_dtype); B > 1 runs
  *         all starts together (MFMA Q.X per sweep). With B > 1 and F32

@@ -168,7 +168,7 @@ def perturbation(n: int, sigma: float, seed: int, mode: str = "full") -> np.ndar
 
 
 # ---------------------------------------------------------------------------
-# Initialization (Section 3.5, "Reformation"; Algorithm 3 lines 2-3).
+# Initialization (Section 3.5, "Reformation"; Algorithm 3 initialization).
 
 def reformation_gamma(Q, b) -> np.ndarray:
     """gamma_i = 2 sum_j |Q_ij| + |b_i| + 1.
@@ -398,8 +398,8 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
 
     1. Optional symmetric perturbation of Q (Section 3.5), applied before the
        reformation; the final objective always uses the original Q and b.
-    2. Reformation Q_r = Q + Diag(gamma), b_r = b - gamma (Algorithm 3 line 2).
-    3. x^0 from eq. (gamma) (Algorithm 3 line 3) unless x0 is supplied, in
+    2. Reformation Q_r = Q + Diag(gamma), b_r = b - gamma (Algorithm 3, reformation).
+    3. x^0 from eq. (gamma) (Algorithm 3, initial point) unless x0 is supplied, in
        which case x0 replaces it; p^0 = 0 unless p0 is supplied.
     4. While x is not within tol_binary of a 0/1 vector and s < max_outer:
        alpha = eta * max(lambda_min(...), floor) (eqs. (alpha), (alpha1));

@@ -361,7 +361,7 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
 }
 
 // ---------------------------------------------------------------------------
-// End of a subproblem (Algorithm 3 after line 6).
+// End of a subproblem (Algorithm 3, after the subproblem solve).
 
 template <typename OpT, int EPT>
 __device__ void end_subproblem(const Work &w, Col &c, const ColView &cv, double *red, int ci,
