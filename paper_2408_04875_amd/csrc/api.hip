@@ -655,10 +655,13 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     // column data
     const int kmax = (batched && !i8) ? kMaxSplit : 1;  // integer slices add into one buffer
     if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, st, ld)) return s2;
-    if (S.rowptr) {  // the operands' grid values as words, for the sparse products
+    if (S.rowptr) {
+        // the operands' grid values as words, for the sparse products; like
+        // the digit planes they hold one extra all-zero column (index B),
+        // which empty list slots and the slots past the count name
         for (int32_t **pw : {&w.tw, &w.tw_hi, &w.tw_lo}) {
-            HIPCHK(S.ar.get((void **)pw, ld * B * sizeof(int32_t)));
-            HIPCHK(hipMemsetAsync(*pw, 0, ld * B * sizeof(int32_t), st));
+            HIPCHK(S.ar.get((void **)pw, ld * (B + 1) * sizeof(int32_t)));
+            HIPCHK(hipMemsetAsync(*pw, 0, ld * (B + 1) * sizeof(int32_t), st));
         }
     }
     const int MT = (int)((ld + 63) / 64);

@@ -400,7 +400,7 @@ struct SparseJob {
     const int32_t *rowptr;   // n + 1 row starts
     const uint32_t *pk;      // packed nonzeros: column in bits 0-15, int8 value in bits 16-23
     int64_t n;
-    const int32_t *w0, *w1;  // operand words: T, or T_hi and T_lo; column c at c * ldw
+    const int32_t *w0, *w1;  // operand words: T, or T_hi and T_lo; column c at c * ldw, zero_col + 1 columns
     int64_t ldw;
     const int32_t *active;   // live list (zero_col + 1 readable entries) and its device count
     const int32_t *nactive;

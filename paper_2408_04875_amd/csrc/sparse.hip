@@ -74,7 +74,8 @@ struct SparseArgs {
     const int32_t *rowptr;
     const uint32_t *pk;
     int64_t n;
-    const int32_t *w0, *w1;  // operand words: T (main), or T_hi and T_lo (aux); column c at c * ldw
+    const int32_t *w0, *w1;  // operand words: T (main), or T_hi and T_lo (aux); column c at c * ldw,
+                             // zero_col + 1 columns (an empty list slot names the all-zero column)
     int64_t ldw;
     const int32_t *active;   // live list (zero_col + 1 readable entries) and its count
     const int32_t *nactive;
