@@ -27,7 +27,8 @@
  *    evaluation, adjoint and objective entry points are stream-ordered and
  *    return without synchronizing.
  *  - No C++ exception crosses this boundary and nothing aborts. Argument
- *    validation happens before any device work. Reaching an iteration cap is
+ *    validation happens before any solve work (the checks of the data run
+ *    as kernels on the caller's stream). Reaching an iteration cap is
  *    not an error: the status is PSDP_OK and psdp_stats.exit_reason says why
  *    the solve stopped.
  *  - Calls are serialized per process by an internal lock (the solve
@@ -185,7 +186,8 @@ int32_t psdp_version(void);
  *         PSDP_E_UNSUPPORTED (FULL perturbation with BF16 operands; I8
  *         operands with |Q_ij| > 127 off the diagonal or a FULL
  *         perturbation; BF16 with B > 1), PSDP_E_DEVICE / PSDP_E_NOMEM.
- * Validation reads Q, b and X0 back to the host once.
+ * Validation runs on the device (symmetry with the first offending entry,
+ * magnitudes, X0 in [0,1], p0 finite); a few words come back to the host.
  */
 psdp_status psdp_solve_i32(const int32_t *Q, const int32_t *b, int64_t n,
                            const double *X0, const double *p0, int32_t B,
