@@ -958,12 +958,18 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     int64_t *drow;
     HIPCHK(S.ar.get((void **)&drow, (count + 1) * sizeof(int64_t)));
     HIPCHK(hipMemcpyAsync(drow, rowstart.data(), (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    std::vector<int32_t> unitcol(rowstart[count]);  // the column of every unit of 4 rows
+    for (int i = 0; i < count; ++i)
+        std::fill(unitcol.begin() + rowstart[i], unitcol.begin() + rowstart[i + 1], i);
+    int32_t *dunit;
+    HIPCHK(S.ar.get((void **)&dunit, unitcol.size() * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(dunit, unitcol.data(), unitcol.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIPCHK(launch_solver_init(S.optype, w, nullptr, 1, st));
     HIPCHK(launch_compact(w, st));
     QxTimer tm, ta, ts;
     tm.on = ts.on = prm.timing != 0;
     psdp_status rs = run_sweeps(
-        S, prm, tm, ta, ts, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, rowstart[count], st); },
+        S, prm, tm, ta, ts, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, dunit, rowstart[count], st); },
         []() { return hipSuccess; });
     if (rs != PSDP_OK) return rs;
     int64_t maxblk = 0;

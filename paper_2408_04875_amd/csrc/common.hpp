@@ -352,7 +352,7 @@ constexpr int kGemmF32QF64 = 16;
 // Q.X products. U receives sum_j Qop[i][j] * op[j] for every live column.
 hipError_t launch_gemv(int dtype, const Inst *inst_host, int ninst_same, const Work &w,
                        int ncol_max, hipStream_t st);
-hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart,
+hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart, const int32_t *unitcol,
                              int64_t total_rows, hipStream_t st);
 hipError_t launch_stream(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
                          const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,

@@ -118,22 +118,19 @@ __global__ void __launch_bounds__(kBlock) gemv_kernel(const QT *Qop, int64_t n, 
 }
 
 // Flat work list of all columns in units of 4 rows: units rowstart[c] ..
-// rowstart[c+1]-1 belong to column c (ceil(n_c / 4) of them); a wave takes
-// one unit, rows_dot over its rows (per-row sums as in row_dot).
+// rowstart[c+1]-1 belong to column c (ceil(n_c / 4) of them), and unitcol
+// names the column of every unit (one load instead of a search, which
+// matters late in a solve, when most units belong to finished columns and
+// only look up their column and leave); a wave takes one unit, rows_dot
+// over its rows (per-row sums as in row_dot).
 template <typename QT>
 __global__ void __launch_bounds__(kBlock) gemv_group_kernel(const Col *col, const Inst *inst,
-                                                            const int64_t *rowstart, int ncol,
-                                                            int64_t total, const double *op,
-                                                            double *U) {
+                                                            const int64_t *rowstart, const int32_t *unitcol,
+                                                            int64_t total, const double *op, double *U) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * kWaves + wv;
     if (r >= total) return;
-    int lo = 0, hi = ncol - 1;  // last c with rowstart[c] <= r
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (rowstart[mid] <= r) lo = mid;
-        else hi = mid - 1;
-    }
+    const int lo = unitcol[r];
     const Col &c = col[lo];
     if (c.phase == PH_DONE) return;
     const Inst &in = inst[c.inst];
@@ -593,21 +590,21 @@ hipError_t launch_gemv(int dtype, const Inst *in, int, const Work &w, int ncol_m
     return hipGetLastError();
 }
 
-hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart, int64_t total_rows,
-                             hipStream_t st) {
+hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart, const int32_t *unitcol,
+                             int64_t total_rows, hipStream_t st) {
     // total_rows counts units of 4 rows (rowstart in the same units)
     const dim3 grid((unsigned)((total_rows + kWaves - 1) / kWaves));
     const double *op = (const double *)w.op;
     double *U = (double *)w.U;
     if (dtype == PSDP_F64)
         hipLaunchKernelGGL(gemv_group_kernel<double>, grid, dim3(kBlock), 0, st, w.col, w.inst,
-                           rowstart, w.ncol, total_rows, op, U);
+                           rowstart, unitcol, total_rows, op, U);
     else if (dtype == PSDP_F32)
         hipLaunchKernelGGL(gemv_group_kernel<float>, grid, dim3(kBlock), 0, st, w.col, w.inst,
-                           rowstart, w.ncol, total_rows, op, U);
+                           rowstart, unitcol, total_rows, op, U);
     else
         hipLaunchKernelGGL(gemv_group_kernel<__hip_bfloat16>, grid, dim3(kBlock), 0, st, w.col,
-                           w.inst, rowstart, w.ncol, total_rows, op, U);
+                           w.inst, rowstart, unitcol, total_rows, op, U);
     return hipGetLastError();
 }
 
