@@ -5,10 +5,11 @@
 // columns c listed in `active` (Qop: zero-diagonal operand copy, row-major,
 // leading dimension ld, a multiple of 16 with zero padding).
 //
-//  gemv_kernel        one instance, few columns: one wave per row, 16-byte
-//                     coalesced loads of Q, FP64 accumulation, x in FP64.
-//  gemv_group_kernel  uneven instances: the rows of every live instance form
-//                     one flat work list (one wave per row).
+//  gemv_kernel        one instance, few columns: one wave per row (four
+//                     from n = 8192), 16-byte coalesced loads of Q, FP64
+//                     accumulation, x in FP64.
+//  gemv_group_kernel  uneven instances: the rows of every instance form one
+//                     flat work list of four-row units (one wave per unit).
 //  gemm_*_kernel      one instance, many columns: MFMA tiles (FP32 16x16x4 or
 //                     FP64 16x16x4) staged through LDS, split over K into
 //                     separate output slices that the solver sums in order.
