@@ -53,9 +53,14 @@ __global__ void __launch_bounds__(256) check_q_kernel(const int32_t *Q, int64_t 
         omax = max(omax, (uint64_t)__shfl_xor((long long)omax, off, 64));
         bad = min(bad, (uint64_t)__shfl_xor((long long)bad, off, 64));
     }
+    // lane 0 of every wave updates the totals, and only where it would
+    // change them (a relaxed read filters the contended atomics: the totals
+    // only grow, so a stale read costs at most one atomic more)
     if ((threadIdx.x & 63) == 0) {
-        if (amax) atomicMax((unsigned long long *)&o->qmax, (unsigned long long)amax);
-        if (omax) atomicMax((unsigned long long *)&o->offmax, (unsigned long long)omax);
+        if (amax > __hip_atomic_load(&o->qmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax((unsigned long long *)&o->qmax, (unsigned long long)amax);
+        if (omax > __hip_atomic_load(&o->offmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax((unsigned long long *)&o->offmax, (unsigned long long)omax);
         if (bad != ~0ull) atomicMin((unsigned long long *)&o->first_asym, (unsigned long long)bad);
     }
 }
