@@ -1,12 +1,13 @@
 """Writes the stored expected values under tests/golden/.
 
 bruteforce_n16_20.txt: the exact minimum and minimizer of every instance of
-the seeded brute-force set, by exhaustive enumeration over {0,1}^n. Run from
-the repository root:
+the seeded brute-force set, by exhaustive enumeration over {0,1}^n.
+oracle_n1000_single.txt: the oracle's solve of the n = 1000 single instance
+(its objective and iteration counts). Run from the repository root:
 
     python tests/golden/make_golden.py
 
-Uses only the oracle's enumeration and the seeded instance generators.
+Uses only the oracle and the seeded instance generators.
 """
 import os
 import sys
@@ -27,7 +28,21 @@ HEADER = """\
 """
 
 
+HEADER_N1000 = """\
+# The oracle's solve (Algorithm 3 with PABB, FP64) of the single instance of
+# n = 1000 at 10% density (nonzeros +-{1..100}, b = 0, workloads seed 1) from
+# x^0 of eq. (gamma), with the subproblem cap at 1000 iterations.
+# Written by tests/golden/make_golden.py.
+# columns: objective outer_iterations inner_iterations exit_reason
+"""
+
+
 def main():
+    from oracle import psdp as O
+    Q, b = gen.sparse_1000()
+    r = O.solve(Q, b, O.Params(max_inner=1000))
+    with open(os.path.join(HERE, "oracle_n1000_single.txt"), "w") as f:
+        f.write(HEADER_N1000 + f"{r.obj} {r.outer_iters} {r.inner_iters} {r.exit_reason}\n")
     lines = [HEADER.rstrip("\n")]
     for seed, Q, b in gen.bruteforce_set():
         opt, x = brute_force(Q, b)
