@@ -408,7 +408,6 @@ struct SparseJob {
     int64_t *U0, *U1;        // outputs (U1 for the low half), column c at c * ldu
     int64_t ldu;
 };
-hipError_t launch_csr_count(const int8_t *Q8, int64_t ldq, int64_t n, int32_t *cnt, hipStream_t st);
 hipError_t launch_csr_fill(const int8_t *Q8, int64_t ldq, int64_t n, const int32_t *rowptr, uint32_t *pk,
                            hipStream_t st);
 hipError_t launch_sparse(const SparseJob *main4, const SparseJob *aux8, hipStream_t st);

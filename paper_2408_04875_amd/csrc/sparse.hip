@@ -21,21 +21,8 @@ namespace psdp {
 
 // ---------------------------------------------------------------------------
 // Building the rows from the int8 operand copy (row-major, leading dimension
-// ldq, zero diagonal).
-
-__global__ void __launch_bounds__(kBlock) csr_count_kernel(const int8_t *Q8, int64_t ldq, int64_t n, int32_t *cnt) {
-    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= n) return;
-    const int8_t *row = Q8 + i * ldq;
-    int c = 0;
-    for (int64_t j0 = 0; j0 < n; j0 += 64) {
-        const int64_t j = j0 + lane;
-        const bool nz = j < n && row[j] != 0;
-        c += __popcll(__ballot(nz));
-    }
-    if (lane == 0) cnt[i] = c;
-}
+// ldq, zero diagonal); the row starts come from the row nonzero counts of the
+// input checks.
 
 __global__ void __launch_bounds__(kBlock) csr_fill_kernel(const int8_t *Q8, int64_t ldq, int64_t n,
                                                           const int32_t *rowptr, uint32_t *pk) {
@@ -52,12 +39,6 @@ __global__ void __launch_bounds__(kBlock) csr_fill_kernel(const int8_t *Q8, int6
         if (v != 0) pk[pos + __popcll(m & below)] = (uint32_t)j | ((uint32_t)(uint8_t)v << 16);
         pos += __popcll(m);
     }
-}
-
-hipError_t launch_csr_count(const int8_t *Q8, int64_t ldq, int64_t n, int32_t *cnt, hipStream_t st) {
-    const unsigned grid = (unsigned)((n + kBlock / 64 - 1) / (kBlock / 64));
-    hipLaunchKernelGGL(csr_count_kernel, dim3(grid), dim3(kBlock), 0, st, Q8, ldq, n, cnt);
-    return hipGetLastError();
 }
 
 hipError_t launch_csr_fill(const int8_t *Q8, int64_t ldq, int64_t n, const int32_t *rowptr, uint32_t *pk,
