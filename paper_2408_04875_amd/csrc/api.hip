@@ -189,6 +189,11 @@ struct Solver {
     Work w{};
     std::function<void(int, int)> repick;  // adapts the product kernels to the live counts
     std::function<int64_t()> config_key;   // identifies the current product configuration
+    // when set, each poll also copies the first list_cap entries of the main
+    // live list, and relist receives the list and its count (a superset of the
+    // columns still live when it runs)
+    std::function<hipError_t(const int32_t *, int)> relist;
+    int32_t list_cap = 0;
     int optype = PSDP_F64, utype = PSDP_F64;
     int64_t *sweeps = nullptr;
     int64_t nmax = 0;  // largest column length (selects the per-thread unroll)
@@ -366,6 +371,14 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
         int32_t *p;
         ~HostFree() { (void)hipHostFree(p); }
     } hf{host_cnt};
+    int32_t *host_list = nullptr;
+    if (S.relist) HIPCHK(hipHostMalloc((void **)&host_list, 2 * (size_t)S.list_cap * sizeof(int32_t), hipHostMallocDefault));
+    struct ListFree {
+        int32_t *p;
+        ~ListFree() {
+            if (p) (void)hipHostFree(p);
+        }
+    } lf{host_list};
     hipEvent_t evs[2];
     HIPCHK(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
@@ -439,12 +452,18 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
         set_parity(S, (int)(done_sweeps & 1));  // the lists the next sweep would read
         const int slot = batch & 1;
         HIPCHK(hipMemcpyAsync(host_cnt + 2 * slot, w.nactive, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if (host_list)
+            HIPCHK(hipMemcpyAsync(host_list + (size_t)slot * S.list_cap, w.active, (size_t)S.list_cap * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(evs[slot], st));
         if (batch > 0) {
             const int prev = slot ^ 1;
             HIPCHK(hipEventSynchronize(evs[prev]));
             if (host_cnt[2 * prev] + host_cnt[2 * prev + 1] == 0) finished = true;
-            else if (S.repick) S.repick(host_cnt[2 * prev], host_cnt[2 * prev + 1]);
+            else {
+                if (S.repick) S.repick(host_cnt[2 * prev], host_cnt[2 * prev + 1]);
+                if (host_list) HIPCHK(S.relist(host_list + (size_t)prev * S.list_cap, host_cnt[2 * prev]));
+            }
         }
         if ((tm.on && tm.used > 4096) || (ta.on && ta.used > 4096) || (ts.on && ts.used > 4096)) {
             HIPCHK(hipEventSynchronize(evs[slot]));
@@ -966,10 +985,43 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     HIPCHK(hipMemcpyAsync(dunit, unitcol.data(), unitcol.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIPCHK(launch_solver_init(S.optype, w, nullptr, 1, st));
     HIPCHK(launch_compact(w, st));
+    // Work list of the live instances only: once a poll finds at most 3/4 of
+    // the instances of the last list live, the units of the live ones are laid
+    // out again (rowstart stays indexed by column) and later batches launch
+    // over those units alone. Which rows a live column gets, and how each row
+    // is summed, do not change.
+    int64_t live_units = rowstart[count], list_gen = 0;
+    int last_live = count;
+    S.list_cap = count;
+    S.relist = [&](const int32_t *list, int cnt) -> hipError_t {
+        if (cnt < 1 || cnt > count || 4 * (int64_t)cnt > 3 * (int64_t)last_live) return hipSuccess;
+        std::vector<int32_t> ids(list, list + cnt);
+        std::sort(ids.begin(), ids.end());
+        std::vector<int64_t> rsv(count + 1, 0);
+        int64_t u = 0;
+        for (int32_t id : ids) {
+            if (id < 0 || id >= count) return hipErrorInvalidValue;
+            rsv[id] = u;
+            u += (n[id] + 3) / 4;
+        }
+        unitcol.resize(u);
+        for (int32_t id : ids) std::fill(unitcol.begin() + rsv[id], unitcol.begin() + rsv[id] + (n[id] + 3) / 4, id);
+        // the batch in flight still reads the old list: the copies queue behind it
+        hipError_t e = hipMemcpyAsync(drow, rsv.data(), (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dunit, unitcol.data(), u * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vectors are consumed
+        if (e != hipSuccess) return e;
+        live_units = u;
+        last_live = cnt;
+        ++list_gen;
+        return hipSuccess;
+    };
+    S.config_key = [&]() { return list_gen; };
     QxTimer tm, ta, ts;
     tm.on = ts.on = prm.timing != 0;
     psdp_status rs = run_sweeps(
-        S, prm, tm, ta, ts, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, dunit, rowstart[count], st); },
+        S, prm, tm, ta, ts, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, dunit, live_units, st); },
         []() { return hipSuccess; });
     if (rs != PSDP_OK) return rs;
     int64_t maxblk = 0;

@@ -150,6 +150,29 @@ def test_group_equals_single_instance_path_and_oracle(P):
     assert match >= 5
 
 
+@pytest.mark.parametrize("poll,graph", [(2, 1), (3, 0)])
+def test_group_live_work_list_keeps_results(P, poll, graph):
+    """The group product's work list is rebuilt over the live instances as
+    instances finish (here at polls every 2 or 3 sweeps, so many times, with
+    and without graphs): every instance still equals the single-instance
+    path bit for bit."""
+    insts = gen.uneven_group(seed=7, count=12, nmin=10, nmax=120)
+    sigma = max(1e-3 * float(np.abs(d["Q"]).max()) for d in insts)
+    Qs = [_t(d["Q"]) for d in insts]
+    bs = [_t(d["b"]) for d in insts]
+    seeds = [d["seed"] for d in insts]
+    xh, obj, stats = P.solve_group(Qs, bs, seeds=seeds, sigma=sigma, perturb="diag", poll_sweeps=poll, graph=graph)
+    evals = sorted(s["inner_iters"] + s["aux_matvecs"] for s in stats)
+    print(f"poll {poll} graph {graph}: evaluations per instance {evals}", flush=True)
+    assert evals[0] < evals[-1]  # the instances finish at different sweeps
+    for i, d in enumerate(insts):
+        one = P.solve(Qs[i], bs[i], sigma=sigma, perturb="diag", seed=d["seed"])
+        assert int(one.obj[0]) == int(obj[i])
+        assert np.array_equal(one.xhat.cpu().numpy(), xh[i].cpu().numpy())
+        assert one.stats[0]["inner_iters"] == stats[i]["inner_iters"]
+        assert one.stats[0]["aux_matvecs"] == stats[i]["aux_matvecs"]
+
+
 @pytest.mark.parametrize("B,qdt", [(1, "f64"), (24, "f32"), (24, "f64"), (1, "i8"), (24, "i8")])
 def test_graph_replay_matches_eager_launches(P, B, qdt):
     """Sweeps replayed from captured graphs give bit-identical results."""
