@@ -186,6 +186,23 @@ def test_graph_replay_matches_eager_launches(P, B, qdt):
         assert [s["inner_iters"] for s in g.stats] == [s["inner_iters"] for s in eager.stats]
 
 
+@pytest.mark.parametrize("qdt", ["f64", "i8"])
+def test_timed_solve_matches_untimed(P, qdt):
+    """Timing (HIP events around every launch, graphs off) changes no
+    result, and every step launch is timed."""
+    Q, b = gen.dense_int(200, 5)
+    X0 = _t(gen.random_box_points(200, 6, 3))
+    plain = P.solve(_t(Q), _t(b), X0=X0, qx_dtype=qdt)
+    timed = P.solve(_t(Q), _t(b), X0=X0, qx_dtype=qdt, timing=1)
+    assert np.array_equal(timed.X.cpu().numpy(), plain.X.cpu().numpy())
+    assert np.array_equal(timed.obj.cpu().numpy(), plain.obj.cpu().numpy())
+    s = timed.stats[0]
+    print(f"{qdt}: {s['step_launches']} step launches, {1e6 * s['step_seconds'] / s['step_launches']:.2f} us each, "
+          f"{s['sweeps']} sweeps", flush=True)
+    assert s["step_launches"] >= s["sweeps"] - 1  # the count includes the start; whole batches between polls
+    assert 0.0 < s["step_seconds"] / s["step_launches"] < 1e-3
+
+
 @pytest.mark.parametrize("qdt", ["f32", "i8"])
 def test_run_to_run_bit_identity(P, qdt):
     """Fixed-order reductions: the same batched solve twice gives the same bits."""
