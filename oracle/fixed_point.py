@@ -88,3 +88,25 @@ def qx_fixed_point(Q, X, digits: int, rows=None) -> np.ndarray:
             S = int(s_hi[i]) * (1 << 28) + int(s_lo[i])   # exact Python integer
             out[c, i] = math.ldexp(float(S), e - AUX_BITS)  # int -> float rounds to nearest even
     return out
+
+
+class GridProduct:
+    """The 4-digit product Q_off x_q as a callable on one vector x in [0,1].
+
+    Same contract as qx_fixed_point(Q, x, 4), with Q_off kept once as FP64:
+    every partial sum of Q_off T (|Q_ij| <= 127, |T| <= 2^27, n <= 65536) is
+    an integer below 2^53, so the FP64 matrix product is exact whatever its
+    summation order, and so is the scaling by 2^-27. The off-diagonal
+    entries must be integers of magnitude at most 127.
+    """
+
+    def __init__(self, Q):
+        Qf = np.array(Q, dtype=np.float64, copy=True)
+        np.fill_diagonal(Qf, 0.0)
+        if not (np.rint(Qf) == Qf).all() or np.abs(Qf).max(initial=0.0) > 127:
+            raise ValueError("the integer operand type needs integer |Q_ij| <= 127 off the diagonal")
+        self.Qoff = Qf
+
+    def __call__(self, x) -> np.ndarray:
+        T = main_grid(x).astype(np.float64)
+        return (self.Qoff @ T) / float(1 << MAIN_BITS)

@@ -57,6 +57,27 @@ def objective_exact(Q, b, xhat) -> int:
     return tot
 
 
+def objective_real(Q, b, xhat) -> float:
+    """f(x) = x^T Q x + b^T x for a 0/1 vector and real (float) Q, b.
+
+    Section 2, eq. (bqp). The exact value of the sum of the selected entries
+    Q_ij (x_i = x_j = 1) and b_i (x_i = 1), rounded once to FP64 (nearest,
+    ties to even): math.fsum returns the correctly rounded sum of its terms,
+    so the result does not depend on any summation order.
+    """
+    idx = [i for i, v in enumerate(np.asarray(xhat).tolist()) if v]
+    Qf = np.asarray(Q, dtype=np.float64)
+    bf = np.asarray(b, dtype=np.float64)
+    terms = [float(Qf[i, j]) for i in idx for j in idx]
+    terms += [float(bf[i]) for i in idx]
+    return math.fsum(terms)
+
+
+def is_integer_instance(Q, b) -> bool:
+    """True when Q and b have integer dtypes (exact int objective)."""
+    return np.issubdtype(np.asarray(Q).dtype, np.integer) and np.issubdtype(np.asarray(b).dtype, np.integer)
+
+
 def objective(Q, b, x) -> float:
     """f(x) = x^T Q x + b^T x in float64 for any real x."""
     x = np.asarray(x, dtype=np.float64)
@@ -250,6 +271,25 @@ class Params:
     sigma: float = 0.0         # perturbation standard deviation
     perturb: str = "none"      # "none", "full" or "diag"
     seed: int = 0
+    # subproblem product: "fp64" forms (Q_r - Diag p) x in FP64 as written;
+    # "i8" applies the off-diagonal part of Q_r to the iterate rounded to the
+    # grid 2^-27 (the library's integer operand type, oracle.fixed_point),
+    # exactly, and the diagonal part to x itself in FP64
+    product: str = "fp64"
+
+
+def _subproblem_gradient(Q_r, b_r, p, x, prm: Params, grid_product=None):
+    """grad h(x, p) as the subproblem solvers evaluate it.
+
+    "fp64": 2 (Q_r - Diag p) x + (b_r + p) (eq. (kkt1)). "i8": the same
+    gradient with the off-diagonal product taken on the 2^-27 grid, i.e.
+    2 (Q_off x_q + (diag(Q_r) - p) o x) + (b_r + p) with Q_off x_q exact
+    (``grid_product``, from oracle.fixed_point).
+    """
+    if prm.product == "fp64" or grid_product is None:
+        return penalty_grad(Q_r, b_r, p, x)
+    u = grid_product(x)
+    return 2.0 * (u + (np.diag(Q_r) - p) * x) + (np.asarray(b_r, dtype=np.float64) + p)
 
 
 def _bb_step(k, s, y, rho, prm: Params):
@@ -274,7 +314,8 @@ def _bb_step(k, s, y, rho, prm: Params):
     return min(max(a, prm.alpha_min), prm.alpha_max)
 
 
-def solve_subproblem_pabb(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = None, callback=None):
+def solve_subproblem_pabb(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = None, callback=None,
+                          grid_product=None):
     """Algorithm 2 (PABB) for problem (p1) at fixed p, from x.
 
     Each iteration k evaluates g^k = grad h(x^k, p), stops when
@@ -293,7 +334,7 @@ def solve_subproblem_pabb(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = No
     x_prev = g_prev = None
     rel = math.inf
     for k in range(prm.max_inner):
-        g = penalty_grad(Q_r, b_r, p, x)
+        g = _subproblem_gradient(Q_r, b_r, p, x, prm, grid_product)
         rel = kkt_violation(x, g) / rho
         if callback is not None:
             callback(k, x, g)
@@ -323,7 +364,8 @@ def proximal_diagonal(Q_r, p, eps) -> np.ndarray:
     return np.maximum(np.abs(np.asarray(Q_r, dtype=np.float64)).sum(axis=1) - p, eps)
 
 
-def solve_subproblem_ppa(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = None, callback=None):
+def solve_subproblem_ppa(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = None, callback=None,
+                         grid_product=None):
     """Algorithm 1 (PPA) for problem (p1) at fixed p, from x.
 
     d~ = -grad h / (2 h_p) (eq. for d~), x^{k+1} = P(x^k + d~) (eq. (x1)),
@@ -336,7 +378,7 @@ def solve_subproblem_ppa(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = Non
     x = np.array(x, dtype=np.float64)
     rel = math.inf
     for k in range(prm.max_inner):
-        g = penalty_grad(Q_r, b_r, p, x)
+        g = _subproblem_gradient(Q_r, b_r, p, x, prm, grid_product)
         rel = kkt_violation(x, g) / rho
         if callback is not None:
             callback(k, x, g)
@@ -384,12 +426,13 @@ def round_binary(x) -> np.ndarray:
 class Result:
     x: np.ndarray            # final continuous iterate
     xhat: np.ndarray         # rounded 0/1 solution (uint8)
-    obj: int                 # exact objective of xhat on the original Q, b
+    obj: object              # objective of xhat on the original Q, b: int (integer data,
+                             # exact) or float (real data, correctly rounded)
     exit_reason: int
     outer_iters: int
     inner_iters: int         # total gradient evaluations in subproblems
     aux_matvecs: int         # eigen/linear solves are dense here: 0
-    trace: list              # per outer step: dict(s, nI, lam, alpha, inner, rel)
+    trace: list              # per outer step: dict(s, nI, lam, alpha, inner, rel, x)
     p: np.ndarray            # final penalty vector (reformulated problem)
 
 
@@ -409,12 +452,24 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
        which already is that problem's stationary point).
     The floor is lambda_floor_rel * rho: the paper does not cover a
     non-positive lambda_min.
-    5. No-progress exit: when ``stall_outer`` consecutive subproblems stop at
-       their starting point, x is a fixed point of the loop at this tolerance:
-       with x unchanged, I and z are unchanged, and by eq. (alpha) the next
-       scaled matrix is the previous one shifted by -alpha, so lambda shrinks
-       by the factor (1 - eta) and every later update moves the gradient by
-       less than the step that already failed to trigger an iteration.
+    5. No-progress exit (an addition to Algorithm 3, not a reading of it):
+       when ``stall_outer`` consecutive subproblems stop at their starting
+       point, the loop ends. With x unchanged, I and z are unchanged, and by
+       eq. (alpha) the next scaled matrix is the previous one shifted by
+       -alpha, so lambda shrinks by the factor (1 - eta) until it reaches the
+       floor lambda_floor_rel * rho; from there every update adds
+       eta * lambda_floor_rel * rho * z_i (1 - 2 x_i) <= 2.5e-9 rho to a
+       gradient entry, at most 2.5e-6 rho over the 1000 updates of the cap,
+       a quarter of the KKT tolerance. A start point whose violation lies
+       within that margin of the tolerance could still move later, so the
+       exit is a stated deviation; the tests pin that it changes no result
+       on the seeded sets they cover (stall_outer=2 against an exit that
+       never fires).
+    The objective of the rounded point is exact: an integer for integer Q and
+    b, else the correctly rounded FP64 value of the exact sum.
+    ``product`` "i8" evaluates the subproblem gradients with the library's
+    integer operand grid (see Params); lambda_min and x^0 stay dense FP64.
+    Every trace record also holds "x", the point the update starts from.
     """
     prm = prm or Params()
     Q = np.asarray(Q)
@@ -428,6 +483,12 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
     x = initial_point(Q_r, b_r) if x0 is None else np.array(x0, dtype=np.float64)
     p = np.zeros(n) if p0 is None else np.array(p0, dtype=np.float64)
     sub = solve_subproblem_pabb if prm.inner == "pabb" else solve_subproblem_ppa
+    grid_product = None
+    if prm.product == "i8":
+        from oracle.fixed_point import GridProduct
+        grid_product = GridProduct(Qt)
+    elif prm.product != "fp64":
+        raise ValueError("product must be 'fp64' or 'i8'")
     trace = []
     s = 0
     stall = 0
@@ -443,15 +504,17 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
             reason = STALL if bool((np.abs(x - 0.5) < 1e-9).any()) else OUTER_CAP
             break
         rho = rho_scale(Q_r, b_r, p)
+        x_start = x.copy()
         lam, I, z = lambda_min_scaled(Q_r, p, x)
         alpha = prm.eta * max(lam, prm.lambda_floor_rel * rho)
         p = p.copy()
         p[I] += alpha * z
-        x, it, rel, moved = sub(Q_r, b_r, p, x, prm)
+        x, it, rel, moved = sub(Q_r, b_r, p, x, prm, grid_product=grid_product)
         stall = 0 if moved else stall + 1
         inner_total += it
-        trace.append(dict(s=s, nI=int(I.sum()), lam=lam, alpha=alpha, inner=it, rel=rel))
+        trace.append(dict(s=s, nI=int(I.sum()), lam=lam, alpha=alpha, inner=it, rel=rel, x=x_start))
         s += 1
     xhat = round_binary(x)
-    return Result(x=x, xhat=xhat, obj=objective_exact(Q, b, xhat), exit_reason=reason,
+    obj = objective_exact(Q, b, xhat) if is_integer_instance(Q, b) else objective_real(Q, b, xhat)
+    return Result(x=x, xhat=xhat, obj=obj, exit_reason=reason,
                   outer_iters=s, inner_iters=inner_total, aux_matvecs=0, trace=trace, p=p)

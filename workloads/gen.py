@@ -169,3 +169,13 @@ def random_box_points(n: int, B: int, seed: int):
 def random_vector(n: int, seed: int, scale: float = 1.0):
     """Standard normal vector of length n times scale."""
     return np.random.default_rng(seed).standard_normal(n) * scale
+
+
+def real_normal(n: int, seed: int):
+    """Real symmetric Q with entries N(0,1) (upper triangle mirrored) and
+    b ~ N(0,1), both FP64: the real-valued form of the problem (Section 2)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    Q = _mirror_upper(A)
+    b = rng.standard_normal(n)
+    return Q, b
