@@ -114,6 +114,10 @@ typedef struct {
                                   the sweeps with nonzeros x 2 x live columns <= n^2 / 4 (the
                                   range where it was measured faster on gfx950); 1 builds it
                                   whatever the size and uses it for every sweep; 0 never */
+    int32_t lambda_reuse;      /* 1 (default): after a subproblem that left x unchanged,
+                                  lambda_min is the previous value minus the previous alpha (I and
+                                  z are unchanged, so eq. (alpha) shifted the scaled matrix by
+                                  exactly -alpha) and no LOBPCG runs; 0: every update runs LOBPCG */
     double tol_kkt;            /* delta of eq. (cret) (1e-5) */
     double tol_binary;         /* Algorithm 3 loop tolerance (1e-5) */
     double eta;                /* eq. (alpha1) scaling, 0 < eta < 1 (0.999) */
@@ -196,17 +200,78 @@ psdp_status psdp_solve_i32(const int32_t *Q, const int32_t *b, int64_t n,
                            hipStream_t stream);
 
 /*
- * psdp_solve_i32_ex - psdp_solve_i32 plus a per-penalty-update trace.
+ * psdp_solve_i32_ex - psdp_solve_i32 plus a per-penalty-update trace and a
+ * replay of given penalty steps.
  * trace     host, nullable: B x trace_cap records of 6 doubles
  *           {s, |I|, lambda_min, alpha, subproblem evaluations, final cret/rho},
  *           one record per completed subproblem (unused records untouched).
  * trace_cap records per column (>= 1 when trace is given).
+ * alpha_in  host, nullable: B x alpha_cap penalty steps, row c for start c.
+ *           Penalty update s < alpha_cap of start c takes
+ *           alpha = alpha_in[c * alpha_cap + s] in place of
+ *           eta * max(lambda_min, lambda_floor_rel * rho) (eqs. (alpha),
+ *           (alpha1)); lambda_min is still computed and traced. Later updates
+ *           compute alpha. A parity hook: with another implementation's
+ *           steps, the rest of every update (the penalty update eq. (pp1),
+ *           the subproblem, the exit tests) can be compared step by step.
+ *           Entries must be finite and > 0 (else PSDP_E_INVALID).
+ * alpha_cap steps per start (>= 1 when alpha_in is given).
  */
 psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n,
                               const double *X0, const double *p0, int32_t B,
                               const psdp_params *prm, uint8_t *xhat, int64_t *obj,
                               double *X_out, int32_t *best, psdp_stats *stats,
-                              double *trace, int32_t trace_cap, hipStream_t stream);
+                              double *trace, int32_t trace_cap,
+                              const double *alpha_in, int32_t alpha_cap, hipStream_t stream);
+
+/*
+ * psdp_solve_f64 - Algorithm 3 on B starts of one instance with real data:
+ * Q real symmetric and b real (Section 2, eq. (bqp)), both FP64.
+ *
+ * Arguments as psdp_solve_i32, except:
+ * Q, b    device, double; Q n x n row-major, exactly symmetric, finite.
+ * obj     device, double, length B: f(xhat) on the original Q and b, the
+ *         exact value of the sum of the selected entries rounded once to
+ *         FP64 (nearest, ties to even), so it does not depend on any
+ *         summation order.
+ * Operand types: F64 for any data; F32 and BF16 when every off-diagonal
+ * entry of Q is exactly a float / a bfloat16 value (BF16 also without a
+ * FULL perturbation); I8 when every off-diagonal entry is an integer in
+ * [-127, 127] (and no FULL perturbation). Otherwise PSDP_E_UNSUPPORTED.
+ * The perturbed entry Q_ij + mu_ij (Section 3.5) is rounded once to FP64.
+ * Errors as psdp_solve_i32, with PSDP_E_NONFINITE also for NaN/Inf in Q or
+ * b and PSDP_E_OVERFLOW when n^2 max|Q| + n max|b| >= 1e300.
+ */
+psdp_status psdp_solve_f64(const double *Q, const double *b, int64_t n,
+                           const double *X0, const double *p0, int32_t B,
+                           const psdp_params *prm, uint8_t *xhat, double *obj,
+                           double *X_out, int32_t *best, psdp_stats *stats,
+                           hipStream_t stream);
+
+/* psdp_solve_f64 plus the trace and the replayed steps of psdp_solve_i32_ex. */
+psdp_status psdp_solve_f64_ex(const double *Q, const double *b, int64_t n,
+                              const double *X0, const double *p0, int32_t B,
+                              const psdp_params *prm, uint8_t *xhat, double *obj,
+                              double *X_out, int32_t *best, psdp_stats *stats,
+                              double *trace, int32_t trace_cap,
+                              const double *alpha_in, int32_t alpha_cap, hipStream_t stream);
+
+/*
+ * psdp_solve_host_i32, psdp_solve_host_f64 - the same solves with every
+ * pointer in host memory (Q row-major n x n, b length n, X0 n x B
+ * column-major or NULL, p0 length n or NULL, xhat n x B, obj length B,
+ * X_out n x B or NULL, best and stats as above). The library copies the
+ * inputs to the current device, solves, copies the outputs back and frees
+ * its copies before returning. Errors as the device-pointer entries.
+ */
+psdp_status psdp_solve_host_i32(const int32_t *Q, const int32_t *b, int64_t n,
+                                const double *X0, const double *p0, int32_t B,
+                                const psdp_params *prm, uint8_t *xhat, int64_t *obj,
+                                double *X_out, int32_t *best, psdp_stats *stats);
+psdp_status psdp_solve_host_f64(const double *Q, const double *b, int64_t n,
+                                const double *X0, const double *p0, int32_t B,
+                                const psdp_params *prm, uint8_t *xhat, double *obj,
+                                double *X_out, int32_t *best, psdp_stats *stats);
 
 /*
  * psdp_solve_group_i32 - Algorithm 3 on `count` independent instances of
@@ -217,6 +282,9 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n,
  * b       host array of `count` device pointers, int32 length n_i.
  * seeds   host, uint64[count], nullable: per-instance perturbation seeds
  *         (NULL uses prm->seed for every instance).
+ * sigmas  host, double[count], nullable: per-instance perturbation standard
+ *         deviations (NULL uses prm->sigma for every instance); each finite
+ *         and >= 0.
  * xhat    host array of `count` device pointers, uint8 length n_i.
  * obj     device, int64[count].
  * stats   host, nullable: array of `count` psdp_stats.
@@ -225,7 +293,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n,
  */
 psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n,
                                  const int32_t *const *Q, const int32_t *const *b,
-                                 const uint64_t *seeds, const psdp_params *prm,
+                                 const uint64_t *seeds, const double *sigmas, const psdp_params *prm,
                                  uint8_t *const *xhat, int64_t *obj,
                                  psdp_stats *stats, hipStream_t stream);
 
@@ -266,8 +334,11 @@ psdp_status psdp_penalty_adjoint(int32_t dtype, int32_t vtype, const void *X, co
 
 /*
  * psdp_round_objective_i32 - the final step of the solve on given iterates:
- * xhat_ic = 1 iff X_ic > 1/2 and obj_c = xhat_c^T Q xhat_c + b^T xhat_c, in
- * exact int64 arithmetic on the original integer data.
+ * xhat_ic = 1 iff X_ic > 1/2 and obj_c = xhat_c^T Q xhat_c + b^T xhat_c
+ * (the objective of Section 2, eq. (bqp)), in exact int64 arithmetic on the
+ * original integer data. The paper never states how the final continuous
+ * point becomes binary; rounding at 1/2 with ties to 0 is this library's
+ * reading.
  * Q device int32 n x n; b device int32; X device double n x B;
  * xhat device uint8 n x B; obj device int64[B]. Stream-ordered.
  * Errors: PSDP_E_INVALID.
@@ -275,6 +346,17 @@ psdp_status psdp_penalty_adjoint(int32_t dtype, int32_t vtype, const void *X, co
 psdp_status psdp_round_objective_i32(const int32_t *Q, const int32_t *b, int64_t n,
                                      const double *X, int64_t B, uint8_t *xhat,
                                      int64_t *obj, hipStream_t stream);
+
+/*
+ * psdp_round_objective_f64 - the same for real data: Q device double n x n,
+ * b device double; obj device double[B] is the exact sum of the selected
+ * Q_ij and b_i rounded once to FP64 (nearest, ties to even). The call
+ * allocates B * 32 KiB of stream-ordered scratch. Stream-ordered.
+ * Errors: PSDP_E_INVALID (n > 65536, B > 65535, null pointer).
+ */
+psdp_status psdp_round_objective_f64(const double *Q, const double *b, int64_t n,
+                                     const double *X, int64_t B, uint8_t *xhat,
+                                     double *obj, hipStream_t stream);
 
 /*
  * psdp_perturbation - the symmetric perturbation mu of Section 3.5 as this
@@ -314,6 +396,27 @@ psdp_status psdp_perturbation(int64_t n, double sigma, uint64_t seed, int32_t mo
  */
 psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t B,
                            int32_t digits, double *Y, hipStream_t stream);
+
+/*
+ * psdp_qx_dense - the floating-point Q.X product of the batched solver path
+ * (the O(n^2) part of every gradient evaluation, eq. (kkt1)) on given
+ * vectors: Y[:, c] = Q_off X[:, c], Q_off = Q with a zero diagonal, through
+ * the kernel and split-K the solver picks for B live columns (the streaming
+ * MFMA kernel up to 64 columns, the LDS-tiled MFMA GEMM above), with the
+ * K slices summed in FP64 in slice order as the solver's column kernel
+ * reads them.
+ * dtype   F32: FP32 operands, FP32 MFMA accumulation within a slice (X is
+ *         rounded to float); F64: FP64 operands and FP64 MFMA (Q read from
+ *         its exact FP32 copy).
+ * Q       device, int32, n x n row-major, |Q_ij| <= 2^24 (the diagonal is
+ *         ignored; symmetry is checked).
+ * X, Y    device, double, n x B column-major (leading dimension n).
+ * The call allocates its own workspace and synchronizes `stream`.
+ * Errors: PSDP_E_INVALID (dtype, sizes, null pointer), PSDP_E_NOT_SYMMETRIC,
+ *         PSDP_E_UNSUPPORTED (|Q_ij| > 2^24), PSDP_E_DEVICE / PSDP_E_NOMEM.
+ */
+psdp_status psdp_qx_dense(int32_t dtype, const int32_t *Q, int64_t n, const double *X, int32_t B,
+                          double *Y, hipStream_t stream);
 
 /*
  * psdp_qx_sparse - the same product as psdp_qx_digits (same arguments, same

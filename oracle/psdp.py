@@ -217,16 +217,101 @@ def initial_point(Q_r, b_r) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Subproblem machinery (Sections 3.1-3.3).
 
+# ---------------------------------------------------------------------------
+# Inner products and norms as exact values rounded once.
+#
+# The BB step lengths (eq. (bb1)) and the scale rho (Section 3.3) are real
+# inner products and norms. The oracle computes each one as its exact value
+# rounded once to FP64 (nearest, ties to even), so no summation order enters
+# the trajectory.
+
+def _two_product(a, b):
+    """(p, e) with p = fl(a b) and p + e = a b exactly (Dekker's product with
+    Veltkamp's splitting), elementwise. Exact when no |a|, |b| exceeds 2^995
+    and no nonzero product falls below 2^-969 (callers check)."""
+    c = 134217729.0  # 2^27 + 1
+    ta = c * a
+    ah = ta - (ta - a)
+    al = a - ah
+    tb = c * b
+    bh = tb - (tb - b)
+    bl = b - bh
+    p = a * b
+    e = ((ah * bh - p) + ah * bl + al * bh) + al * bl
+    return p, e
+
+
+def dot_exact(a, b) -> float:
+    """sum_i a_i b_i: the exact value rounded once to FP64.
+
+    math.fsum returns the correctly rounded sum of its (exact) terms; each
+    product enters as the exact pair of _two_product. Inputs outside that
+    pair's range are summed as exact rationals instead.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    p = a * b
+    big = max(float(np.abs(a).max(initial=0.0)), float(np.abs(b).max(initial=0.0)))
+    tiny = (p != 0.0) & (np.abs(p) < 2.0 ** -960)
+    lost = (p == 0.0) & (a != 0.0) & (b != 0.0)
+    if big > 2.0 ** 995 or tiny.any() or lost.any():
+        from fractions import Fraction
+        return float(sum((Fraction(float(x)) * Fraction(float(y)) for x, y in zip(a, b)), Fraction(0)))
+    p, e = _two_product(a, b)
+    return math.fsum(np.concatenate([p, e]).tolist())
+
+
+def row_abs_sums(M) -> np.ndarray:
+    """sum_j |M_ij| for every row: exact values rounded once (math.fsum)."""
+    return np.array([math.fsum(row) for row in np.abs(np.asarray(M, dtype=np.float64)).tolist()])
+
+
 def rho_scale(Q_r, b_r, p) -> float:
     """rho = max{1, ||2(Q_r - Diag p)||_inf, ||b_r + p||_inf} (Section 3.3).
 
     The paper leaves the norms unstated; the induced infinity norm (largest
     absolute row sum) and the vector infinity norm are used, as in the
-    bounds of the proof of Theorem 2.
+    bounds of the proof of Theorem 2. Each row sum is exact, rounded once.
     """
     Qbar = np.asarray(Q_r, dtype=np.float64) - np.diag(p)
-    return max(1.0, float(np.abs(2.0 * Qbar).sum(axis=1).max()),
+    return max(1.0, float(row_abs_sums(2.0 * Qbar).max()),
                float(np.abs(np.asarray(b_r) + p).max()))
+
+
+class _RowNorms:
+    """rho and the row sums of |Q_r| for one solve, exact and rounded once.
+
+    The off-diagonal part of Q_r - Diag p does not change with p, so its exact
+    absolute row sums are kept as rationals once; each evaluation adds the
+    row's one diagonal term |(Q_r)_ii - p_i| (itself rounded as the matrix
+    entry is) exactly and rounds once. Same values as rho_scale and
+    proximal_diagonal, without re-summing every row.
+    """
+
+    def __init__(self, Q_r):
+        from fractions import Fraction
+        Q_r = np.asarray(Q_r, dtype=np.float64)
+        off = np.abs(Q_r)
+        np.fill_diagonal(off, 0.0)
+        self._F = Fraction
+        self.diag = np.diag(Q_r).copy()
+        self.off = []
+        for row in off.tolist():
+            if all(v == int(v) for v in row):
+                self.off.append(Fraction(int(sum(int(v) for v in row))))
+            else:
+                self.off.append(sum((Fraction(v) for v in row), Fraction(0)))
+
+    def _rows(self, d):
+        F = self._F
+        return np.array([float(o + F(float(abs(v)))) for o, v in zip(self.off, d)])
+
+    def rho(self, b_r, p) -> float:
+        rows = 2.0 * self._rows(self.diag - p)   # 2 |a| rounds like |a|: scaling by 2 is exact
+        return max(1.0, float(rows.max()), float(np.abs(np.asarray(b_r) + p).max()))
+
+    def hp(self, p, eps) -> np.ndarray:
+        return np.maximum(self._rows(self.diag) - p, eps)
 
 
 def kkt_violation(x, g) -> float:
@@ -271,6 +356,11 @@ class Params:
     sigma: float = 0.0         # perturbation standard deviation
     perturb: str = "none"      # "none", "full" or "diag"
     seed: int = 0
+    # lambda_min after a subproblem that did not move x: "shift" takes the
+    # previous value minus the previous alpha (x, I and z are unchanged, so
+    # eq. (alpha) shifts the scaled matrix by -alpha and its smallest
+    # eigenvalue by the same amount); "solve" calls the eigensolver again
+    lambda_reuse: str = "shift"
     # subproblem product: "fp64" forms (Q_r - Diag p) x in FP64 as written;
     # "i8" applies the off-diagonal part of Q_r to the iterate rounded to the
     # grid 2^-27 (the library's integer operand type, oracle.fixed_point),
@@ -302,9 +392,9 @@ def _bb_step(k, s, y, rho, prm: Params):
     """
     if k == 0:
         return 1.0 / rho
-    ss = float(s @ s)
-    sy = float(s @ y)
-    yy = float(y @ y)
+    ss = dot_exact(s, s)
+    sy = dot_exact(s, y)
+    yy = dot_exact(y, y)
     if sy <= 0.0:
         a = prm.alpha_max
     elif k % 2 == 1:
@@ -359,13 +449,13 @@ def proximal_diagonal(Q_r, p, eps) -> np.ndarray:
     """Diagonal of H_p: max(sum_i |(Q_r)_ji| - p_j, eps) (Section 3.1).
 
     The row sum runs over every column, diagonal included, as the positive
-    semidefiniteness argument for H_p + P requires.
+    semidefiniteness argument for H_p + P requires; it is exact, rounded once.
     """
-    return np.maximum(np.abs(np.asarray(Q_r, dtype=np.float64)).sum(axis=1) - p, eps)
+    return np.maximum(row_abs_sums(Q_r) - p, eps)
 
 
 def solve_subproblem_ppa(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = None, callback=None,
-                         grid_product=None):
+                         grid_product=None, hp=None):
     """Algorithm 1 (PPA) for problem (p1) at fixed p, from x.
 
     d~ = -grad h / (2 h_p) (eq. for d~), x^{k+1} = P(x^k + d~) (eq. (x1)),
@@ -374,7 +464,8 @@ def solve_subproblem_ppa(Q_r, b_r, p, x, prm: Params, rho: Optional[float] = Non
     """
     if rho is None:
         rho = rho_scale(Q_r, b_r, p)
-    hp = proximal_diagonal(Q_r, p, prm.eps_hp)
+    if hp is None:
+        hp = proximal_diagonal(Q_r, p, prm.eps_hp)
     x = np.array(x, dtype=np.float64)
     rel = math.inf
     for k in range(prm.max_inner):
@@ -434,6 +525,7 @@ class Result:
     aux_matvecs: int         # eigen/linear solves are dense here: 0
     trace: list              # per outer step: dict(s, nI, lam, alpha, inner, rel, x)
     p: np.ndarray            # final penalty vector (reformulated problem)
+    eig_solves: int = 0      # lambda_min computations (eigensolver calls)
 
 
 def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
@@ -466,7 +558,10 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
        on the seeded sets they cover (stall_outer=2 against an exit that
        never fires).
     The objective of the rounded point is exact: an integer for integer Q and
-    b, else the correctly rounded FP64 value of the exact sum.
+    b, else the correctly rounded FP64 value of the exact sum. The BB inner
+    products and the row norms of rho and H_p are exact values rounded once
+    (dot_exact, row_abs_sums), so the trajectory depends on no summation order
+    except the matrix-vector products' (none in the "i8" product mode).
     ``product`` "i8" evaluates the subproblem gradients with the library's
     integer operand grid (see Params); lambda_min and x^0 stay dense FP64.
     Every trace record also holds "x", the point the update starts from.
@@ -483,6 +578,7 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
     x = initial_point(Q_r, b_r) if x0 is None else np.array(x0, dtype=np.float64)
     p = np.zeros(n) if p0 is None else np.array(p0, dtype=np.float64)
     sub = solve_subproblem_pabb if prm.inner == "pabb" else solve_subproblem_ppa
+    norms = _RowNorms(Q_r)
     grid_product = None
     if prm.product == "i8":
         from oracle.fixed_point import GridProduct
@@ -493,6 +589,8 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
     s = 0
     stall = 0
     inner_total = 0
+    eig_solves = 0
+    moved = True
     while True:
         if binary_gap(x) <= prm.tol_binary:
             reason = CONVERGED
@@ -503,13 +601,21 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
         if s >= prm.max_outer:
             reason = STALL if bool((np.abs(x - 0.5) < 1e-9).any()) else OUTER_CAP
             break
-        rho = rho_scale(Q_r, b_r, p)
+        rho = norms.rho(b_r, p)
         x_start = x.copy()
-        lam, I, z = lambda_min_scaled(Q_r, p, x)
+        if prm.lambda_reuse == "shift" and trace and not moved:
+            # warm start by the shift law: the last subproblem left x as it was
+            lam = trace[-1]["lam"] - trace[-1]["alpha"]
+            I = (x > 0.0) & (x < 1.0)
+            z = x[I] - x[I] * x[I]
+        else:
+            lam, I, z = lambda_min_scaled(Q_r, p, x)
+            eig_solves += 1
         alpha = prm.eta * max(lam, prm.lambda_floor_rel * rho)
         p = p.copy()
         p[I] += alpha * z
-        x, it, rel, moved = sub(Q_r, b_r, p, x, prm, grid_product=grid_product)
+        extra = {} if prm.inner == "pabb" else {"hp": norms.hp(p, prm.eps_hp)}
+        x, it, rel, moved = sub(Q_r, b_r, p, x, prm, rho=norms.rho(b_r, p), grid_product=grid_product, **extra)
         stall = 0 if moved else stall + 1
         inner_total += it
         trace.append(dict(s=s, nI=int(I.sum()), lam=lam, alpha=alpha, inner=it, rel=rel, x=x_start))
@@ -517,4 +623,5 @@ def solve(Q, b, prm: Optional[Params] = None, x0=None, p0=None) -> Result:
     xhat = round_binary(x)
     obj = objective_exact(Q, b, xhat) if is_integer_instance(Q, b) else objective_real(Q, b, xhat)
     return Result(x=x, xhat=xhat, obj=obj, exit_reason=reason,
-                  outer_iters=s, inner_iters=inner_total, aux_matvecs=0, trace=trace, p=p)
+                  outer_iters=s, inner_iters=inner_total, aux_matvecs=0, trace=trace, p=p,
+                  eig_solves=eig_solves)

@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("gemm_variant", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("sparse", ctypes.c_int32),
+        ("lambda_reuse", ctypes.c_int32),
         ("tol_kkt", ctypes.c_double),
         ("tol_binary", ctypes.c_double),
         ("eta", ctypes.c_double),
@@ -87,15 +88,25 @@ SIGNATURES = {
     "psdp_solve_i32": (_I32, [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(Params), _P, _P, _P,
                               ctypes.POINTER(_I32), ctypes.POINTER(Stats), _P]),
     "psdp_solve_i32_ex": (_I32, [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(Params), _P, _P, _P,
-                                 ctypes.POINTER(_I32), ctypes.POINTER(Stats), _P, _I32, _P]),
-    "psdp_solve_group_i32": (_I32, [_I32, _P, _P, _P, _P, ctypes.POINTER(Params), _P, _P,
+                                 ctypes.POINTER(_I32), ctypes.POINTER(Stats), _P, _I32, _P, _I32, _P]),
+    "psdp_solve_f64": (_I32, [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(Params), _P, _P, _P,
+                              ctypes.POINTER(_I32), ctypes.POINTER(Stats), _P]),
+    "psdp_solve_f64_ex": (_I32, [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(Params), _P, _P, _P,
+                                 ctypes.POINTER(_I32), ctypes.POINTER(Stats), _P, _I32, _P, _I32, _P]),
+    "psdp_solve_host_i32": (_I32, [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(Params), _P, _P, _P,
+                                   ctypes.POINTER(_I32), ctypes.POINTER(Stats)]),
+    "psdp_solve_host_f64": (_I32, [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(Params), _P, _P, _P,
+                                   ctypes.POINTER(_I32), ctypes.POINTER(Stats)]),
+    "psdp_solve_group_i32": (_I32, [_I32, _P, _P, _P, _P, _P, ctypes.POINTER(Params), _P, _P,
                                     ctypes.POINTER(Stats), _P]),
     "psdp_eval_penalty_grad": (_I32, [_I32, _I32, _P, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P]),
     "psdp_penalty_adjoint": (_I32, [_I32, _I32, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P]),
     "psdp_round_objective_i32": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
+    "psdp_round_objective_f64": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
     "psdp_perturbation": (_I32, [_I64, _D, _U64, _I32, _P, _P]),
     "psdp_qx_digits": (_I32, [_P, _I64, _P, _I32, _I32, _P, _P]),
     "psdp_qx_sparse": (_I32, [_P, _I64, _P, _I32, _I32, _P, _P]),
+    "psdp_qx_dense": (_I32, [_I32, _P, _I64, _P, _I32, _P, _P]),
     "psdp_release": (None, []),
 }
 
@@ -186,16 +197,23 @@ class SolveResult:
     trace: Optional[object] = None   # numpy (B, trace_cap, 6) when requested
 
 
-def solve(Q, b, X0=None, p0=None, trace_cap: int = 0, params: Optional[Params] = None, **kw) -> SolveResult:
-    """Algorithm 3 on one integer instance, one or many starts.
+def solve(Q, b, X0=None, p0=None, trace_cap: int = 0, params: Optional[Params] = None, alpha=None,
+          **kw) -> SolveResult:
+    """Algorithm 3 on one instance, one or many starts.
 
-    Q: int32 (n, n) symmetric; b: int32 (n,); X0: float64 (B, n) starts in
-    [0,1] (None: x^0 of eq. (gamma), one start); p0: float64 (n,) or None.
+    Q: int32 (n, n) symmetric with b int32 (n,) (psdp_solve_i32, int64
+    objectives), or Q float64 with b float64 (psdp_solve_f64, FP64
+    objectives); X0: float64 (B, n) starts in [0,1] (None: x^0 of eq.
+    (gamma), one start); p0: float64 (n,) or None. alpha: optional host
+    array (B, cap) of penalty steps replayed by the first cap updates of
+    every start (psdp_solve_*_ex); trace_cap > 0 returns the per-update trace.
     """
     torch = _torch()
     lib = load()
-    Q = _dev(Q, torch.int32, "Q")
-    b = _dev(b, torch.int32, "b")
+    real = Q.dtype == torch.float64
+    vt = torch.float64 if real else torch.int32
+    Q = _dev(Q, vt, "Q")
+    b = _dev(b, vt, "b")
     n = b.shape[0]
     single = X0 is None or X0.dim() == 1
     if X0 is not None:
@@ -208,20 +226,28 @@ def solve(Q, b, X0=None, p0=None, trace_cap: int = 0, params: Optional[Params] =
         p0 = _dev(p0, torch.float64, "p0")
     prm = params if params is not None else default_params(**kw)
     xhat = torch.empty((B, n), dtype=torch.uint8, device=Q.device)
-    obj = torch.empty(B, dtype=torch.int64, device=Q.device)
+    obj = torch.empty(B, dtype=torch.float64 if real else torch.int64, device=Q.device)
     X = torch.empty((B, n), dtype=torch.float64, device=Q.device)
     best = ctypes.c_int32(0)
     stats = (Stats * B)()
     tr = None
-    if trace_cap > 0:
+    if trace_cap > 0 or alpha is not None:
         import numpy as np
-        tr = np.full((B, trace_cap, 6), np.nan)
-        st = lib.psdp_solve_i32_ex(_ptr(Q), _ptr(b), n, _ptr(X0v), _ptr(p0), B, ctypes.byref(prm),
-                                   _ptr(xhat), _ptr(obj), _ptr(X), ctypes.byref(best), stats,
-                                   tr.ctypes.data_as(ctypes.c_void_p), trace_cap, _stream())
+        trp, cap = None, 0
+        if trace_cap > 0:
+            tr = np.full((B, trace_cap, 6), np.nan)
+            trp, cap = tr.ctypes.data_as(ctypes.c_void_p), trace_cap
+        ap, acap = None, 0
+        if alpha is not None:
+            al = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64).reshape(B, -1))
+            ap, acap = al.ctypes.data_as(ctypes.c_void_p), al.shape[1]
+        fn = lib.psdp_solve_f64_ex if real else lib.psdp_solve_i32_ex
+        st = fn(_ptr(Q), _ptr(b), n, _ptr(X0v), _ptr(p0), B, ctypes.byref(prm), _ptr(xhat), _ptr(obj), _ptr(X),
+                ctypes.byref(best), stats, trp, cap, ap, acap, _stream())
     else:
-        st = lib.psdp_solve_i32(_ptr(Q), _ptr(b), n, _ptr(X0v), _ptr(p0), B, ctypes.byref(prm),
-                                _ptr(xhat), _ptr(obj), _ptr(X), ctypes.byref(best), stats, _stream())
+        fn = lib.psdp_solve_f64 if real else lib.psdp_solve_i32
+        st = fn(_ptr(Q), _ptr(b), n, _ptr(X0v), _ptr(p0), B, ctypes.byref(prm), _ptr(xhat), _ptr(obj), _ptr(X),
+                ctypes.byref(best), stats, _stream())
     _check(st)
     if single:
         xhat, X = xhat[0], X[0]
@@ -229,11 +255,39 @@ def solve(Q, b, X0=None, p0=None, trace_cap: int = 0, params: Optional[Params] =
                        trace=tr)
 
 
+def solve_host(Q, b, X0=None, p0=None, params: Optional[Params] = None, **kw):
+    """The host-pointer entry points (psdp_solve_host_i32 / _f64) on numpy
+    arrays: returns (xhat uint8 (B, n), obj (B,), X (B, n), best, stats)."""
+    import numpy as np
+    lib = load()
+    real = np.asarray(Q).dtype == np.float64
+    vt = np.float64 if real else np.int32
+    Qh = np.ascontiguousarray(Q, dtype=vt)
+    bh = np.ascontiguousarray(b, dtype=vt)
+    n = bh.shape[0]
+    X0h = None if X0 is None else np.ascontiguousarray(np.asarray(X0, dtype=np.float64).reshape(-1, n))
+    B = 1 if X0h is None else X0h.shape[0]
+    p0h = None if p0 is None else np.ascontiguousarray(p0, dtype=np.float64)
+    prm = params if params is not None else default_params(**kw)
+    xhat = np.empty((B, n), dtype=np.uint8)
+    obj = np.empty(B, dtype=np.float64 if real else np.int64)
+    X = np.empty((B, n), dtype=np.float64)
+    best = ctypes.c_int32(0)
+    stats = (Stats * B)()
+    hp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    fn = lib.psdp_solve_host_f64 if real else lib.psdp_solve_host_i32
+    _check(fn(hp(Qh), hp(bh), n, hp(X0h), hp(p0h), B, ctypes.byref(prm), hp(xhat), hp(obj), hp(X),
+              ctypes.byref(best), stats))
+    return xhat, obj, X, best.value, [s.as_dict() for s in stats]
+
+
 def solve_group(Qs: Sequence, bs: Sequence, seeds: Optional[Sequence[int]] = None,
-                params: Optional[Params] = None, **kw):
+                sigmas: Optional[Sequence[float]] = None, params: Optional[Params] = None, **kw):
     """Algorithm 3 on several instances of different sizes, advanced together.
 
-    Returns (list of uint8 xhat tensors, int64 obj tensor, list of stats dicts).
+    seeds / sigmas: optional per-instance perturbation seeds and standard
+    deviations. Returns (list of uint8 xhat tensors, int64 obj tensor, list
+    of stats dicts).
     """
     torch = _torch()
     lib = load()
@@ -249,9 +303,10 @@ def solve_group(Qs: Sequence, bs: Sequence, seeds: Optional[Sequence[int]] = Non
     xp = (ctypes.c_void_p * count)(*[t.data_ptr() for t in xh])
     obj = torch.empty(count, dtype=torch.int64, device=dev)
     sd = (ctypes.c_uint64 * count)(*seeds) if seeds is not None else None
+    sg = (ctypes.c_double * count)(*[float(v) for v in sigmas]) if sigmas is not None else None
     prm = params if params is not None else default_params(**kw)
     stats = (Stats * count)()
-    st = lib.psdp_solve_group_i32(count, ns, qp, bp, sd, ctypes.byref(prm), xp, _ptr(obj), stats,
+    st = lib.psdp_solve_group_i32(count, ns, qp, bp, sd, sg, ctypes.byref(prm), xp, _ptr(obj), stats,
                                   _stream())
     _check(st)
     return xh, obj, [s.as_dict() for s in stats]
@@ -308,18 +363,22 @@ def penalty_adjoint(X, G, w, want=("dX", "dQ", "db", "dp")):
 
 
 def round_objective(Q, b, X):
-    """x^ = [X > 1/2] and the exact int64 objective of every row of X."""
+    """x^ = [X > 1/2] and the objective of every row of X: exact int64 for
+    int32 Q and b, the correctly rounded FP64 sum for float64 Q and b."""
     torch = _torch()
     lib = load()
-    _dev(Q, torch.int32, "Q")
-    _dev(b, torch.int32, "b")
+    real = Q.dtype == torch.float64
+    vt = torch.float64 if real else torch.int32
+    _dev(Q, vt, "Q")
+    _dev(b, vt, "b")
     _dev(X, torch.float64, "X")
     n = b.shape[0]
     X2 = X.reshape(-1, n)
     B = X2.shape[0]
     xhat = torch.empty((B, n), dtype=torch.uint8, device=X.device)
-    obj = torch.empty(B, dtype=torch.int64, device=X.device)
-    _check(lib.psdp_round_objective_i32(_ptr(Q), _ptr(b), n, _ptr(X2), B, _ptr(xhat), _ptr(obj), _stream()))
+    obj = torch.empty(B, dtype=torch.float64 if real else torch.int64, device=X.device)
+    fn = lib.psdp_round_objective_f64 if real else lib.psdp_round_objective_i32
+    _check(fn(_ptr(Q), _ptr(b), n, _ptr(X2), B, _ptr(xhat), _ptr(obj), _stream()))
     return xhat, obj
 
 
@@ -339,6 +398,22 @@ def qx_digits(Q, X, digits: int = 4, sparse: bool = False):
     Y = torch.empty((B, n), dtype=torch.float64, device=X.device)
     fn = lib.psdp_qx_sparse if sparse else lib.psdp_qx_digits
     _check(fn(_ptr(Q), n, _ptr(X2), B, int(digits), _ptr(Y), _stream()))
+    return Y
+
+
+def qx_dense(Q, X, dtype: str = "f32"):
+    """The batched solver's floating-point product (psdp_qx_dense): rows of
+    X (shape (B, n) float64) times Q with a zero diagonal, through the kernel
+    the solver picks for B columns, returned as (B, n) float64."""
+    torch = _torch()
+    lib = load()
+    _dev(Q, torch.int32, "Q")
+    _dev(X, torch.float64, "X")
+    n = Q.shape[0]
+    X2 = X.reshape(-1, n)
+    B = X2.shape[0]
+    Y = torch.empty((B, n), dtype=torch.float64, device=X.device)
+    _check(lib.psdp_qx_dense({"f32": F32, "f64": F64}[dtype], _ptr(Q), n, _ptr(X2), B, _ptr(Y), _stream()))
     return Y
 
 

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -72,6 +73,7 @@ psdp_status check_params(const psdp_params &p) {
         !(p.lambda_floor_rel >= 0.0) || !(p.sigma >= 0.0) || !std::isfinite(p.sigma))
         return fail(PSDP_E_INVALID, "params: tolerance out of range");
     if (p.sparse < -1 || p.sparse > 1) return fail(PSDP_E_INVALID, "params.sparse must be -1, 0 or 1");
+    if (p.lambda_reuse < 0 || p.lambda_reuse > 1) return fail(PSDP_E_INVALID, "params.lambda_reuse must be 0 or 1");
     if (p.sparse == 1 && p.qx_dtype != PSDP_I8)
         return fail(PSDP_E_UNSUPPORTED, "sparse products need I8 operands");
     return PSDP_OK;
@@ -103,32 +105,61 @@ constexpr int64_t kSparseMinN = 4096;
 bool sparse_worth_building(int64_t n, int64_t nnz) { return n >= kSparseMinN && 64 * nnz <= n * n; }
 bool sparse_batch(int64_t n, int64_t nnz, int live) { return (double)nnz * 2.0 * live <= 0.25 * (double)n * (double)n; }
 
-// Limits of one integer instance from its largest magnitudes: the int64
-// objective bound and what each operand type represents exactly.
-psdp_status check_limits(int64_t n, uint64_t qmax, uint64_t offmax, uint64_t bmax, const psdp_params &p) {
-    // |f(x)| <= n^2 max|Q| + n max|b| must stay below 2^62
-    const long double bound = (long double)n * n * qmax + (long double)n * bmax;
-    if (bound >= 4.611686018427388e18L) return fail(PSDP_E_OVERFLOW, "n^2 max|Q| + n max|b| >= 2^62");
-    if (p.qx_dtype == PSDP_BF16 && p.perturb == PSDP_PERTURB_FULL && p.sigma > 0.0)
-        return fail(PSDP_E_UNSUPPORTED, "FULL perturbation is not exact in bfloat16 operands");
-    if (p.qx_dtype == PSDP_BF16 && offmax > 256)
-        return fail(PSDP_E_UNSUPPORTED, "bfloat16 operands need |Q_ij| <= 256 off the diagonal");
-    if (p.qx_dtype == PSDP_F32 && offmax > (1u << 24))
-        return fail(PSDP_E_UNSUPPORTED, "float operands need |Q_ij| <= 2^24 off the diagonal");
-    if (p.qx_dtype == PSDP_I8 && offmax > 127)
-        return fail(PSDP_E_UNSUPPORTED, "int8 operands need |Q_ij| <= 127 off the diagonal");
-    if (p.qx_dtype == PSDP_I8 && p.perturb == PSDP_PERTURB_FULL && p.sigma > 0.0)
+// What the device checks found about one instance, in host terms. For
+// integer data the magnitudes are integers; for real data they come back as
+// the bit patterns of non-negative doubles.
+struct InstFacts {
+    bool real = false;
+    double qmax = 0.0, offmax = 0.0, bmax = 0.0;
+    uint64_t nonint_off = 0, non32_off = 0, non16_off = 0;
+};
+
+double bits_to_double(uint64_t u) {
+    double d;
+    std::memcpy(&d, &u, sizeof d);
+    return d;
+}
+
+// Limits of one instance from its largest magnitudes: the objective bound
+// and what each operand type represents exactly.
+psdp_status check_limits(int64_t n, const InstFacts &f, const psdp_params &p) {
+    const bool full = p.perturb == PSDP_PERTURB_FULL && p.sigma > 0.0;
+    const long double bound = (long double)n * n * f.qmax + (long double)n * f.bmax;
+    if (!f.real) {
+        // |f(x)| <= n^2 max|Q| + n max|b| must stay below 2^62
+        if (bound >= 4.611686018427388e18L) return fail(PSDP_E_OVERFLOW, "n^2 max|Q| + n max|b| >= 2^62");
+        if (p.qx_dtype == PSDP_BF16 && full)
+            return fail(PSDP_E_UNSUPPORTED, "FULL perturbation is not exact in bfloat16 operands");
+        if (p.qx_dtype == PSDP_BF16 && f.offmax > 256)
+            return fail(PSDP_E_UNSUPPORTED, "bfloat16 operands need |Q_ij| <= 256 off the diagonal");
+        if (p.qx_dtype == PSDP_F32 && f.offmax > (double)(1u << 24))
+            return fail(PSDP_E_UNSUPPORTED, "float operands need |Q_ij| <= 2^24 off the diagonal");
+        if (p.qx_dtype == PSDP_I8 && f.offmax > 127)
+            return fail(PSDP_E_UNSUPPORTED, "int8 operands need |Q_ij| <= 127 off the diagonal");
+    } else {
+        // every partial sum of the objective (and of the products) stays finite
+        if (!(bound < 1e300L)) return fail(PSDP_E_OVERFLOW, "n^2 max|Q| + n max|b| >= 1e300");
+        if (p.qx_dtype == PSDP_BF16 && (full || f.non16_off))
+            return fail(PSDP_E_UNSUPPORTED, "bfloat16 operands need Q~ off the diagonal exact in bfloat16");
+        if (p.qx_dtype == PSDP_F32 && f.non32_off)
+            return fail(PSDP_E_UNSUPPORTED, "float operands need Q off the diagonal exact in float");
+        if (p.qx_dtype == PSDP_I8 && f.nonint_off)
+            return fail(PSDP_E_UNSUPPORTED, "int8 operands need integral |Q_ij| <= 127 off the diagonal");
+    }
+    if (p.qx_dtype == PSDP_I8 && full)
         return fail(PSDP_E_UNSUPPORTED, "FULL perturbation is not integer (int8 operands)");
     return PSDP_OK;
 }
 
-// Checks of one integer instance on the device (device pointers, stream
-// st), in this order: exact symmetry of Q, the limits above, X0 (nx
-// entries, nullable) in [0,1], p0 (nullable) finite. rownnz (optional): the
-// off-diagonal nonzeros of every row.
-psdp_status check_instance(const int32_t *Q, const int32_t *b, int64_t n, const double *X0, int64_t nx,
-                           const double *p0, const psdp_params &p, hipStream_t st, int64_t *offmax_out = nullptr,
+// Checks of one instance (integer or real data) on the device (device
+// pointers, stream st), in this order: finite entries (real data), exact
+// symmetry of Q, the limits above, X0 (nx entries, nullable) in [0,1], p0
+// (nullable) finite. rownnz (optional): the off-diagonal nonzeros of every row.
+template <typename T>
+psdp_status check_instance(const T *Q, const T *b, int64_t n, const double *X0, int64_t nx, const double *p0,
+                           const psdp_params &p, hipStream_t st, InstFacts *facts_out = nullptr,
                            std::vector<int64_t> *rownnz = nullptr) {
+    constexpr bool kReal = std::is_same<T, double>::value;
     Arena ar;
     CheckOut *o;
     int32_t *rn = nullptr;
@@ -146,33 +177,27 @@ psdp_status check_instance(const int32_t *Q, const int32_t *b, int64_t n, const 
         HIPCHK(hipMemcpyAsync(hr.data(), rn, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
+    if (h.nonfinite) return fail(PSDP_E_NONFINITE, "Q and b must be finite");
     if (h.first_asym != ~0ull) {
         const long long i = (long long)(h.first_asym / (uint64_t)n), j = (long long)(h.first_asym % (uint64_t)n);
         char buf[128];
         snprintf(buf, sizeof buf, "Q[%lld][%lld] != Q[%lld][%lld]", i, j, j, i);
         return fail(PSDP_E_NOT_SYMMETRIC, buf);
     }
-    if (psdp_status s = check_limits(n, h.qmax, h.offmax, h.bmax, p)) return s;
+    InstFacts f;
+    f.real = kReal;
+    f.qmax = kReal ? bits_to_double(h.qmax) : (double)h.qmax;
+    f.offmax = kReal ? bits_to_double(h.offmax) : (double)h.offmax;
+    f.bmax = kReal ? bits_to_double(h.bmax) : (double)h.bmax;
+    f.nonint_off = h.nonint_off;
+    f.non32_off = h.non32_off;
+    f.non16_off = h.non16_off;
+    if (psdp_status s = check_limits(n, f, p)) return s;
     if (h.x0_bad) return fail(PSDP_E_NONFINITE, "X0 entries must lie in [0,1]");
     if (h.p0_bad) return fail(PSDP_E_NONFINITE, "p0 must be finite");
-    if (offmax_out) *offmax_out = (int64_t)h.offmax;
+    if (facts_out) *facts_out = f;
     if (rownnz) rownnz->assign(hr.begin(), hr.end());
     return PSDP_OK;
-}
-
-__global__ void gamma_kernel(const int32_t *b, const double *R, const double *dq, int64_t n,
-                             int64_t ld, double *bd, double *gam) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ld) return;
-    if (i < n) {
-        const double bi = (double)b[i];
-        bd[i] = bi;
-        // gamma_i = 2 sum_j |Q~_ij| + |b_i| + 1 (Section 3.5, strict margin 1)
-        gam[i] = 2.0 * (R[i] + fabs(dq[i])) + fabs(bi) + 1.0;
-    } else {
-        bd[i] = 0.0;
-        gam[i] = 0.0;
-    }
 }
 
 __global__ void fill_p_kernel(double *p, const double *p0, int64_t n, int64_t ld, int ncol) {
@@ -183,6 +208,58 @@ __global__ void fill_p_kernel(double *p, const double *p0, int64_t n, int64_t ld
 }
 
 constexpr int kMaxSplit = 8;
+
+// Floating-point Q.X kernel for a batch: up to 64 columns the wave-streaming
+// kernel (needs the FP32 copy of Q), above that the LDS-tiled GEMM with
+// enough split-K for ~512 tiles. ncols: columns of the list; live: the live
+// count of the last poll (est bounds the grid); MT: 64-row tiles of Q.
+struct Pick { bool stream; int nt; int ks; int est; };
+Pick pick_product(int B, int ncols, int live, int gemm_dtype, int gemm_variant, int64_t MT) {
+    Pick pk{false, 4, 1, std::min({B, ncols + 16, live})};
+    if (gemm_variant > 0) {
+        pk.ks = std::min(kMaxSplit, gemm_variant & 0xff);
+        pk.stream = (gemm_variant & 0x100) != 0 && gemm_dtype != PSDP_F64;
+        pk.nt = 4;
+        return pk;
+    }
+    if (ncols <= 64 && gemm_dtype != PSDP_F64) {
+        pk.stream = true;
+        pk.nt = ncols <= 16 ? 1 : (ncols <= 32 ? 2 : 4);
+        pk.ks = 4;
+        return pk;
+    }
+    const int tiles = (int)MT * std::max(1, (ncols + 63) / 64);
+    pk.ks = std::max(1, std::min(kMaxSplit, (512 + tiles - 1) / tiles));
+    return pk;
+}
+
+// Operand columns of a product from X (n x B, leading dimension n): entry
+// converted to the operand type, padded with zeros to ld.
+template <typename OpT>
+__global__ void pack_operand_kernel(const double *X, int64_t n, int64_t ld, int B, OpT *op) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ld * B) return;
+    const int64_t c = idx / ld, i = idx % ld;
+    op[idx] = i < n ? from_f64<OpT>(X[c * n + i]) : from_f64<OpT>(0.0);
+}
+
+// Y = the K slices of U summed in slice order in FP64, as the column kernel
+// reads them.
+template <typename UT>
+__global__ void sum_slices_kernel(const UT *U, int64_t slice, int ks, int64_t n, int64_t ld, int B, double *Y) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * B) return;
+    const int64_t c = idx / n, i = idx % n;
+    double u = to_f64<UT>(U[c * ld + i]);
+    for (int t = 1; t < ks; ++t) u += to_f64<UT>(U[t * slice + c * ld + i]);
+    Y[idx] = u;
+}
+
+__global__ void iota_list_kernel(int32_t *a, int B) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < B) a[i] = i;
+    if (i == 0) a[B] = B;
+}
 
 struct Solver {
     Arena ar;
@@ -250,6 +327,7 @@ void fill_work_params(Work &w, const psdp_params &p) {
     w.stall_outer = p.stall_outer;
     w.eig_maxit = p.eig_maxit;
     w.cg_maxit = p.cg_maxit;
+    w.lambda_reuse = p.lambda_reuse;
     w.tol_kkt = p.tol_kkt;
     w.tol_binary = p.tol_binary;
     w.eta = p.eta;
@@ -505,65 +583,13 @@ void fill_stats(const std::vector<Col> &cols, int64_t sweeps, const QxTimer &tm,
     }
 }
 
-}  // namespace
-
-// ===========================================================================
-
-extern "C" {
-
-void psdp_params_default(psdp_params *p) {
-    if (!p) return;
-    std::memset(p, 0, sizeof *p);
-    p->struct_size = sizeof(psdp_params);
-    p->inner = PSDP_INNER_PABB;
-    p->qx_dtype = PSDP_F64;
-    p->perturb = PSDP_PERTURB_NONE;
-    p->max_inner = 10000;
-    p->max_outer = 1000;
-    p->stall_outer = 2;
-    p->eig_maxit = 500;
-    p->cg_maxit = 500;
-    p->timing = 0;
-    p->poll_sweeps = 64;
-    p->gemm_variant = -1;
-    p->graph = 1;
-    p->sparse = -1;
-    p->tol_kkt = 1e-5;
-    p->tol_binary = 1e-5;
-    p->eta = 0.999;
-    p->eps_hp = 1e-8;
-    p->lambda_floor_rel = 1e-8;
-    p->alpha_min = 1e-30;
-    p->alpha_max = 1e30;
-    p->sigma = 0.0;
-    p->eig_tol = 1e-7;
-    p->cg_tol = 1e-12;
-    p->seed = 0;
-}
-
-const char *psdp_status_string(psdp_status s) {
-    switch (s) {
-        case PSDP_OK: return "ok";
-        case PSDP_E_INVALID: return "invalid argument";
-        case PSDP_E_NOT_SYMMETRIC: return "Q is not symmetric";
-        case PSDP_E_NONFINITE: return "non-finite or out-of-range input";
-        case PSDP_E_OVERFLOW: return "objective bound overflows int64";
-        case PSDP_E_DEVICE: return "HIP device error";
-        case PSDP_E_NOMEM: return "out of device memory";
-        case PSDP_E_UNSUPPORTED: return "unsupported combination";
-    }
-    return "unknown status";
-}
-
-const char *psdp_last_error(void) { return g_err.c_str(); }
-
-int32_t psdp_version(void) { return 10000; }
-
-psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, const double *X0,
-                              const double *p0, int32_t B, const psdp_params *prm_in,
-                              uint8_t *xhat, int64_t *obj, double *X_out, int32_t *best,
-                              psdp_stats *stats, double *trace, int32_t trace_cap,
-                              hipStream_t st) {
+// Algorithm 3 on B starts of one instance with integer (T = int32_t, obj
+// int64) or real (T = double, obj FP64) data.
+template <typename T, typename ObjT>
+psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, const double *p0, int32_t B,
+                       const psdp_params *prm_in, uint8_t *xhat, ObjT *obj, double *X_out, int32_t *best,
+                       psdp_stats *stats, double *trace, int32_t trace_cap, const double *alpha_in,
+                       int32_t alpha_cap, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_lock);
     g_err.clear();
     psdp_params prm;
@@ -577,13 +603,18 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     if (n < 1 || B < 1) return fail(PSDP_E_INVALID, "n and B must be >= 1");
     if (!X0 && B != 1) return fail(PSDP_E_INVALID, "X0 = NULL needs B = 1");
     if (trace && trace_cap < 1) return fail(PSDP_E_INVALID, "trace_cap");
+    if (alpha_in && alpha_cap < 1) return fail(PSDP_E_INVALID, "alpha_cap");
+    if (alpha_in)
+        for (int64_t q = 0; q < (int64_t)B * alpha_cap; ++q)
+            if (!(std::isfinite(alpha_in[q]) && alpha_in[q] > 0.0))
+                return fail(PSDP_E_INVALID, "alpha_in entries must be finite and positive");
     if (n > 65536) return fail(PSDP_E_UNSUPPORTED, "n > 65536");
     // validation on the device; a few words come back (the caller's stream is
     // synchronized, so the inputs are ready for the solve stream too)
-    int64_t offmax = 0;
+    InstFacts facts;
     std::vector<int64_t> rownnz;
     const bool want_counts = prm.qx_dtype == PSDP_I8 && prm.sparse != 0;
-    if (psdp_status s = check_instance(Q, b, n, X0, X0 ? n * B : 0, p0, prm, st, &offmax,
+    if (psdp_status s = check_instance(Q, b, n, X0, X0 ? n * B : 0, p0, prm, st, &facts,
                                        want_counts ? &rownnz : nullptr))
         return s;
     std::vector<int32_t> hrowptr;
@@ -616,9 +647,11 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     w.i8 = i8 ? 1 : 0;
     // Q~ off the diagonal is exact in FP32 for integers up to 2^24 unless a
     // FULL perturbation adds 2^-16-grid values to entries of 2^8 or more
-    const bool q32_exact = offmax <= (1 << 24) &&
-                           (prm.perturb != PSDP_PERTURB_FULL || prm.sigma == 0.0 ||
-                            (double)offmax + 3.5 * prm.sigma < 256.0);
+    // (real data: every off-diagonal entry a float, and no FULL perturbation)
+    const bool no_full = prm.perturb != PSDP_PERTURB_FULL || prm.sigma == 0.0;
+    const bool q32_exact = facts.real ? (facts.non32_off == 0 && no_full)
+                                      : (facts.offmax <= (double)(1 << 24) &&
+                                         (no_full || facts.offmax + 3.5 * prm.sigma < 256.0));
     // Qop: operand of the main product; Qaux: operand of the FP64 products
     // (the exact FP32 copy widened in the kernel, or an FP64 copy)
     const int qtype = i8 ? PSDP_I8
@@ -661,9 +694,7 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
         HIPCHK(S.ar.get(&Qaux, ld * ld * sizeof(double)));
         HIPCHK(launch_prep_q(PSDP_F64, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qaux, R, dq, st));
     }
-    hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, st, b, R, dq, n, ld,
-                       bd, gam);
-    HIPCHK(hipGetLastError());
+    HIPCHK(launch_gamma(b, R, dq, n, ld, bd, gam, st));
     w.b = bd;
     w.gam = gam;
     w.R = R;
@@ -691,25 +722,9 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     // poll: the estimate is the list's count plus 16, at most that total.
     // up to 64 live columns the wave-streaming kernel (needs the FP32 copy of
     // Q), above that the LDS-tiled GEMM with enough split-K for ~512 tiles.
-    struct Pick { bool stream; int nt; int ks; int est; };
     auto pick = [&](int ncols, int live, int gemm_dtype) {
-        Pick pk{false, 4, 1, std::min({B, ncols + 16, live})};
-        if (!batched) return pk;
-        if (prm.gemm_variant > 0) {
-            pk.ks = std::min(kMaxSplit, prm.gemm_variant & 0xff);
-            pk.stream = (prm.gemm_variant & 0x100) != 0 && gemm_dtype != PSDP_F64;
-            pk.nt = 4;
-            return pk;
-        }
-        if (ncols <= 64 && gemm_dtype != PSDP_F64) {
-            pk.stream = true;
-            pk.nt = ncols <= 16 ? 1 : (ncols <= 32 ? 2 : 4);
-            pk.ks = 4;
-            return pk;
-        }
-        const int tiles = MT * std::max(1, (ncols + 63) / 64);
-        pk.ks = std::max(1, std::min(kMaxSplit, (512 + tiles - 1) / tiles));
-        return pk;
+        if (!batched) return Pick{false, 4, 1, std::min({B, ncols + 16, live})};
+        return pick_product(B, ncols, live, gemm_dtype, prm.gemm_variant, MT);
     };
     // integer path: layouts from the estimated live counts, K slices from
     // the blocks of both products (they share one launch)
@@ -754,6 +769,13 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     if (trace) {
         HIPCHK(S.ar.get((void **)&w.trace, (size_t)B * trace_cap * 6 * sizeof(double)));
         w.trace_cap = trace_cap;
+    }
+    if (alpha_in) {
+        double *da;
+        HIPCHK(S.ar.get((void **)&da, (size_t)B * alpha_cap * sizeof(double)));
+        HIPCHK(hipMemcpyAsync(da, alpha_in, (size_t)B * alpha_cap * sizeof(double), hipMemcpyHostToDevice, st));
+        w.alpha_in = da;
+        w.alpha_cap = alpha_cap;
     }
     HIPCHK(launch_solver_init(S.optype, w, X0, X0 ? 0 : 1, st));
     HIPCHK(launch_compact(w, st));
@@ -851,20 +873,27 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
                         1e3 * (double)hp[3 * q] / hp[3 * q + 1] / rate_khz, 1e3 * (double)hp[3 * q + 2] / rate_khz);
     }
     // rounding and exact objective on the original data
-    int64_t *partial;
-    const int64_t nblk = (n + 15) / 16;
-    HIPCHK(S.ar.get((void **)&partial, nblk * B * sizeof(int64_t)));
-    HIPCHK(launch_round_objective(Q, b, n, w.x, ld, B, xhat, n, obj, partial, st));
+    if constexpr (std::is_same<T, double>::value) {
+        int64_t *acc;
+        HIPCHK(S.ar.get((void **)&acc, (size_t)B * kObjAccWords * sizeof(int64_t)));
+        HIPCHK(hipMemsetAsync(acc, 0, (size_t)B * kObjAccWords * sizeof(int64_t), st));
+        HIPCHK(launch_round_objective(Q, b, n, w.x, ld, B, xhat, n, obj, acc, st));
+    } else {
+        int64_t *partial;
+        const int64_t nblk = (n + 15) / 16;
+        HIPCHK(S.ar.get((void **)&partial, nblk * B * sizeof(int64_t)));
+        HIPCHK(launch_round_objective(Q, b, n, w.x, ld, B, xhat, n, obj, partial, st));
+    }
     if (X_out)
         HIPCHK(hipMemcpy2DAsync(X_out, n * sizeof(double), w.x, ld * sizeof(double), n * sizeof(double), B,
                                 hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(hcol.data(), w.col, B * sizeof(Col), hipMemcpyDeviceToHost, st));
     int64_t nsweeps = 0;
     HIPCHK(hipMemcpyAsync(&nsweeps, S.sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    std::vector<int64_t> hobj;
+    std::vector<ObjT> hobj;
     if (best) {
         hobj.resize(B);
-        HIPCHK(hipMemcpyAsync(hobj.data(), obj, B * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hobj.data(), obj, B * sizeof(ObjT), hipMemcpyDeviceToHost, st));
     }
     if (trace)
         HIPCHK(hipMemcpyAsync(trace, w.trace, (size_t)B * trace_cap * 6 * sizeof(double),
@@ -890,15 +919,106 @@ psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, con
     return PSDP_OK;
 }
 
+}  // namespace
+
+namespace psdp {
+// The thread-local error detail of psdp_last_error, for the entry points of
+// other translation units.
+psdp_status set_error(psdp_status s, const char *msg) {
+    g_err = msg ? msg : "";
+    return s;
+}
+}  // namespace psdp
+
+// ===========================================================================
+
+extern "C" {
+
+void psdp_params_default(psdp_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(psdp_params);
+    p->inner = PSDP_INNER_PABB;
+    p->qx_dtype = PSDP_F64;
+    p->perturb = PSDP_PERTURB_NONE;
+    p->max_inner = 10000;
+    p->max_outer = 1000;
+    p->stall_outer = 2;
+    p->eig_maxit = 500;
+    p->cg_maxit = 500;
+    p->timing = 0;
+    p->poll_sweeps = 64;
+    p->gemm_variant = -1;
+    p->graph = 1;
+    p->sparse = -1;
+    p->lambda_reuse = 1;
+    p->tol_kkt = 1e-5;
+    p->tol_binary = 1e-5;
+    p->eta = 0.999;
+    p->eps_hp = 1e-8;
+    p->lambda_floor_rel = 1e-8;
+    p->alpha_min = 1e-30;
+    p->alpha_max = 1e30;
+    p->sigma = 0.0;
+    p->eig_tol = 1e-7;
+    p->cg_tol = 1e-12;
+    p->seed = 0;
+}
+
+const char *psdp_status_string(psdp_status s) {
+    switch (s) {
+        case PSDP_OK: return "ok";
+        case PSDP_E_INVALID: return "invalid argument";
+        case PSDP_E_NOT_SYMMETRIC: return "Q is not symmetric";
+        case PSDP_E_NONFINITE: return "non-finite or out-of-range input";
+        case PSDP_E_OVERFLOW: return "objective bound overflows int64";
+        case PSDP_E_DEVICE: return "HIP device error";
+        case PSDP_E_NOMEM: return "out of device memory";
+        case PSDP_E_UNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown status";
+}
+
+const char *psdp_last_error(void) { return g_err.c_str(); }
+
+int32_t psdp_version(void) { return 10000; }
+
+psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, const double *X0,
+                              const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
+                              int64_t *obj, double *X_out, int32_t *best, psdp_stats *stats,
+                              double *trace, int32_t trace_cap, const double *alpha_in, int32_t alpha_cap,
+                              hipStream_t st) {
+    return solve_impl<int32_t, int64_t>(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats, trace,
+                                        trace_cap, alpha_in, alpha_cap, st);
+}
+
 psdp_status psdp_solve_i32(const int32_t *Q, const int32_t *b, int64_t n, const double *X0,
                            const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
                            int64_t *obj, double *X_out, int32_t *best, psdp_stats *stats,
                            hipStream_t st) {
-    return psdp_solve_i32_ex(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats, nullptr, 0, st);
+    return solve_impl<int32_t, int64_t>(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats, nullptr, 0,
+                                        nullptr, 0, st);
+}
+
+psdp_status psdp_solve_f64_ex(const double *Q, const double *b, int64_t n, const double *X0,
+                              const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
+                              double *obj, double *X_out, int32_t *best, psdp_stats *stats,
+                              double *trace, int32_t trace_cap, const double *alpha_in, int32_t alpha_cap,
+                              hipStream_t st) {
+    return solve_impl<double, double>(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats, trace,
+                                      trace_cap, alpha_in, alpha_cap, st);
+}
+
+psdp_status psdp_solve_f64(const double *Q, const double *b, int64_t n, const double *X0,
+                           const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
+                           double *obj, double *X_out, int32_t *best, psdp_stats *stats,
+                           hipStream_t st) {
+    return solve_impl<double, double>(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats, nullptr, 0,
+                                      nullptr, 0, st);
 }
 
 psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t *const *Q,
-                                 const int32_t *const *b, const uint64_t *seeds,
+                                 const int32_t *const *b, const uint64_t *seeds, const double *sigmas,
                                  const psdp_params *prm_in, uint8_t *const *xhat, int64_t *obj,
                                  psdp_stats *stats, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_lock);
@@ -916,8 +1036,15 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         if (n[i] < 1 || n[i] > 65536) return fail(PSDP_E_INVALID, "instance size out of range");
         if (!Q[i] || !b[i] || !xhat[i]) return fail(PSDP_E_INVALID, "null instance pointer");
     }
+    // per-instance perturbation scale (sigmas) or the parameters' one
+    auto sigma_of = [&](int i) { return sigmas ? sigmas[i] : prm.sigma; };
+    for (int i = 0; i < count; ++i)
+        if (!(sigma_of(i) >= 0.0) || !std::isfinite(sigma_of(i)))
+            return fail(PSDP_E_INVALID, "instance " + std::to_string(i) + ": sigma must be finite and >= 0");
     for (int i = 0; i < count; ++i) {
-        if (psdp_status s = check_instance(Q[i], b[i], n[i], nullptr, 0, nullptr, prm, st)) {
+        psdp_params pi = prm;
+        pi.sigma = sigma_of(i);
+        if (psdp_status s = check_instance(Q[i], b[i], n[i], nullptr, 0, nullptr, pi, st)) {
             g_err = "instance " + std::to_string(i) + ": " + g_err;
             return s;
         }
@@ -946,11 +1073,9 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         void *Qop;
         HIPCHK(S.ar.get(&Qop, ld[i] * ld[i] * esize(prm.qx_dtype)));
         const uint64_t seed = seeds ? seeds[i] : prm.seed;
-        HIPCHK(launch_prep_q(prm.qx_dtype, Q[i], n[i], ld[i], prm.perturb, prm.sigma, seed, Qop, R + off[i],
+        HIPCHK(launch_prep_q(prm.qx_dtype, Q[i], n[i], ld[i], prm.perturb, sigma_of(i), seed, Qop, R + off[i],
                              dq + off[i], st));
-        hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((ld[i] + 255) / 256)), dim3(256), 0, st, b[i],
-                           R + off[i], dq + off[i], n[i], ld[i], bd + off[i], gam + off[i]);
-        HIPCHK(hipGetLastError());
+        HIPCHK(launch_gamma(b[i], R + off[i], dq + off[i], n[i], ld[i], bd + off[i], gam + off[i], st));
         hin[i] = Inst{n[i], ld[i], off[i], Qop};
     }
     w.b = bd;
@@ -1180,6 +1305,58 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     return PSDP_OK;
 }
 
+psdp_status psdp_qx_dense(int32_t dtype, const int32_t *Q, int64_t n, const double *X, int32_t B, double *Y,
+                          hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    if (dtype != PSDP_F32 && dtype != PSDP_F64) return fail(PSDP_E_INVALID, "dtype must be F32 or F64");
+    if (!Q || !X || !Y) return fail(PSDP_E_INVALID, "null pointer");
+    if (n < 1 || n > 65536 || B < 1) return fail(PSDP_E_INVALID, "n must be in [1, 65536] and B >= 1");
+    psdp_params prm;
+    psdp_params_default(&prm);
+    prm.qx_dtype = dtype;
+    InstFacts facts;
+    if (psdp_status s = check_instance(Q, Q, n, nullptr, 0, nullptr, prm, st, &facts)) return s;
+    const bool q32 = facts.offmax <= (double)(1 << 24);
+    if (!q32) return fail(PSDP_E_UNSUPPORTED, "the products read an FP32 copy of Q: |Q_ij| <= 2^24 needed");
+    Arena ar;
+    const int64_t ld = padld(n), MT = (ld + 63) / 64;
+    const int gemm_dtype = dtype == PSDP_F32 ? PSDP_F32 : kGemmF32QF64;
+    const Pick pk = pick_product(B, B, B, gemm_dtype, -1, MT);
+    void *Qop, *op, *U;
+    double *R, *dq;
+    int32_t *act;
+    const size_t oe = dtype == PSDP_F32 ? 4 : 8;
+    const int64_t slice = ld * B;
+    HIPCHK(ar.get(&Qop, ld * ld * sizeof(float)));
+    HIPCHK(ar.get((void **)&R, ld * 8));
+    HIPCHK(ar.get((void **)&dq, ld * 8));
+    HIPCHK(launch_prep_q(PSDP_F32, Q, n, ld, PSDP_PERTURB_NONE, 0.0, 0, Qop, R, dq, st));
+    HIPCHK(ar.get(&op, slice * oe));
+    HIPCHK(ar.get(&U, slice * oe * pk.ks));
+    HIPCHK(ar.get((void **)&act, (B + 1) * sizeof(int32_t)));
+    const unsigned g = (unsigned)((slice + 255) / 256), gy = (unsigned)((n * B + 255) / 256);
+    if (dtype == PSDP_F32)
+        hipLaunchKernelGGL(pack_operand_kernel<float>, dim3(g), dim3(256), 0, st, X, n, ld, B, (float *)op);
+    else
+        hipLaunchKernelGGL(pack_operand_kernel<double>, dim3(g), dim3(256), 0, st, X, n, ld, B, (double *)op);
+    hipLaunchKernelGGL(iota_list_kernel, dim3((unsigned)((B + 256) / 256)), dim3(256), 0, st, act, B);
+    HIPCHK(hipGetLastError());
+    if (pk.stream)
+        HIPCHK(launch_stream(gemm_dtype, Qop, ld, op, U, act, act + B, slice, pk.ks, pk.est, pk.nt, st));
+    else
+        HIPCHK(launch_gemm(gemm_dtype, Qop, ld, op, U, act, act + B, slice, pk.ks, B, st));
+    if (dtype == PSDP_F32)
+        hipLaunchKernelGGL(sum_slices_kernel<float>, dim3(gy), dim3(256), 0, st, (const float *)U, slice, pk.ks, n,
+                           ld, B, Y);
+    else
+        hipLaunchKernelGGL(sum_slices_kernel<double>, dim3(gy), dim3(256), 0, st, (const double *)U, slice, pk.ks,
+                           n, ld, B, Y);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return PSDP_OK;
+}
+
 psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits, double *Y,
                            hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_lock);
@@ -1223,6 +1400,81 @@ psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t
     HIPCHK(launch_digit_combine(U0, U1, n, ld, B, D, esc, Y, st));
     HIPCHK(hipStreamSynchronize(st));
     return PSDP_OK;
+}
+
+psdp_status psdp_round_objective_f64(const double *Q, const double *b, int64_t n, const double *X,
+                                     int64_t B, uint8_t *xhat, double *obj, hipStream_t st) {
+    g_err.clear();
+    if (!Q || !b || !X || !xhat || !obj) return fail(PSDP_E_INVALID, "null required pointer");
+    if (n < 1 || B < 1 || B > 65535 || n > 65536) return fail(PSDP_E_INVALID, "sizes");
+    int64_t *acc = nullptr;
+    const size_t bytes = (size_t)B * kObjAccWords * sizeof(int64_t);
+    HIPCHK(hipMallocAsync((void **)&acc, bytes, st));
+    hipError_t e = hipMemsetAsync(acc, 0, bytes, st);
+    if (e == hipSuccess) e = launch_round_objective(Q, b, n, X, n, B, xhat, n, obj, acc, st);
+    hipError_t e2 = hipFreeAsync(acc, st);
+    if (e != hipSuccess) return hipfail(e, "round_objective");
+    if (e2 != hipSuccess) return hipfail(e2, "hipFreeAsync");
+    return PSDP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host-pointer form of the solve: device copies of the inputs, the device
+// entry point on the null stream, the outputs copied back.
+template <typename T, typename ObjT>
+psdp_status solve_host(const T *Q, const T *b, int64_t n, const double *X0, const double *p0, int32_t B,
+                       const psdp_params *prm, uint8_t *xhat, ObjT *obj, double *X_out, int32_t *best,
+                       psdp_stats *stats) {
+    g_err.clear();
+    if (!Q || !b || !xhat || !obj) return fail(PSDP_E_INVALID, "null required pointer");
+    if (n < 1 || B < 1) return fail(PSDP_E_INVALID, "n and B must be >= 1");
+    if (n > 65536) return fail(PSDP_E_UNSUPPORTED, "n > 65536");
+    Arena ar;
+    T *dQ, *db;
+    double *dX0 = nullptr, *dp0 = nullptr, *dX = nullptr;
+    uint8_t *dxh;
+    ObjT *dobj;
+    HIPCHK(ar.get((void **)&dQ, (size_t)n * n * sizeof(T)));
+    HIPCHK(ar.get((void **)&db, (size_t)n * sizeof(T)));
+    HIPCHK(hipMemcpy(dQ, Q, (size_t)n * n * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(db, b, (size_t)n * sizeof(T), hipMemcpyHostToDevice));
+    if (X0) {
+        HIPCHK(ar.get((void **)&dX0, (size_t)n * B * sizeof(double)));
+        HIPCHK(hipMemcpy(dX0, X0, (size_t)n * B * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (p0) {
+        HIPCHK(ar.get((void **)&dp0, (size_t)n * sizeof(double)));
+        HIPCHK(hipMemcpy(dp0, p0, (size_t)n * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIPCHK(ar.get((void **)&dxh, (size_t)n * B));
+    HIPCHK(ar.get((void **)&dobj, (size_t)B * sizeof(ObjT)));
+    if (X_out) HIPCHK(ar.get((void **)&dX, (size_t)n * B * sizeof(double)));
+    psdp_status s = solve_impl<T, ObjT>(dQ, db, n, dX0, dp0, B, prm, dxh, dobj, dX, best, stats, nullptr, 0,
+                                        nullptr, 0, nullptr);
+    if (s != PSDP_OK) return s;
+    HIPCHK(hipMemcpy(xhat, dxh, (size_t)n * B, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(obj, dobj, (size_t)B * sizeof(ObjT), hipMemcpyDeviceToHost));
+    if (X_out) HIPCHK(hipMemcpy(X_out, dX, (size_t)n * B * sizeof(double), hipMemcpyDeviceToHost));
+    return PSDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psdp_status psdp_solve_host_i32(const int32_t *Q, const int32_t *b, int64_t n, const double *X0,
+                                const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
+                                int64_t *obj, double *X_out, int32_t *best, psdp_stats *stats) {
+    return solve_host<int32_t, int64_t>(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats);
+}
+
+psdp_status psdp_solve_host_f64(const double *Q, const double *b, int64_t n, const double *X0,
+                                const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
+                                double *obj, double *X_out, int32_t *best, psdp_stats *stats) {
+    return solve_host<double, double>(Q, b, n, X0, p0, B, prm, xhat, obj, X_out, best, stats);
 }
 
 void psdp_release(void) {}

@@ -123,9 +123,14 @@ struct Work {
     unsigned long long *phase_prof;  // optional per-phase {sum, count, max} of step ticks
     double *trace;       // per column trace_cap records of 6 doubles, or null
     int32_t trace_cap;
+    // prescribed penalty steps (a parity hook): update s < alpha_cap of the
+    // column with id c takes alpha_in[c * alpha_cap + s]; null: computed
+    const double *alpha_in;
+    int32_t alpha_cap;
     // parameters
     int32_t inner;       // psdp_inner
     int32_t max_inner, max_outer, stall_outer, eig_maxit, cg_maxit;
+    int32_t lambda_reuse;  // shift-law lambda_min after a subproblem that left x unchanged
     double tol_kkt, tol_binary, eta, eps_hp, lambda_floor_rel, alpha_min, alpha_max;
     double eig_tol, cg_tol;
 };
@@ -282,6 +287,86 @@ __device__ __forceinline__ void block_maxsum(double (&mx)[NM], double (&sm)[NS],
     __syncthreads();
 }
 
+// Double-double sums (Ogita, Rump and Oishi, "Accurate sum and dot
+// product", 2005: Sum2 / Dot2): a pair (h, l) carries a value h + l; every
+// addition keeps the rounding error of the high part exactly (TwoSum) and a
+// product enters as its exact pair (a b rounded, and the fma residual). The
+// result h + l, rounded once, is the exact sum rounded to nearest unless the
+// exact sum lies within about n^2 2^-106 of the summed magnitudes of a
+// rounding boundary, so it agrees with an exact reference in practice and does
+// not depend on the order of the terms. Needs fp-contraction off (the build
+// sets it) so that no TwoSum is fused.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void dd_add(double &h, double &l, double h2, double l2) {
+    double s, e;
+    two_sum(h, h2, s, e);
+    h = s;
+    l = (l + l2) + e;
+}
+__device__ __forceinline__ void dd_add_prod(double &h, double &l, double a, double b) {
+    const double p = a * b;
+    const double pe = fma(a, b, -p);
+    double s, e;
+    two_sum(h, p, s, e);
+    h = s;
+    l = l + (e + pe);
+}
+
+// The DPP pattern of wave_sum_to_63 on pairs: lane 63 ends with the wave's pair.
+__device__ __forceinline__ void wave_ddsum_to_63(double &h, double &l) {
+    dd_add(h, l, dpp_f64<kDppRowShr1, 0xf>(h), dpp_f64<kDppRowShr1, 0xf>(l));
+    dd_add(h, l, dpp_f64<kDppRowShr2, 0xf>(h), dpp_f64<kDppRowShr2, 0xf>(l));
+    dd_add(h, l, dpp_f64<kDppRowShr4, 0xf>(h), dpp_f64<kDppRowShr4, 0xf>(l));
+    dd_add(h, l, dpp_f64<kDppRowShr8, 0xf>(h), dpp_f64<kDppRowShr8, 0xf>(l));
+    dd_add(h, l, dpp_f64<kDppRowBcast15, 0xa>(h), dpp_f64<kDppRowBcast15, 0xa>(l));
+    dd_add(h, l, dpp_f64<kDppRowBcast31, 0xc>(h), dpp_f64<kDppRowBcast31, 0xc>(l));
+}
+
+// Max-reduction of mx and double-double sum-reduction of the pairs (h, l) in
+// one shared-memory round; on return h[j] holds the sum rounded once (and
+// l[j] zero). scratch: (NM + 2 NS) * NT / 64 doubles.
+template <int NM, int NS, int NT>
+__device__ __forceinline__ void block_maxsum_dd(double (&mx)[NM], double (&h)[NS], double (&l)[NS],
+                                                double *scratch) {
+    constexpr int kWaves = NT / 64;
+#pragma unroll
+    for (int j = 0; j < NM; ++j) mx[j] = wave_max_to_63(mx[j]);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) wave_ddsum_to_63(h[j], l[j]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 63) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j) scratch[j * kWaves + wv] = mx[j];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            scratch[(NM + 2 * j) * kWaves + wv] = h[j];
+            scratch[(NM + 2 * j + 1) * kWaves + wv] = l[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+        double v = scratch[j * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) v = fmax(v, scratch[j * kWaves + q]);
+        mx[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        double H = scratch[(NM + 2 * j) * kWaves], L = scratch[(NM + 2 * j + 1) * kWaves];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q)
+            dd_add(H, L, scratch[(NM + 2 * j) * kWaves + q], scratch[(NM + 2 * j + 1) * kWaves + q]);
+        h[j] = H + L;
+        l[j] = 0.0;
+    }
+    __syncthreads();
+}
+
 template <int N, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[N], double *scratch) {
     constexpr int kWaves = NT / 64;
@@ -325,6 +410,11 @@ __device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
 }
 
 // ---------------------------------------------------------------------------
+// Sets the thread-local detail returned by psdp_last_error (an empty string
+// for msg = nullptr) and returns s.
+psdp_status set_error(psdp_status s, const char *msg);
+
+// ---------------------------------------------------------------------------
 // Host-side launchers implemented in the kernel translation units.
 
 // Device-side input checks (check.hip): the first asymmetric entry as
@@ -332,19 +422,40 @@ __device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
 // |Q_ij| and |b_i|, and the counts of X0 entries outside [0,1] and of
 // non-finite p0 entries. rownnz (nullable, zeroed beforehand) gets the
 // off-diagonal nonzeros of every row.
+// Real (FP64) data: the magnitudes are bit patterns of non-negative doubles;
+// nonfinite counts NaN/Inf entries of Q and b; nonint_off, non32_off and
+// non16_off count the off-diagonal entries of Q that are not integers in
+// [-127, 127], not floats, not bfloat16 values (zero for integer data).
 struct CheckOut {
     uint64_t qmax, offmax, bmax, x0_bad, p0_bad, first_asym;
+    uint64_t nonfinite, nonint_off, non32_off, non16_off;
 };
 hipError_t launch_check(const int32_t *Q, const int32_t *b, int64_t n, const double *X0, int64_t nx,
+                        const double *p0, CheckOut *o, int32_t *rownnz, hipStream_t st);
+hipError_t launch_check(const double *Q, const double *b, int64_t n, const double *X0, int64_t nx,
                         const double *p0, CheckOut *o, int32_t *rownnz, hipStream_t st);
 hipError_t launch_prep_q(int dtype, const int32_t *Q, int64_t n, int64_t ld, int perturb,
                          double sigma, uint64_t seed, void *Qop, double *R, double *dq,
                          hipStream_t st);
+hipError_t launch_prep_q(int dtype, const double *Q, int64_t n, int64_t ld, int perturb,
+                         double sigma, uint64_t seed, void *Qop, double *R, double *dq,
+                         hipStream_t st);
+hipError_t launch_gamma(const int32_t *b, const double *R, const double *dq, int64_t n, int64_t ld,
+                        double *bd, double *gam, hipStream_t st);
+hipError_t launch_gamma(const double *b, const double *R, const double *dq, int64_t n, int64_t ld,
+                        double *bd, double *gam, hipStream_t st);
 hipError_t launch_perturbation(int64_t n, double sigma, uint64_t seed, int mode, double *mu,
                                hipStream_t st);
 hipError_t launch_round_objective(const int32_t *Q, const int32_t *b, int64_t n,
                                   const double *X, int64_t ldx, int64_t B, uint8_t *xhat,
                                   int64_t ldh, int64_t *obj, int64_t *partial, hipStream_t st);
+// Real data: obj_c is the exact sum of the selected Q_ij and b_i rounded once
+// to FP64 (nearest, ties to even). acc: B * kObjAccWords int64 words of
+// scratch, zero on entry (left zero on return).
+constexpr int64_t kObjAccWords = 2 * 2048;
+hipError_t launch_round_objective(const double *Q, const double *b, int64_t n,
+                                  const double *X, int64_t ldx, int64_t B, uint8_t *xhat,
+                                  int64_t ldh, double *obj, int64_t *acc, hipStream_t st);
 
 // GEMM operand mode: FP32-stored Q (exact) widened to FP64, FP64 operands.
 constexpr int kGemmF32QF64 = 16;

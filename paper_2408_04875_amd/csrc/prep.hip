@@ -7,8 +7,9 @@
 //    reformation gamma (Section 3.5, "Reformation"), rho (Section 3.3) and
 //    H_p (Section 3.1).
 //  - perturbation: the perturbation matrix alone (test hook).
-//  - round_objective: x^_i = [x_i > 1/2] and f(x^) = x^T Q x^ + b^T x^ in
-//    exact integer arithmetic on the original data (Section 2, eq. (bqp)).
+//  - round_objective: x^_i = [x_i > 1/2] and f(x^) = x^T Q x^ + b^T x^ on the
+//    original data (Section 2, eq. (bqp)): exact integer arithmetic for
+//    integer data, the exact sum rounded once to FP64 for real data.
 #include "common.hpp"
 
 namespace psdp {
@@ -33,7 +34,8 @@ __device__ __forceinline__ double perturb_entry(uint64_t key, int64_t n, int64_t
     return rint((N * sigma) * 65536.0) / 65536.0;
 }
 
-__device__ __forceinline__ double perturbed(const int32_t *Q, int64_t n, int64_t i, int64_t j,
+template <typename QIn>
+__device__ __forceinline__ double perturbed(const QIn *Q, int64_t n, int64_t i, int64_t j,
                                             int perturb, double sigma, uint64_t key) {
     double q = (double)Q[i * n + j];
     if (perturb == PSDP_PERTURB_FULL || (perturb == PSDP_PERTURB_DIAG && i == j)) {
@@ -43,9 +45,11 @@ __device__ __forceinline__ double perturbed(const int32_t *Q, int64_t n, int64_t
     return q;
 }
 
-// One block per operand row i < ld (rows n..ld-1 are zero padding).
-template <typename QT>
-__global__ void __launch_bounds__(kBlock) prep_q_kernel(const int32_t *Q, int64_t n, int64_t ld,
+// One block per operand row i < ld (rows n..ld-1 are zero padding). For
+// real data the perturbed entry is Q_ij + mu_ij rounded once to FP64, and R_i
+// sums in the block's fixed order (integer data sums exactly).
+template <typename QT, typename QIn>
+__global__ void __launch_bounds__(kBlock) prep_q_kernel(const QIn *Q, int64_t n, int64_t ld,
                                                         int perturb, double sigma, uint64_t key,
                                                         QT *Qop, double *R, double *dq) {
     const int64_t i = blockIdx.x;
@@ -141,6 +145,144 @@ __global__ void __launch_bounds__(kBlock) objective_final_kernel(const int32_t *
     }
 }
 
+// ---------------------------------------------------------------------------
+// Real data: the objective as the exact sum of its terms, rounded once.
+//
+// Every finite double is v = (-1)^s M 2^(e - 1075) with an integer
+// mantissa M < 2^53 and e = max(biased exponent, 1), so v 2^1074 is the
+// integer +-M 2^(e - 1). The terms of one column are accumulated exactly in
+// integers bucketed by e: acc[e] collects the signed high parts M >> 26
+// (< 2^27) and acc[2048 + e] the low parts M mod 2^26. With at most
+// 2^32 + 2^16 terms no bucket leaves int64. The final kernel expands the
+// buckets into a big integer N = sum_e (hi_e 2^26 + lo_e) 2^(e - 1) of
+// 32-bit limbs, normalizes it and rounds N 2^-1074 to the nearest double
+// (ties to even). The result is independent of the order of the terms.
+
+__device__ __forceinline__ void obj_term(double v, long long *hi, long long *lo) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int E = (int)((u >> 52) & 0x7ff);
+    uint64_t M = u & 0xfffffffffffffull;
+    if (E != 0) M |= 1ull << 52;
+    if (M == 0) return;
+    const int e = E == 0 ? 1 : E;
+    const long long h = (long long)(M >> 26), l = (long long)(M & 0x3ffffffull);
+    const bool neg = (u >> 63) != 0;
+    atomicAdd((unsigned long long *)&hi[e], (unsigned long long)(neg ? -h : h));
+    atomicAdd((unsigned long long *)&lo[e], (unsigned long long)(neg ? -l : l));
+}
+
+// Block (blk, c): rows blk * kObjRowsReal .. of column c; block 0 adds b.
+constexpr int kObjRowsReal = 64;
+__global__ void __launch_bounds__(kBlock) objective_real_partial_kernel(const double *Q, const double *b, int64_t n,
+                                                                        const uint8_t *xhat, int64_t ldh,
+                                                                        int64_t *acc) {
+    __shared__ long long bk[2 * 2048];
+    const int64_t c = blockIdx.y, blk = blockIdx.x;
+    const uint8_t *xh = xhat + c * ldh;
+    for (int t = threadIdx.x; t < 2 * 2048; t += kBlock) bk[t] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = wv; r < kObjRowsReal; r += kWaves) {
+        const int64_t i = blk * kObjRowsReal + r;
+        if (i >= n || !xh[i]) continue;
+        const double *row = Q + i * n;
+        for (int64_t j = lane; j < n; j += 64)
+            if (xh[j]) obj_term(row[j], bk, bk + 2048);
+    }
+    if (blk == 0)
+        for (int64_t i = threadIdx.x; i < n; i += kBlock)
+            if (xh[i]) obj_term(b[i], bk, bk + 2048);
+    __syncthreads();
+    int64_t *a = acc + c * kObjAccWords;
+    for (int t = threadIdx.x; t < 2 * 2048; t += kBlock)
+        if (bk[t] != 0) atomicAdd((unsigned long long *)&a[t], (unsigned long long)bk[t]);
+}
+
+constexpr int kLimbs = 72;  // 32-bit limbs (in int64 slots) of N: bits up to 2^2304
+
+// adds t 2^sh to the limbs (t signed, |t| < 2^61); every addend is below
+// 2^32 in magnitude, so the limbs absorb all 4096 buckets without overflow
+__device__ __forceinline__ void limb_add(long long *L, long long t, int sh) {
+    const int q = sh >> 5, r = sh & 31;
+    const unsigned long long a0 = (unsigned long long)t & 0xffffffffull;
+    const long long t1 = t >> 32;
+    const unsigned long long A = a0 << r;
+    const long long T1 = (long long)((unsigned long long)t1 << r);
+    atomicAdd((unsigned long long *)&L[q], A & 0xffffffffull);
+    atomicAdd((unsigned long long *)&L[q + 1], (A >> 32) + ((unsigned long long)T1 & 0xffffffffull));
+    atomicAdd((unsigned long long *)&L[q + 2], (unsigned long long)(T1 >> 32));
+}
+
+// limbs normalized to [0, 2^32) below the top, which keeps the sign
+__device__ void limb_carry(long long *L) {
+    for (int k = 0; k + 1 < kLimbs; ++k) {
+        const long long cy = L[k] >> 32;
+        L[k] -= cy << 32;
+        L[k + 1] += cy;
+    }
+}
+
+// 64 bits of N >> pos (pos >= 0) from normalized limbs
+__device__ __forceinline__ unsigned long long limb_window(const long long *L, int pos) {
+    const int q = pos >> 5, r = pos & 31;
+    const unsigned long long lo = (unsigned long long)L[q] | ((unsigned long long)L[q + 1] << 32);
+    const unsigned long long hi = (unsigned long long)L[q + 2];
+    return r ? (lo >> r) | (hi << (64 - r)) : lo;
+}
+
+__global__ void __launch_bounds__(kBlock) objective_real_final_kernel(int64_t *acc, double *obj) {
+    __shared__ long long L[kLimbs];
+    const int64_t c = blockIdx.x;
+    int64_t *a = acc + c * kObjAccWords;
+    for (int t = threadIdx.x; t < kLimbs; t += kBlock) L[t] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2048; e += kBlock) {
+        const long long h = a[e], l = a[2048 + e];
+        if (h) limb_add(L, h, e - 1 + 26);
+        if (l) limb_add(L, l, e - 1);
+        a[e] = 0;  // leave the scratch zero for the next use
+        a[2048 + e] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    limb_carry(L);
+    const bool neg = L[kLimbs - 1] < 0;
+    if (neg) {
+        for (int k = 0; k < kLimbs; ++k) L[k] = -L[k];
+        limb_carry(L);
+    }
+    int top = kLimbs - 1;
+    while (top >= 0 && L[top] == 0) --top;
+    double v = 0.0;
+    if (top >= 0) {
+        const int p = 32 * top + (31 - __clz((unsigned)L[top]));  // highest set bit of N
+        if (p <= 52) {
+            v = ldexp((double)((unsigned long long)L[0] | ((unsigned long long)L[1] << 32)), -1074);
+        } else {
+            // m = bits p-52 .. p; then the round bit and the sticky bits below
+            unsigned long long w;
+            bool sticky;
+            if (p < 63) {
+                w = limb_window(L, 0) << (63 - p);
+                sticky = false;
+            } else {
+                const int pos = p - 63;
+                w = limb_window(L, pos);
+                sticky = false;
+                const int q = pos >> 5, r = pos & 31;
+                for (int k = 0; k < q; ++k) sticky |= L[k] != 0;
+                if (r) sticky |= (L[q] & ((1ll << r) - 1)) != 0;
+            }
+            unsigned long long m = w >> 11;
+            const bool rbit = (w >> 10) & 1;
+            sticky |= (w & 0x3ffull) != 0;
+            if (rbit && (sticky || (m & 1))) ++m;
+            v = ldexp((double)m, p - 52 - 1074);
+        }
+    }
+    obj[c] = neg ? -v : v;
+}
+
 // Host-side mixing of the seed into the stream key (same function on the host).
 static uint64_t splitmix64_host(uint64_t state) {
     uint64_t z = state + 0x9E3779B97F4A7C15ull;
@@ -149,23 +291,66 @@ static uint64_t splitmix64_host(uint64_t state) {
     return z ^ (z >> 31);
 }
 
-hipError_t launch_prep_q(int dtype, const int32_t *Q, int64_t n, int64_t ld, int perturb,
-                         double sigma, uint64_t seed, void *Qop, double *R, double *dq,
-                         hipStream_t st) {
+template <typename QIn>
+static hipError_t prep_typed(int dtype, const QIn *Q, int64_t n, int64_t ld, int perturb, double sigma,
+                             uint64_t seed, void *Qop, double *R, double *dq, hipStream_t st) {
     const uint64_t key = splitmix64_host(seed);
     if (sigma == 0.0) perturb = PSDP_PERTURB_NONE;
     if (dtype == PSDP_F64)
-        hipLaunchKernelGGL(prep_q_kernel<double>, dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
+        hipLaunchKernelGGL((prep_q_kernel<double, QIn>), dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
                            sigma, key, (double *)Qop, R, dq);
     else if (dtype == PSDP_F32)
-        hipLaunchKernelGGL(prep_q_kernel<float>, dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
+        hipLaunchKernelGGL((prep_q_kernel<float, QIn>), dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
                            sigma, key, (float *)Qop, R, dq);
     else if (dtype == PSDP_I8)
-        hipLaunchKernelGGL(prep_q_kernel<int8_t>, dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
+        hipLaunchKernelGGL((prep_q_kernel<int8_t, QIn>), dim3(ld), dim3(kBlock), 0, st, Q, n, ld, perturb,
                            sigma, key, (int8_t *)Qop, R, dq);
     else
-        hipLaunchKernelGGL(prep_q_kernel<__hip_bfloat16>, dim3(ld), dim3(kBlock), 0, st, Q, n, ld,
+        hipLaunchKernelGGL((prep_q_kernel<__hip_bfloat16, QIn>), dim3(ld), dim3(kBlock), 0, st, Q, n, ld,
                            perturb, sigma, key, (__hip_bfloat16 *)Qop, R, dq);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_q(int dtype, const int32_t *Q, int64_t n, int64_t ld, int perturb,
+                         double sigma, uint64_t seed, void *Qop, double *R, double *dq,
+                         hipStream_t st) {
+    return prep_typed<int32_t>(dtype, Q, n, ld, perturb, sigma, seed, Qop, R, dq, st);
+}
+
+hipError_t launch_prep_q(int dtype, const double *Q, int64_t n, int64_t ld, int perturb,
+                         double sigma, uint64_t seed, void *Qop, double *R, double *dq,
+                         hipStream_t st) {
+    return prep_typed<double>(dtype, Q, n, ld, perturb, sigma, seed, Qop, R, dq, st);
+}
+
+// gamma_i = 2 sum_j |Q~_ij| + |b_i| + 1 (Section 3.5, strict margin 1) and b
+// as FP64, zero in the padding up to ld.
+template <typename BT>
+__global__ void gamma_kernel(const BT *b, const double *R, const double *dq, int64_t n, int64_t ld, double *bd,
+                             double *gam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ld) return;
+    if (i < n) {
+        const double bi = (double)b[i];
+        bd[i] = bi;
+        gam[i] = 2.0 * (R[i] + fabs(dq[i])) + fabs(bi) + 1.0;
+    } else {
+        bd[i] = 0.0;
+        gam[i] = 0.0;
+    }
+}
+
+hipError_t launch_gamma(const int32_t *b, const double *R, const double *dq, int64_t n, int64_t ld,
+                        double *bd, double *gam, hipStream_t st) {
+    hipLaunchKernelGGL(gamma_kernel<int32_t>, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, st, b, R, dq, n,
+                       ld, bd, gam);
+    return hipGetLastError();
+}
+
+hipError_t launch_gamma(const double *b, const double *R, const double *dq, int64_t n, int64_t ld,
+                        double *bd, double *gam, hipStream_t st) {
+    hipLaunchKernelGGL(gamma_kernel<double>, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, st, b, R, dq, n,
+                       ld, bd, gam);
     return hipGetLastError();
 }
 
@@ -190,6 +375,20 @@ hipError_t launch_round_objective(const int32_t *Q, const int32_t *b, int64_t n,
                        nblk, partial);
     hipLaunchKernelGGL(objective_final_kernel, dim3(B), dim3(kBlock), 0, st, b, n, xhat, ldh, nblk,
                        partial, obj);
+    return hipGetLastError();
+}
+
+}  // namespace psdp
+
+namespace psdp {
+
+hipError_t launch_round_objective(const double *Q, const double *b, int64_t n, const double *X, int64_t ldx,
+                                  int64_t B, uint8_t *xhat, int64_t ldh, double *obj, int64_t *acc, hipStream_t st) {
+    const int64_t tot = n * B;
+    hipLaunchKernelGGL(round_kernel, dim3((tot + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X, ldx, n, B, xhat, ldh);
+    const int64_t nblk = (n + kObjRowsReal - 1) / kObjRowsReal;
+    hipLaunchKernelGGL(objective_real_partial_kernel, dim3(nblk, B), dim3(kBlock), 0, st, Q, b, n, xhat, ldh, acc);
+    hipLaunchKernelGGL(objective_real_final_kernel, dim3(B), dim3(kBlock), 0, st, acc, obj);
     return hipGetLastError();
 }
 

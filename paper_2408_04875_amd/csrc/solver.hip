@@ -232,6 +232,9 @@ template <int N> __device__ __forceinline__ void bmax(double (&v)[N], double *re
     block_max<N, kSB>(v, red);
 }
 
+template <typename OpT, int EPT>
+__device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red, double lam);
+
 // ---------------------------------------------------------------------------
 // Outer loop head (Algorithm 3): exit tests, then start lambda_min.
 
@@ -286,6 +289,13 @@ __device__ void outer_begin(const Work &w, Col &c, const ColView &cv, double *re
     }
     __syncthreads();
     if (exitr >= 0) return;
+    if (w.lambda_reuse && c.stall > 0) {
+        // the last subproblem left x as it was: I and z are unchanged and the
+        // penalty update shifted the scaled matrix of eq. (alpha) by -alpha, so
+        // its smallest eigenvalue moved by exactly -alpha; no LOBPCG is needed
+        eig_finish<OpT, EPT>(w, c, cv, red, c.lam - c.alpha);
+        return;
+    }
     // first LOBPCG vector: constant on I, normalized in the Z inner product
     // z = x - x^2 for lambda_min (positive exactly on I: for 0 < x < 1 it
     // rounds to a positive double)
@@ -318,7 +328,8 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
     const UVec<double> p = uvec(w.p, cv.off), dgo = uvec(w.diag, cv.off), lno = uvec(w.lin, cv.off);
     const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
     const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
-    const double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
+    double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
+    if (w.alpha_in && c.s < w.alpha_cap) alpha = w.alpha_in[(int64_t)uni(c.id) * w.alpha_cap + uni(c.s)];
     double mx[2] = {0.0, 0.0};
     CHUNKS(n) {
         CHUNK_INDEX(n)
@@ -396,7 +407,10 @@ __device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red
     const UVec<const double> dg = uvec((const double *)w.diag, cv.off), ln = uvec((const double *)w.lin, cv.off);
     const int k = c.k;
     double mx[2] = {0.0, 0.0};       // cret, any nonzero step component
-    double sm[3] = {0.0, 0.0, 0.0};  // s's, s'y, y'y
+    // s's, s'y, y'y of eq. (bb1) as double-double sums (high parts sm, low
+    // parts sl): the BB steps take their exact values rounded once
+    double sm[3] = {0.0, 0.0, 0.0};
+    double sl[3] = {0.0, 0.0, 0.0};
     double xr[EPT], gr[EPT];         // register copies when one pass covers the column
     CHUNKS(n) {
         CHUNK_INDEX(n)
@@ -428,14 +442,14 @@ __device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red
             if (k > 0) {
                 const double s = xi - xpv[_j];
                 const double y = gi - gpv[_j];
-                sm[0] += s * s;
-                sm[1] += s * y;
-                sm[2] += y * y;
+                dd_add_prod(sm[0], sl[0], s, s);
+                dd_add_prod(sm[1], sl[1], s, y);
+                dd_add_prod(sm[2], sl[2], y, y);
                 if (s != 0.0) mx[1] = 1.0;
             }
         }
     }
-    block_maxsum<2, 3, kSB>(mx, sm, red);  // sm is zero when k == 0
+    block_maxsum_dd<2, 3, kSB>(mx, sm, sl, red);  // sm is zero when k == 0
     const double rel = mx[0] / c.rho;
     if (threadIdx.x == 0) {
         c.evals += 1;
@@ -725,7 +739,11 @@ __device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red)
         c.hasP = 0;
     }
     __syncthreads();
-    if (sqrt(rn[0] / sm[1]) <= w.eig_tol * fabs(lam) || w.eig_maxit <= 1) {
+    // a Ritz value is an upper bound of lambda_min: below the floor of
+    // eq. (alpha1)'s maximum it already fixes alpha (the floor), whatever
+    // lambda_min is
+    const double floor_lam = w.lambda_floor_rel * c.rho_outer;
+    if (sqrt(rn[0] / sm[1]) <= w.eig_tol * fabs(lam) || lam < floor_lam || w.eig_maxit <= 1) {
         eig_finish<OpT, EPT>(w, c, cv, red, lam);
         return;
     }
@@ -911,7 +929,10 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
         c.hasP = 1;
     }
     __syncthreads();
-    if (sqrt(rn[0] / rn[1]) <= w.eig_tol * fabs(theta) || it >= w.eig_maxit) {
+    // below the floor of alpha's maximum the Ritz value (an upper bound of
+    // lambda_min) already fixes alpha: stop (see eig0_step)
+    if (sqrt(rn[0] / rn[1]) <= w.eig_tol * fabs(theta) || theta < w.lambda_floor_rel * c.rho_outer ||
+        it >= w.eig_maxit) {
         eig_finish<OpT, EPT>(w, c, cv, red, theta);
     } else {
         aux_digits<OpT, EPT>(w, c, cv, mw[0], wnr, one);

@@ -18,14 +18,3 @@ def bruteforce_optima():
             assert len(x) == int(n)
             out[int(seed)] = (int(n), int(opt), x)
     return out
-
-
-def oracle_n1000_single():
-    """(objective, outer iterations, inner iterations, exit reason) from
-    oracle_n1000_single.txt."""
-    with open(os.path.join(GOLDEN, "oracle_n1000_single.txt")) as f:
-        for line in f:
-            if line.startswith("#") or not line.strip():
-                continue
-            return tuple(int(v) for v in line.split())
-    raise ValueError("empty fixture")

@@ -423,7 +423,7 @@ def test_solve_resume_is_bit_identical():
 def test_no_progress_exit_matches_shift_law():
     # after a non-moving subproblem, I and z are unchanged and lambda shrinks by (1 - eta)
     Q, b = gen.small_dense(0)
-    prm = O.Params(eta=0.9, stall_outer=3)
+    prm = O.Params(eta=0.9, stall_outer=3, lambda_reuse="solve")
     r = O.solve(Q, b, prm)
     assert r.exit_reason == O.STALL
     tail = r.trace[-3:]
