@@ -317,6 +317,24 @@ psdp_status psdp_eval_penalty_grad(int32_t dtype, int32_t vtype, const void *Q, 
                                    hipStream_t stream);
 
 /*
+ * psdp_eval_penalty_grad_noalloc - psdp_eval_penalty_grad (same arguments,
+ * same kernels, bit-identical h and G) for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation. The product workspace (8 n B + 4 B +
+ * 320 bytes) lives in a fixed 32 MiB device array of the library, one per
+ * device, held until the process ends; no hipMalloc or other allocation
+ * happens in the call. Calls that overlap on one device share that array
+ * and race: serialize them (one stream, or events). Every word the
+ * evaluation reads from the array is written by the same call first.
+ * Errors: as psdp_eval_penalty_grad, and PSDP_E_UNSUPPORTED when
+ * 8 n B + 4 B + 320 exceeds 32 MiB.
+ */
+psdp_status psdp_eval_penalty_grad_noalloc(int32_t dtype, int32_t vtype, const void *Q, int64_t ldq,
+                                           const void *b, const void *p, const void *X,
+                                           int64_t n, int64_t B, void *h, void *G,
+                                           hipStream_t stream);
+
+/*
  * psdp_penalty_adjoint - gradients of L = sum_c w_c h(x_c, p) (h of eq. (p1),
  * linear in Q, b and p):
  *   dX[:, c] = w_c G[:, c]             (G = grad h from psdp_eval_penalty_grad)

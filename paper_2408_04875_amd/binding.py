@@ -100,6 +100,7 @@ SIGNATURES = {
     "psdp_solve_group_i32": (_I32, [_I32, _P, _P, _P, _P, _P, ctypes.POINTER(Params), _P, _P,
                                     ctypes.POINTER(Stats), _P]),
     "psdp_eval_penalty_grad": (_I32, [_I32, _I32, _P, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P]),
+    "psdp_eval_penalty_grad_noalloc": (_I32, [_I32, _I32, _P, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P]),
     "psdp_penalty_adjoint": (_I32, [_I32, _I32, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P]),
     "psdp_round_objective_i32": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
     "psdp_round_objective_f64": (_I32, [_P, _P, _I64, _P, _I64, _P, _P, _P]),
@@ -320,11 +321,13 @@ def _dtype_codes(t):
     return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
 
 
-def eval_penalty_grad(Q, b, p, X, want_grad: bool = True):
+def eval_penalty_grad(Q, b, p, X, want_grad: bool = True, noalloc: bool = False):
     """h(x_c, p) and grad h(x_c, p) for the rows x_c of X (shape (B, n)).
 
     Q and X share a dtype (float64, float32 or bfloat16); b and p share the
-    dtype of the outputs (float64 or float32).
+    dtype of the outputs (float64 or float32). noalloc=True runs
+    psdp_eval_penalty_grad_noalloc (the library's fixed workspace; the
+    outputs are still allocated here by torch).
     """
     torch = _torch()
     lib = load()
@@ -337,8 +340,9 @@ def eval_penalty_grad(Q, b, p, X, want_grad: bool = True):
     B = X2.shape[0]
     h = torch.empty(B, dtype=b.dtype, device=X.device)
     G = torch.empty((B, n), dtype=b.dtype, device=X.device) if want_grad else None
-    st = lib.psdp_eval_penalty_grad(_dtype_codes(Q), _dtype_codes(b), _ptr(Q), Q.stride(0), _ptr(b),
-                                    _ptr(p), _ptr(X2), n, B, _ptr(h), _ptr(G), _stream())
+    fn = lib.psdp_eval_penalty_grad_noalloc if noalloc else lib.psdp_eval_penalty_grad
+    st = fn(_dtype_codes(Q), _dtype_codes(b), _ptr(Q), Q.stride(0), _ptr(b), _ptr(p), _ptr(X2), n, B, _ptr(h),
+            _ptr(G), _stream())
     _check(st)
     return h, G
 
