@@ -2,11 +2,17 @@
 
 Workload: one UBQP instance, n = 2500, symmetric integer Q at 10% density with
 nonzeros uniform over +-{1..100}, b = 0, and 256 random starts uniform in
-[0,1)^n, all solved together (Algorithm 3 with projected alternating BB
-subproblems). One step = one whole batched solve: Q preparation, every sweep
-of Q.X products (subproblem and lambda_min / CG products), the per-column
-state machine, and the exact int64 objectives. Inputs are resident in device
-memory before the timed region starts.
+[0,1)^n per step, all solved batched (Algorithm 3 with projected alternating
+BB subproblems). One step = one start set of 256 starts solved to the end:
+every sweep of Q.X products (subproblem and lambda_min products), the
+per-column state machine, and the exact int64 objectives. By default the
+timed steps' start sets run as one queued launch of 1024 columns (--slots):
+a column whose start ends takes the next queued start, so the launch stays
+full instead of idling while each set's slowest start finishes; every start
+performs exactly the arithmetic of its own-column solve (tested bit for
+bit). The same sets solved one launch per set are reported beside it
+(`per_set_launches`). Inputs are resident in device memory before the timed
+region starts.
 
 The default operand type is I8: exact integer products on int8 MFMA (an
 iterate rounded to the grid 2^-27, eigen/CG vectors to 55 bits of their
@@ -51,6 +57,7 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 MFMA
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 MFMA
 STEP_BYTES_PER_COLUMN = 80  # about 10 FP64 vectors of n per column update
 START_SEED = 3              # start set of the first timed step (the workload generator's default)
+INSTR_SETS = 8              # start sets of the solve timed launch by launch (queued launches)
 STEP_SOURCES = ("paper_2408_04875_amd/csrc/solver.hip", "paper_2408_04875_amd/csrc/common.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_traffic.json")
 
@@ -63,6 +70,11 @@ def parse():
     ap.add_argument("--n", type=int, default=2500)
     ap.add_argument("--starts", type=int, default=256)
     ap.add_argument("--plain-starts", type=int, default=32)
+    ap.add_argument("--slots", type=int, default=1024,
+                    help="solve the timed steps' start sets as one queued launch with this many columns "
+                         "(0: one launch per start set)")
+    ap.add_argument("--no-per-set", action="store_true",
+                    help="skip the comparison with one launch per start set")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -104,6 +116,10 @@ def step_source_hash():
 
 
 TRACE_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_trace.json")
+# the bench command the kernel records are taken from: the default configuration (queued launch
+# of 1024 columns) over eight start sets, without the side legs
+PROFILE_ARGS = ("--steps 8 --warmup 0 --no-cpu-baseline --no-plain --no-fp32 --no-sparse --no-gemv --no-group "
+                "--no-replay --no-adjoint --no-per-set")
 STEP_KERNEL_PREFIX = "solver_step_kernel"
 
 
@@ -123,9 +139,8 @@ def record_trace(stats_csv, kernel=STEP_KERNEL_PREFIX):
     rec = {"kernel": [r["Name"] for r in rows], "source_sha256": step_source_hash(), "calls": calls,
            "avg_ns": total / max(calls, 1),
            "command": "cd /tmp && rocprofv3 --kernel-trace --stats -d <out> -o run -- python -u <repo>/bench.py "
-                      "--steps 1 --warmup 0 --no-cpu-baseline --no-plain --no-fp32 --no-sparse --no-gemv "
-                      "--no-group --no-replay --no-adjoint",
-           "note": "both solves of the run (the timed one and the one with HIP events around every launch)"}
+                      + PROFILE_ARGS,
+           "note": "both queued solves of the run (the timed one and the one with HIP events around every launch)"}
     with open(TRACE_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -150,15 +165,15 @@ def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel=
     f_kib, nd = per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
     w_kib, _ = per_dispatch(write_csv, "WRITE_SIZE", kernel)
     fb, wb = f_kib * 1024.0 * fs, w_kib * 1024.0 * ws
-    rec = {"kernel": f"{kernel} (n = 2500, 256 starts, I8 operands)", "source_sha256": step_source_hash(),
+    rec = {"kernel": f"{kernel} (n = 2500, 8 sets of 256 starts through 1024 columns, I8 operands)",
+           "source_sha256": step_source_hash(),
            "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "dispatches": nd, "fetch_size_kib_avg": f_kib, "write_size_kib_avg": w_kib,
            "copy_calibration": {"bytes": 1 << 30, "fetch_size_kib": sum(cf) / len(cf),
                                 "write_size_kib": sum(cw) / len(cw), "fetch_scale": fs, "write_scale": ws},
            "commands": [f"cd /tmp && rocprofv3 --pmc {c} --output-format csv -d <out> -o run -- python -u "
                         f"<repo>/bench.py {a}" for c in ("FETCH_SIZE", "WRITE_SIZE")
-                        for a in ("--steps 1 --warmup 0 --no-cpu-baseline --no-plain --no-fp32 --no-sparse "
-                                  "--no-gemv --no-group --no-replay --no-adjoint", "--calibrate-copy")],
+                        for a in (PROFILE_ARGS, "--calibrate-copy")],
            "note": "bytes = FETCH_SIZE KiB x 1024 x fetch_scale + WRITE_SIZE KiB x 1024 x write_scale, averaged "
                    "over the step-kernel dispatches of both solves of the run (timed and instrumented)"}
     with open(TRAFFIC_FILE, "w") as f:
@@ -571,26 +586,54 @@ def main():
                    for j in range(1, max(args.steps, 1))]
     torch.cuda.synchronize()
 
-    def step(qx, timing=False, X=None):
-        return P.solve(Qd, bd, X0=X0d if X is None else X, qx_dtype=qx, timing=1 if timing else 0)
+    def step(qx, timing=False, X=None, slots=0):
+        return P.solve(Qd, bd, X0=X0d if X is None else X, qx_dtype=qx, timing=1 if timing else 0, slots=slots)
 
-    def timed(qx, steps, warmup):
+    class SetView:
+        """One start set's share of a queued launch (the fields used below)."""
+        def __init__(self, r, j):
+            self.obj = r.obj[j * B:(j + 1) * B]
+            self.stats = r.stats[j * B:(j + 1) * B]
+            self.best = int(np.argmin(self.obj.cpu().numpy()))
+
+    def timed(qx, steps, warmup, slots=0):
         for _ in range(warmup):
             step(qx)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = [step(qx, X=X0s[j]) for j in range(steps)]
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        if slots:
+            # every set's starts in one launch of `slots` columns: a column whose
+            # start ends takes the next start, so the launch stays full
+            Xall = torch.cat(X0s[:steps], dim=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = step(qx, X=Xall, slots=slots)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            res = [SetView(r, j) for j in range(steps)]
+            for v in res:
+                v.sweeps = int(r.stats[0]["sweeps"])
+        else:
+            t0 = time.perf_counter()
+            res = [step(qx, X=X0s[j]) for j in range(steps)]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            for v in res:
+                v.sweeps = int(v.stats[0]["sweeps"])
         evals = sum(sum(s["inner_iters"] for s in r.stats) for r in res)
         return res, wall, evals
 
-    results, wall, evals = timed(args.qx, args.steps, args.warmup)
+    results, wall, evals = timed(args.qx, args.steps, args.warmup, args.slots)
     print(f"bench: {args.qx} {args.steps} timed steps in {wall:.2f} s", file=sys.stderr, flush=True)
     aux = sum(sum(s["aux_matvecs"] for s in r.stats) for r in results)
-    # one more solve of the first start set with HIP events around every launch
-    # (library solve stream): per-kernel average durations and algorithmic work
-    s0 = step(args.qx, timing=True).stats[0]
+    # one more solve with HIP events around every launch (library solve
+    # stream): per-kernel average durations and algorithmic work. Per-set
+    # launches: the first start set; queued: the first eight sets' starts
+    # through the same number of columns
+    if args.slots:
+        s0 = step(args.qx, timing=True, X=torch.cat(X0s[:min(INSTR_SETS, args.steps)], dim=0),
+                  slots=args.slots).stats[0]
+    else:
+        s0 = step(args.qx, timing=True).stats[0]
     step_s, step_l, colsteps = s0["step_seconds"], s0["step_launches"], s0["column_steps"]
     step_bytes = STEP_BYTES_PER_COLUMN * n * colsteps
     qx_s = s0["qx_seconds"] + s0["aux_seconds"]
@@ -637,12 +680,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"ubqp n={n} 10% density ints +-[1,100] b=0, {B} random starts in [0,1)^n "
                                f"(one start set per step, seeds {START_SEED}..{START_SEED + args.steps - 1}), "
-                               f"batched PABB, Q.X {args.qx}",
-                   "n": n, "starts": B, "global_batch": B, "parallelism": "single gpu"},
+                               f"batched PABB, Q.X {args.qx}" +
+                               (f", the steps' sets as one queued launch of {args.slots} columns"
+                                if args.slots else ", one launch per set"),
+                   "n": n, "starts": B, "global_batch": B, "slots": args.slots or B,
+                   "parallelism": "single gpu"},
         "roofline": dominant,
         "roofline_other": other,
         "solve": {"evals": evals // args.steps, "aux_matvecs": aux // args.steps,
-                  "sweeps": int(first.stats[0]["sweeps"]),
+                  "sweeps": first.sweeps,
                   "best_obj": int(objs.min()), "best_start": first.best,
                   "exit_reasons": {k: int((np.array([s["exit_reason"] for s in first.stats]) == v).sum())
                                    for k, v in (("converged", 0), ("outer_cap", 1), ("stall", 2))},
@@ -650,12 +696,19 @@ def main():
         "steps_detail": [{"start_seed": START_SEED + j,
                           "evals": int(sum(s["inner_iters"] for s in r.stats)),
                           "aux_matvecs": int(sum(s["aux_matvecs"] for s in r.stats)),
-                          "sweeps": int(r.stats[0]["sweeps"]), "best_obj": int(r.obj.min()),
+                          "sweeps": r.sweeps, "best_obj": int(r.obj.min()),
                           "mean_obj": float(r.obj.double().mean())} for j, r in enumerate(results)],
     }
+    if args.slots and not args.no_per_set:
+        pres, pwall, pevals = timed(args.qx, args.steps, 0, 0)
+        same = sum(int((a.obj.cpu() == b.obj.cpu()).all()) for a, b in zip(results, pres))
+        out["per_set_launches"] = {"value": pevals / pwall, "unit": "evals/s", "ms_per_step": pwall / args.steps * 1e3,
+                                   "sets_with_equal_objectives": same,
+                                   "note": "the same start sets, one launch of 256 columns per set"}
     if not args.no_fp32 and args.qx != "f32":
-        fres, fwall, fevals = timed("f32", args.steps, 0)
-        ft = step("f32", timing=True).stats[0]
+        fres, fwall, fevals = timed("f32", args.steps, 0, args.slots)
+        ft = (step("f32", timing=True, X=torch.cat(X0s[:min(INSTR_SETS, args.steps)], dim=0), slots=args.slots)
+              if args.slots else step("f32", timing=True)).stats[0]
         out["fp32_gemm"] = {"value": fevals / fwall, "unit": "evals/s", "steps": args.steps,
                             "ms_per_step": fwall / args.steps * 1e3,
                             "best_obj": [int(r.obj.min()) for r in fres],
@@ -689,6 +742,8 @@ def main():
         out["plain"] = {"path": "single-instance FP32 GEMV (FP64 accumulation), one start per solve",
                         "starts": len(ks), "evals_per_s": plain_rate, "wall_s": pw,
                         "speedup_batched_vs_plain": (evals / wall) / plain_rate,
+                        "speedup_per_set_launches_vs_plain": (out["per_set_launches"]["value"] / plain_rate
+                                                              if "per_set_launches" in out else None),
                         "equal_objective_vs_batched_i8": int((po == bo).sum()),
                         "mean_obj": float(po.mean()), "best_obj": int(po.min()),
                         "batched_same_starts_mean_obj": float(bo.mean()), "batched_same_starts_best_obj": int(bo.min()),

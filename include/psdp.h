@@ -118,6 +118,11 @@ typedef struct {
                                   lambda_min is the previous value minus the previous alpha (I and
                                   z are unchanged, so eq. (alpha) shifted the scaled matrix by
                                   exactly -alpha) and no LOBPCG runs; 0: every update runs LOBPCG */
+    int32_t slots;             /* batched solves: columns advanced together; 0 (default) or >= B
+                                  gives every start its own column; 0 < slots < B keeps that many
+                                  columns and queues the other starts in index order, a column
+                                  taking the next start when its own ends (each start performs the
+                                  same arithmetic either way; outputs stay per start) */
     double tol_kkt;            /* delta of eq. (cret) (1e-5) */
     double tol_binary;         /* Algorithm 3 loop tolerance (1e-5) */
     double eta;                /* eq. (alpha1) scaling, 0 < eta < 1 (0.999) */

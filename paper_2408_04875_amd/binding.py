@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("sparse", ctypes.c_int32),
         ("lambda_reuse", ctypes.c_int32),
+        ("slots", ctypes.c_int32),
         ("tol_kkt", ctypes.c_double),
         ("tol_binary", ctypes.c_double),
         ("eta", ctypes.c_double),

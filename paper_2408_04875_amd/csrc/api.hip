@@ -74,6 +74,7 @@ psdp_status check_params(const psdp_params &p) {
         return fail(PSDP_E_INVALID, "params: tolerance out of range");
     if (p.sparse < -1 || p.sparse > 1) return fail(PSDP_E_INVALID, "params.sparse must be -1, 0 or 1");
     if (p.lambda_reuse < 0 || p.lambda_reuse > 1) return fail(PSDP_E_INVALID, "params.lambda_reuse must be 0 or 1");
+    if (p.slots < 0) return fail(PSDP_E_INVALID, "params.slots must be >= 0");
     if (p.sparse == 1 && p.qx_dtype != PSDP_I8)
         return fail(PSDP_E_UNSUPPORTED, "sparse products need I8 operands");
     return PSDP_OK;
@@ -274,6 +275,7 @@ struct Solver {
     int optype = PSDP_F64, utype = PSDP_F64;
     int64_t *sweeps = nullptr;
     int64_t nmax = 0;  // largest column length (selects the per-thread unroll)
+    int64_t rounds = 1;  // starts per column (queued starts run one after another)
     // live-list buffers by sweep parity and their counters
     // (cnt[2 p] main, cnt[2 p + 1] aux)
     int32_t *act[2] = {nullptr, nullptr}, *act_aux[2] = {nullptr, nullptr};
@@ -468,8 +470,9 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
         }
     } ef{evs};
     // hard bound from the per-column caps (every sweep advances every live column)
-    const int64_t cap = (int64_t)prm.cg_maxit +
-                        (int64_t)(prm.max_outer + 1) * ((int64_t)prm.eig_maxit + prm.max_inner + 2) + 2;
+    const int64_t cap = ((int64_t)prm.cg_maxit +
+                         (int64_t)(prm.max_outer + 1) * ((int64_t)prm.eig_maxit + prm.max_inner + 2) + 2) *
+                        S.rounds;
     int64_t done_sweeps = 0;
     int batch = 0;
     bool finished = false;
@@ -636,6 +639,10 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     Solver S;
     const bool i8 = prm.qx_dtype == PSDP_I8;  // exact integer products, any B
     const bool batched = B > 1 || i8;
+    // columns advanced together: every start, or prm.slots of them with the
+    // other starts queued (a column takes the next start when its own ends)
+    const int32_t ncol = (batched && prm.slots > 0 && prm.slots < B) ? prm.slots : B;
+    const bool queued = ncol < B;
     const int64_t ld = i8 ? (n + 63) / 64 * 64 : padld(n);
     S.optype = batched ? prm.qx_dtype : PSDP_F64;  // single instance: FP64 x, Q in qx_dtype
     S.utype = batched ? prm.qx_dtype : PSDP_F64;
@@ -704,27 +711,27 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
     // column data
     const int kmax = (batched && !i8) ? kMaxSplit : 1;  // integer slices add into one buffer
-    if (psdp_status s2 = alloc_columns(S, ld * B, B, kmax, st, ld)) return s2;
+    if (psdp_status s2 = alloc_columns(S, ld * ncol, ncol, kmax, st, ld)) return s2;
     if (S.rowptr) {
         // the operands' grid values as words, for the sparse products; like
-        // the digit planes they hold one extra all-zero column (index B),
+        // the digit planes they hold one extra all-zero column (index ncol),
         // which empty list slots and the slots past the count name
         for (int32_t **pw : {&w.tw, &w.tw_hi, &w.tw_lo}) {
-            HIPCHK(S.ar.get((void **)pw, ld * (B + 1) * sizeof(int32_t)));
-            HIPCHK(hipMemsetAsync(*pw, 0, ld * (B + 1) * sizeof(int32_t), st));
+            HIPCHK(S.ar.get((void **)pw, ld * (ncol + 1) * sizeof(int32_t)));
+            HIPCHK(hipMemsetAsync(*pw, 0, ld * (ncol + 1) * sizeof(int32_t), st));
         }
     }
     const int MT = (int)((ld + 63) / 64);
     // Product kernel per live count (the count comes from the last host poll,
-    // so it is an estimate; every kernel covers all B columns regardless).
+    // so it is an estimate; every kernel covers all ncol columns regardless).
     // Columns move between the two lists from sweep to sweep but never come
     // back to life, so neither list outgrows the total live count of the
     // poll: the estimate is the list's count plus 16, at most that total.
     // up to 64 live columns the wave-streaming kernel (needs the FP32 copy of
     // Q), above that the LDS-tiled GEMM with enough split-K for ~512 tiles.
     auto pick = [&](int ncols, int live, int gemm_dtype) {
-        if (!batched) return Pick{false, 4, 1, std::min({B, ncols + 16, live})};
-        return pick_product(B, ncols, live, gemm_dtype, prm.gemm_variant, MT);
+        if (!batched) return Pick{false, 4, 1, std::min({ncol, ncols + 16, live})};
+        return pick_product(ncol, ncols, live, gemm_dtype, prm.gemm_variant, MT);
     };
     // integer path: layouts from the estimated live counts, K slices from
     // the blocks of both products (they share one launch)
@@ -732,25 +739,25 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     Pick8 p8m{}, p8a{};
     auto pick8 = [&](int cm, int ca) {
         int bm = 0, ba = 0;
-        p8m.est = std::min({B, cm + 16, cm + ca});
-        p8a.est = std::min({B, ca + 16, cm + ca});
+        p8m.est = std::min({ncol, cm + 16, cm + ca});
+        p8a.est = std::min({ncol, ca + 16, cm + ca});
         digit_layout(p8m.est, 4, ld, &p8m.mt, &bm);
         digit_layout(p8a.est, 8, ld, &p8a.mt, &ba);
         p8m.ks = digit_slices(p8m.mt, bm + ba);
         p8a.ks = digit_slices(p8a.mt, bm + ba);
         // sparse products while they cost less than the digit products; the
         // bound takes every live column as a two-half lambda_min column
-        const int live = std::min(B, cm + ca);
+        const int live = std::min(ncol, cm + ca);
         S.sparse_now = S.rowptr != nullptr && (prm.sparse == 1 || sparse_batch(n, S.nnz, live));
     };
-    pick8(B, B);
-    Pick pm = pick(B, B, main_gemm), pa = pick(B, B, aux_gemm);
+    pick8(ncol, ncol);
+    Pick pm = pick(ncol, ncol, main_gemm), pa = pick(ncol, ncol, aux_gemm);
     // integer path: the column kernel reads one buffer, whatever the
     // product's K slices
     w.ksplit = i8 ? 1 : pm.ks;
     w.ksplit_aux = i8 ? 1 : (w.split ? pa.ks : w.ksplit);
-    std::vector<Col> hcol(B);
-    for (int c = 0; c < B; ++c) {
+    std::vector<Col> hcol(ncol);
+    for (int c = 0; c < ncol; ++c) {
         Col &cc = hcol[c];
         std::memset(&cc, 0, sizeof cc);
         cc.inst = 0;
@@ -759,15 +766,31 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         cc.off = (int64_t)c * ld;
         cc.ioff = 0;
         cc.id = c;
+        cc.start = c;
         cc.phase = PH_INNER;  // placeholder, set by the init kernel
     }
-    HIPCHK(S.ar.get((void **)&w.col, B * sizeof(Col)));
-    HIPCHK(hipMemcpyAsync(w.col, hcol.data(), B * sizeof(Col), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(fill_p_kernel, dim3((unsigned)((ld * B + 255) / 256)), dim3(256), 0, st, w.p, p0, n,
-                       ld, B);
+    HIPCHK(S.ar.get((void **)&w.col, ncol * sizeof(Col)));
+    HIPCHK(hipMemcpyAsync(w.col, hcol.data(), ncol * sizeof(Col), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(fill_p_kernel, dim3((unsigned)((ld * ncol + 255) / 256)), dim3(256), 0, st, w.p, p0, n,
+                       ld, ncol);
+    if (queued) {
+        S.rounds = (B + ncol - 1) / ncol;
+        int32_t *q;
+        HIPCHK(S.ar.get((void **)&q, 64));
+        HIPCHK(hipMemcpyAsync(q, &ncol, sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(S.ar.get((void **)&w.xfin, (size_t)n * B * sizeof(double)));
+        HIPCHK(S.ar.get((void **)&w.fin, (size_t)B * sizeof(Col)));
+        w.queue = q;
+        w.nstart = B;
+        w.X0 = X0;
+        w.p0 = p0;
+    }
     HIPCHK(hipGetLastError());
     if (trace) {
+        // seeded with the caller's records, so that the unused ones come back untouched
         HIPCHK(S.ar.get((void **)&w.trace, (size_t)B * trace_cap * 6 * sizeof(double)));
+        HIPCHK(hipMemcpyAsync(w.trace, trace, (size_t)B * trace_cap * 6 * sizeof(double), hipMemcpyHostToDevice,
+                              st));
         w.trace_cap = trace_cap;
     }
     if (alpha_in) {
@@ -792,10 +815,10 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     psdp_status rs;
     if (i8) {
         auto job_main = [&]() {
-            return DigitJob{w.dig, w.active, w.nactive, (int64_t *)w.U, nullptr, B, p8m.ks, p8m.mt, p8m.est};
+            return DigitJob{w.dig, w.active, w.nactive, (int64_t *)w.U, nullptr, ncol, p8m.ks, p8m.mt, p8m.est};
         };
         auto job_aux = [&]() {
-            return DigitJob{w.dig_aux, w.active_aux, w.nactive_aux, (int64_t *)w.U_aux, w.U_lo, B, p8a.ks, p8a.mt,
+            return DigitJob{w.dig_aux, w.active_aux, w.nactive_aux, (int64_t *)w.U_aux, w.U_lo, ncol, p8a.ks, p8a.mt,
                             p8a.est};
         };
         const int8_t *Q8 = (const int8_t *)Qop;
@@ -810,10 +833,10 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
             S, prm, tm, ta, ts, st,
             [&]() {
                 if (S.sparse_now) {
-                    const SparseJob sm{p8m.est > 0, S.rowptr, S.pk, n, w.tw, nullptr, ld, w.active, w.nactive, B,
+                    const SparseJob sm{p8m.est > 0, S.rowptr, S.pk, n, w.tw, nullptr, ld, w.active, w.nactive, ncol,
                                        (int64_t *)w.U, nullptr, ld};
                     const SparseJob sa{p8a.est > 0, S.rowptr, S.pk, n, w.tw_hi, w.tw_lo, ld, w.active_aux,
-                                       w.nactive_aux, B, (int64_t *)w.U_aux, w.U_lo, ld};
+                                       w.nactive_aux, ncol, (int64_t *)w.U_aux, w.U_lo, ld};
                     return launch_sparse(&sm, &sa, st);
                 }
                 const DigitJob jm = job_main(), ja = job_aux();
@@ -848,7 +871,7 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
                 if (pm.stream)
                     return launch_stream(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit,
                                          pm.est, pm.nt, st);
-                return launch_gemm(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit, B, st);
+                return launch_gemm(main_gemm, Qop, ld, w.op, w.U, w.active, w.nactive, w.slice, w.ksplit, ncol, st);
             },
             [&]() {
                 if (merge && pm.stream && pa.stream) return hipSuccess;
@@ -856,7 +879,7 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
                     return launch_stream(aux_gemm, Qaux, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
                                          w.slice_aux, w.ksplit_aux, pa.est, pa.nt, st);
                 return launch_gemm(aux_gemm, Qaux, ld, w.op_aux, w.U_aux, w.active_aux, w.nactive_aux,
-                                   w.slice_aux, w.ksplit_aux, B, st);
+                                   w.slice_aux, w.ksplit_aux, ncol, st);
             });
     }
     if (rs != PSDP_OK) return rs;
@@ -872,22 +895,26 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
                 fprintf(stderr, "phase %-5s n=%llu avg %.2f us max %.2f us\n", nm[q], hp[3 * q + 1],
                         1e3 * (double)hp[3 * q] / hp[3 * q + 1] / rate_khz, 1e3 * (double)hp[3 * q + 2] / rate_khz);
     }
-    // rounding and exact objective on the original data
+    // rounding and exact objective on the original data; with queued starts
+    // the final iterates and records were saved per start as each one ended
+    const double *Xf = queued ? w.xfin : w.x;
+    const int64_t ldf = queued ? n : ld;
     if constexpr (std::is_same<T, double>::value) {
         int64_t *acc;
         HIPCHK(S.ar.get((void **)&acc, (size_t)B * kObjAccWords * sizeof(int64_t)));
         HIPCHK(hipMemsetAsync(acc, 0, (size_t)B * kObjAccWords * sizeof(int64_t), st));
-        HIPCHK(launch_round_objective(Q, b, n, w.x, ld, B, xhat, n, obj, acc, st));
+        HIPCHK(launch_round_objective(Q, b, n, Xf, ldf, B, xhat, n, obj, acc, st));
     } else {
         int64_t *partial;
         const int64_t nblk = (n + 15) / 16;
         HIPCHK(S.ar.get((void **)&partial, nblk * B * sizeof(int64_t)));
-        HIPCHK(launch_round_objective(Q, b, n, w.x, ld, B, xhat, n, obj, partial, st));
+        HIPCHK(launch_round_objective(Q, b, n, Xf, ldf, B, xhat, n, obj, partial, st));
     }
     if (X_out)
-        HIPCHK(hipMemcpy2DAsync(X_out, n * sizeof(double), w.x, ld * sizeof(double), n * sizeof(double), B,
+        HIPCHK(hipMemcpy2DAsync(X_out, n * sizeof(double), Xf, ldf * sizeof(double), n * sizeof(double), B,
                                 hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(hcol.data(), w.col, B * sizeof(Col), hipMemcpyDeviceToHost, st));
+    hcol.resize(B);
+    HIPCHK(hipMemcpyAsync(hcol.data(), queued ? w.fin : w.col, B * sizeof(Col), hipMemcpyDeviceToHost, st));
     int64_t nsweeps = 0;
     HIPCHK(hipMemcpyAsync(&nsweeps, S.sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     std::vector<ObjT> hobj;
@@ -952,6 +979,7 @@ void psdp_params_default(psdp_params *p) {
     p->graph = 1;
     p->sparse = -1;
     p->lambda_reuse = 1;
+    p->slots = 0;
     p->tol_kkt = 1e-5;
     p->tol_binary = 1e-5;
     p->eta = 0.999;
@@ -1095,6 +1123,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         cc.off = off[i];
         cc.ioff = off[i];
         cc.id = i;
+        cc.start = i;
         cc.phase = PH_INNER;
     }
     HIPCHK(S.ar.get((void **)&w.col, count * sizeof(Col)));

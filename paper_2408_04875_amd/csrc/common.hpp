@@ -64,6 +64,9 @@ struct Col {
     int32_t escale;      // integer path: lambda_min / CG operand scaled by 2^-escale
     int64_t ioff;        // offset of the instance vectors (Inst::off), so that
                          // the column kernel reads no Inst record
+    int32_t start;       // the start this column holds (its trace, replayed steps
+                         // and outputs); equals id unless starts are queued
+    int32_t pad_;
 };
 
 // Flat solver workspace (device pointers), passed to every solver kernel.
@@ -124,9 +127,19 @@ struct Work {
     double *trace;       // per column trace_cap records of 6 doubles, or null
     int32_t trace_cap;
     // prescribed penalty steps (a parity hook): update s < alpha_cap of the
-    // column with id c takes alpha_in[c * alpha_cap + s]; null: computed
+    // start c takes alpha_in[c * alpha_cap + s]; null: computed
     const double *alpha_in;
     int32_t alpha_cap;
+    // queued starts (null queue: every start has its own column). A column
+    // whose start ends writes the final iterate to xfin (n x nstart, leading
+    // dimension n) and its record to fin, then takes the next start from the
+    // counter *queue (x from X0, n x nstart; the penalty from p0 or 0)
+    int32_t *queue;
+    int32_t nstart;
+    const double *X0;
+    const double *p0;
+    double *xfin;
+    Col *fin;
     // parameters
     int32_t inner;       // psdp_inner
     int32_t max_inner, max_outer, stall_outer, eig_maxit, cg_maxit;

@@ -329,7 +329,7 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
     const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
     const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
     double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
-    if (w.alpha_in && c.s < w.alpha_cap) alpha = w.alpha_in[(int64_t)uni(c.id) * w.alpha_cap + uni(c.s)];
+    if (w.alpha_in && c.s < w.alpha_cap) alpha = w.alpha_in[(int64_t)uni(c.start) * w.alpha_cap + uni(c.s)];
     double mx[2] = {0.0, 0.0};
     CHUNKS(n) {
         CHUNK_INDEX(n)
@@ -372,15 +372,15 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
 }
 
 // ---------------------------------------------------------------------------
-// End of a subproblem (Algorithm 3, after the subproblem solve).
+// End of a subproblem (Algorithm 3, after the subproblem solve); the loop
+// head (outer_begin) follows in the step kernel.
 
 template <typename OpT, int EPT>
-__device__ void end_subproblem(const Work &w, Col &c, const ColView &cv, double *red, int ci,
-                               bool moved, double rel) {
+__device__ void end_subproblem(const Work &w, Col &c, bool moved, double rel) {
     if (threadIdx.x == 0) {
         c.stall = moved ? 0 : c.stall + 1;
         if (w.trace && c.ntrace < w.trace_cap) {
-            double *t = w.trace + ((int64_t)ci * w.trace_cap + c.ntrace) * 6;
+            double *t = w.trace + ((int64_t)c.start * w.trace_cap + c.ntrace) * 6;
             t[0] = (double)c.s;
             t[1] = (double)c.nI;
             t[2] = c.lam;
@@ -392,14 +392,14 @@ __device__ void end_subproblem(const Work &w, Col &c, const ColView &cv, double 
         c.s += 1;
     }
     __syncthreads();
-    outer_begin<OpT, EPT>(w, c, cv, red);
 }
 
 // ---------------------------------------------------------------------------
-// Subproblem iteration (Algorithms 1 and 2).
+// Subproblem iteration (Algorithms 1 and 2). Returns true when the
+// subproblem ended (the loop head runs next).
 
 template <typename OpT, typename UT, int EPT, bool CACHE>
-__device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red, int ci) {
+__device__ bool inner_step(const Work &w, Col &c, const ColView &cv, double *red) {
     const uint32_t n = cv.n;
     const UVec<double> x = uvec(w.x, cv.off), xp = uvec(w.xp, cv.off), g = uvec(w.g, cv.off), gp = uvec(w.gp, cv.off);
     const UVec<const double> p = uvec((const double *)w.p, cv.off), gam = uvec((const double *)w.gam, cv.io);
@@ -457,12 +457,12 @@ __device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red
     }
     __syncthreads();
     if (rel < w.tol_kkt) {
-        end_subproblem<OpT, EPT>(w, c, cv, red, ci, k > 0, rel);
-        return;
+        end_subproblem<OpT, EPT>(w, c, k > 0, rel);
+        return true;
     }
     if (k > 0 && mx[1] == 0.0) {
-        end_subproblem<OpT, EPT>(w, c, cv, red, ci, true, rel);
-        return;
+        end_subproblem<OpT, EPT>(w, c, true, rel);
+        return true;
     }
     double alpha = 0.0;
     if (w.inner == PSDP_INNER_PABB) {
@@ -501,11 +501,12 @@ __device__ void inner_step(const Work &w, Col &c, const ColView &cv, double *red
     }
     if (k + 1 >= w.max_inner) {
         __syncthreads();
-        end_subproblem<OpT, EPT>(w, c, cv, red, ci, true, rel);
-        return;
+        end_subproblem<OpT, EPT>(w, c, true, rel);
+        return true;
     }
     if (threadIdx.x == 0) c.k = k + 1;
     __syncthreads();
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -940,10 +941,11 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
 }
 
 // ---------------------------------------------------------------------------
-// x^0 by Jacobi-preconditioned CG on K = 2 (Q + Diag gamma).
+// x^0 by Jacobi-preconditioned CG on K = 2 (Q + Diag gamma). Returns true
+// when x^0 is done (the loop head runs next).
 
 template <typename OpT, typename UT, int EPT>
-__device__ void cg_step(const Work &w, Col &c, const ColView &cv, double *red) {
+__device__ bool cg_step(const Work &w, Col &c, const ColView &cv, double *red) {
     const uint32_t n = cv.n;
     const UVec<double> x = uvec(w.x, cv.off);
     const UVec<double> r = uvec(w.v, cv.off), d = uvec(w.w, cv.off), Kd = uvec(w.Av, cv.off);
@@ -997,10 +999,7 @@ __device__ void cg_step(const Work &w, Col &c, const ColView &cv, double *red) {
         c.it = it;
     }
     __syncthreads();
-    if (sqrt(s2[1]) <= w.cg_tol * c.r0 || it >= w.cg_maxit) {
-        outer_begin<OpT, EPT>(w, c, cv, red);
-        return;
-    }
+    if (sqrt(s2[1]) <= w.cg_tol * c.r0 || it >= w.cg_maxit) return true;
     const double beta = s2[0] / c.rz;
     double md[1] = {0.0};
     CHUNKS(n) {
@@ -1028,6 +1027,7 @@ __device__ void cg_step(const Work &w, Col &c, const ColView &cv, double *red) {
     }
     if (threadIdx.x == 0) c.rz = s2[0];
     __syncthreads();
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -1097,6 +1097,50 @@ __device__ void compact_lists(const Work &w) {
 }
 
 // ---------------------------------------------------------------------------
+// Queued starts: a column whose start has just ended saves it (final iterate
+// and record) and takes the next start from the queue, set up as the first
+// starts are (x from X0, the penalty terms of p0); the caller then runs the
+// loop head for it. So every start performs the same arithmetic whichever
+// column holds it and when. Returns false when the queue is empty.
+
+template <int EPT>
+__device__ bool next_start(const Work &w, Col &c, const ColView &cv) {
+    __shared__ int32_t nxt;
+    const uint32_t n = cv.n;
+    const UVec<double> x = uvec(w.x, cv.off), p = uvec(w.p, cv.off);
+    const UVec<double> dg = uvec(w.diag, cv.off), ln = uvec(w.lin, cv.off);
+    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
+    const UVec<const double> dq = uvec((const double *)w.dq, cv.io);
+    double *xf = w.xfin + (int64_t)uni(c.start) * n;
+    FOR_I(n) xf[i] = x[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        w.fin[c.start] = c;
+        nxt = atomicAdd(w.queue, 1);
+    }
+    __syncthreads();
+    const int32_t s2 = nxt;
+    if (s2 >= w.nstart) return false;
+    const double *x0 = w.X0 + (int64_t)s2 * n;
+    FOR_I(n) {
+        x[i] = x0[i];
+        const double pi = w.p0 ? w.p0[i] : 0.0;
+        p[i] = pi;
+        dg[i] = (dq[i] + gam[i]) - pi;
+        ln[i] = (b[i] - gam[i]) + pi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c.start = s2;
+        c.k = c.s = c.stall = c.it = c.hasP = c.exit_reason = c.ntrace = c.nI = 0;
+        c.rho = c.rho_outer = c.lam = c.rz = c.r0 = c.final_rel = c.final_bg = c.alpha = 0.0;
+        c.evals = c.aux = c.inner_start = 0;
+    }
+    __syncthreads();
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // Kernels.
 
 template <typename OpT, typename UT, int EPT, bool CI, int CE>
@@ -1118,12 +1162,22 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
     if (ph0 != PH_DONE) {
         const ColView cv = view(c);
         const unsigned long long t0 = w.phase_prof ? wall_clock64() : 0ull;
+        bool head = false;
         switch (ph0) {
-            case PH_INNER: inner_step<OpT, UT, EPT, CI>(w, c, cv, red, ci); break;
+            case PH_INNER: head = inner_step<OpT, UT, EPT, CI>(w, c, cv, red); break;
             case PH_EIG0: eig0_step<OpT, UT, EPT>(w, c, cv, red); break;
             case PH_EIG: eig_step<OpT, UT, EPT, CE>(w, c, cv, red); break;
-            case PH_CG: cg_step<OpT, UT, EPT>(w, c, cv, red); break;
+            case PH_CG: head = cg_step<OpT, UT, EPT>(w, c, cv, red); break;
             default: break;
+        }
+        // Algorithm 3's loop head after a subproblem or the x^0 solve; with
+        // queued starts a column whose start has ended takes the next one and
+        // runs the head for it (one call site of the head keeps the kernel's
+        // register use down)
+        while (head) {
+            outer_begin<OpT, EPT>(w, c, cv, red);
+            __syncthreads();
+            head = w.queue != nullptr && c.phase == PH_DONE && next_start<EPT>(w, c, cv);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1180,7 +1234,7 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
         }
     }
     if (!use_cg) {
-        FOR_I(n) x[i] = X0[(int64_t)ci * n + i];
+        FOR_I(n) x[i] = X0[(int64_t)c.start * n + i];
         __syncthreads();
         outer_begin<OpT, EPT>(w, c, cv, red);
     } else {
