@@ -52,7 +52,8 @@ typedef enum {
     PSDP_E_OVERFLOW = -4,       /* exact int64 objective bound would overflow */
     PSDP_E_DEVICE = -5,         /* HIP runtime error (detail in psdp_last_error) */
     PSDP_E_NOMEM = -6,          /* device allocation failed */
-    PSDP_E_UNSUPPORTED = -7     /* valid but unsupported combination */
+    PSDP_E_UNSUPPORTED = -7,    /* valid but unsupported combination */
+    PSDP_E_INTERNAL = -8        /* a bookkeeping check of the library failed (a library bug) */
 } psdp_status;
 
 /* Subproblem solver: Algorithm 2 (projected alternating BB) or Algorithm 1
@@ -456,6 +457,34 @@ psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t
 
 /* Releases the cached device workspace of every device (optional). */
 void psdp_release(void);
+
+/* Column bookkeeping of a batched solve's workspace (no paper passage: the
+ * layout of the library's own buffers, for callers that size device memory
+ * and for host-side tests of the layout). The product kernels read the
+ * live-column lists and, through them, the per-column operand buffers; a
+ * list slot left empty (its column ended or changed product) names column
+ * zero_col, whose operand data stay zero, and the kernels read list entries
+ * up to index zero_col. So every list and every operand buffer read through
+ * a list holds zero_col + 1 columns; the solve entry points check this when
+ * they allocate and fail with PSDP_E_INTERNAL if it does not hold. */
+typedef struct {
+    int64_t ld;            /* leading dimension of the per-column vectors (elements) */
+    int32_t ncol;          /* columns advanced together: B, or params.slots when 0 < slots < B */
+    int32_t zero_col;      /* the all-zero column that empty list slots name */
+    int32_t list_len;      /* entries of each live-column list */
+    int32_t digit_cols;    /* columns of the digit planes (I8 operands), 0 otherwise */
+    int32_t word_cols;     /* columns of the sparse products' operand words (I8 with a
+                              sparse copy of Q), 0 otherwise */
+    int32_t ok;            /* 1 when every list-indexed buffer holds zero_col + 1 columns */
+} psdp_column_plan;
+
+/* Fills *out with the plan that psdp_solve_i32 / psdp_solve_f64 would use for
+ * n, B starts and *prm (NULL = defaults); sparse_copy = 1 when the sparse copy
+ * of Q is built (params.sparse = 1, or the automatic rule for the data).
+ * Host only: no device work, callable without a GPU. PSDP_E_INVALID for
+ * n outside [1, 65536], B < 1 or bad params. */
+psdp_status psdp_plan_columns(int64_t n, int32_t B, const psdp_params *prm, int32_t sparse_copy,
+                              psdp_column_plan *out);
 
 #ifdef __cplusplus
 }

@@ -6,5 +6,5 @@ the library is not built. Nothing here computes on the CPU.
 from .binding import (  # noqa: F401
     F32, F64, BF16, I8, PABB, PPA, EXIT_NAMES, PSDPError, Params, Stats,
     default_params, eval_penalty_grad, load, penalty_adjoint, penalty_fn,
-    perturbation, qx_dense, qx_digits, round_objective, solve, solve_group, solve_host,
+    perturbation, plan_columns, qx_dense, qx_digits, round_objective, solve, solve_group, solve_host,
 )

@@ -78,6 +78,21 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ColumnPlan(ctypes.Structure):
+    _fields_ = [
+        ("ld", ctypes.c_int64),
+        ("ncol", ctypes.c_int32),
+        ("zero_col", ctypes.c_int32),
+        ("list_len", ctypes.c_int32),
+        ("digit_cols", ctypes.c_int32),
+        ("word_cols", ctypes.c_int32),
+        ("ok", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # Exported symbols of include/psdp.h with their ctypes signatures.
 _P = ctypes.c_void_p
 _I32, _I64, _U64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
@@ -110,6 +125,7 @@ SIGNATURES = {
     "psdp_qx_sparse": (_I32, [_P, _I64, _P, _I32, _I32, _P, _P]),
     "psdp_qx_dense": (_I32, [_I32, _P, _I64, _P, _I32, _P, _P]),
     "psdp_release": (None, []),
+    "psdp_plan_columns": (_I32, [_I64, _I32, ctypes.POINTER(Params), _I32, ctypes.POINTER(ColumnPlan)]),
 }
 
 _lib = None
@@ -163,6 +179,15 @@ def default_params(**overrides) -> Params:
             v = PERTURB[v]
         setattr(p, k, v)
     return p
+
+
+def plan_columns(n: int, B: int, sparse_copy: bool = False, **params) -> dict:
+    """psdp_plan_columns: the column bookkeeping a solve of B starts would
+    allocate (host only, no device work)."""
+    out = ColumnPlan()
+    prm = default_params(**params)
+    _check(load().psdp_plan_columns(n, B, ctypes.byref(prm), 1 if sparse_copy else 0, ctypes.byref(out)))
+    return out.as_dict()
 
 
 def _torch():

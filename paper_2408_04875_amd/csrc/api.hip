@@ -42,6 +42,42 @@ psdp_status hipfail(hipError_t e, const char *where) {
 // (32), zero padded, so that 16-byte loads of whole chunks stay in bounds.
 int64_t padld(int64_t n) { return (n + 31) / 32 * 32; }
 
+// Every list and every operand buffer that the product kernels read through
+// a list holds zero_col + 1 columns: an empty list slot names zero_col.
+bool plan_holds_zero_col(const psdp_column_plan &p) {
+    const int64_t need = (int64_t)p.zero_col + 1;
+    return p.ncol >= 1 && p.zero_col >= p.ncol && p.list_len >= need && (p.digit_cols == 0 || p.digit_cols >= need) &&
+           (p.word_cols == 0 || p.word_cols >= need);
+}
+
+// Column bookkeeping of a solve of B starts on n variables (see
+// psdp_column_plan); the allocations below take their sizes from it.
+psdp_column_plan plan_columns(int64_t n, int32_t B, const psdp_params &prm, bool sparse_copy) {
+    psdp_column_plan p{};
+    const bool i8 = prm.qx_dtype == PSDP_I8;  // exact integer products, any B
+    const bool batched = B > 1 || i8;
+    // columns advanced together: every start, or prm.slots of them with the
+    // other starts queued (a column takes the next start when its own ends)
+    p.ncol = (batched && prm.slots > 0 && prm.slots < B) ? prm.slots : B;
+    p.ld = i8 ? (n + 63) / 64 * 64 : padld(n);
+    p.zero_col = p.ncol;
+    p.list_len = p.ncol + 1;
+    p.digit_cols = i8 ? p.ncol + 1 : 0;
+    p.word_cols = (i8 && sparse_copy) ? p.ncol + 1 : 0;
+    p.ok = plan_holds_zero_col(p) ? 1 : 0;
+    return p;
+}
+
+// The plan of a group launch: one column per instance, no integer operands.
+psdp_column_plan plan_group(int32_t count) {
+    psdp_column_plan p{};
+    p.ncol = count;
+    p.zero_col = count;
+    p.list_len = count + 1;
+    p.ok = plan_holds_zero_col(p) ? 1 : 0;
+    return p;
+}
+
 // Device allocations released in reverse order when the solve returns.
 struct Arena {
     std::vector<void *> ptrs;
@@ -344,8 +380,12 @@ void fill_work_params(Work &w, const psdp_params &p) {
 // Allocates the per-column vectors for `total` doubles of column storage.
 // Every buffer is cleared on the solve stream: that stream does not wait for
 // the null stream, so a plain hipMemset could land after the first kernels.
-psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, hipStream_t st, int64_t ld = 0) {
+psdp_status alloc_columns(Solver &S, int64_t total, const psdp_column_plan &pl, int64_t ksplit, hipStream_t st) {
+    if (!pl.ok || !plan_holds_zero_col(pl))
+        return fail(PSDP_E_INTERNAL, "a list-indexed buffer lacks the all-zero column");
     Work &w = S.w;
+    const int ncol = pl.ncol;
+    const int64_t ld = pl.ld;
     double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w, &w.diag, &w.lin, &w.zx};
     for (double **v : vecs) {
         HIPCHK(S.ar.get((void **)v, total * sizeof(double)));
@@ -363,15 +403,16 @@ psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, hi
     HIPCHK(hipMemsetAsync(w.U, 0, ksplit * total * ue, st));
     if (w.i8) {
         // one extra all-zero column stands in for the unused rows of a digit tile
-        const int64_t pl = (int64_t)(ncol + 1) * ld;
-        HIPCHK(S.ar.get((void **)&w.dig, 4 * pl));
-        HIPCHK(hipMemsetAsync(w.dig, 0, 4 * pl, st));
-        HIPCHK(S.ar.get((void **)&w.dig_aux, 8 * pl));
-        HIPCHK(hipMemsetAsync(w.dig_aux, 0, 8 * pl, st));
+        if (pl.digit_cols < pl.zero_col + 1) return fail(PSDP_E_INTERNAL, "digit planes lack the all-zero column");
+        const int64_t plane = (int64_t)pl.digit_cols * ld;
+        HIPCHK(S.ar.get((void **)&w.dig, 4 * plane));
+        HIPCHK(hipMemsetAsync(w.dig, 0, 4 * plane, st));
+        HIPCHK(S.ar.get((void **)&w.dig_aux, 8 * plane));
+        HIPCHK(hipMemsetAsync(w.dig_aux, 0, 8 * plane, st));
         HIPCHK(S.ar.get((void **)&w.U_lo, ksplit * total * sizeof(int64_t)));
         HIPCHK(hipMemsetAsync(w.U_lo, 0, ksplit * total * sizeof(int64_t), st));
     }
-    for (int p = 0; p < 2; ++p) HIPCHK(S.ar.get((void **)&S.act[p], (ncol + 1) * sizeof(int32_t)));
+    for (int p = 0; p < 2; ++p) HIPCHK(S.ar.get((void **)&S.act[p], (size_t)pl.list_len * sizeof(int32_t)));
     HIPCHK(S.ar.get((void **)&S.cnt, 64));
     HIPCHK(hipMemsetAsync(S.cnt, 0, 64, st));
     HIPCHK(S.ar.get((void **)&S.sweeps, 64));
@@ -385,7 +426,7 @@ psdp_status alloc_columns(Solver &S, int64_t total, int ncol, int64_t ksplit, hi
         HIPCHK(hipMemsetAsync(w.op_aux, 0, total * sizeof(double), st));
         HIPCHK(S.ar.get((void **)&w.U_aux, ksplit * total * sizeof(double)));
         HIPCHK(hipMemsetAsync(w.U_aux, 0, ksplit * total * sizeof(double), st));
-        for (int p = 0; p < 2; ++p) HIPCHK(S.ar.get((void **)&S.act_aux[p], (ncol + 1) * sizeof(int32_t)));
+        for (int p = 0; p < 2; ++p) HIPCHK(S.ar.get((void **)&S.act_aux[p], (size_t)pl.list_len * sizeof(int32_t)));
     } else {
         w.ksplit_aux = w.ksplit;
         w.slice_aux = w.slice;
@@ -639,11 +680,10 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     Solver S;
     const bool i8 = prm.qx_dtype == PSDP_I8;  // exact integer products, any B
     const bool batched = B > 1 || i8;
-    // columns advanced together: every start, or prm.slots of them with the
-    // other starts queued (a column takes the next start when its own ends)
-    const int32_t ncol = (batched && prm.slots > 0 && prm.slots < B) ? prm.slots : B;
+    const psdp_column_plan plan = plan_columns(n, B, prm, csr);
+    const int32_t ncol = plan.ncol;
     const bool queued = ncol < B;
-    const int64_t ld = i8 ? (n + 63) / 64 * 64 : padld(n);
+    const int64_t ld = plan.ld;
     S.optype = batched ? prm.qx_dtype : PSDP_F64;  // single instance: FP64 x, Q in qx_dtype
     S.utype = batched ? prm.qx_dtype : PSDP_F64;
     Work &w = S.w;
@@ -711,14 +751,15 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
     // column data
     const int kmax = (batched && !i8) ? kMaxSplit : 1;  // integer slices add into one buffer
-    if (psdp_status s2 = alloc_columns(S, ld * ncol, ncol, kmax, st, ld)) return s2;
+    if (psdp_status s2 = alloc_columns(S, ld * ncol, plan, kmax, st)) return s2;
     if (S.rowptr) {
         // the operands' grid values as words, for the sparse products; like
         // the digit planes they hold one extra all-zero column (index ncol),
         // which empty list slots and the slots past the count name
+        if (plan.word_cols < plan.zero_col + 1) return fail(PSDP_E_INTERNAL, "operand words lack the all-zero column");
         for (int32_t **pw : {&w.tw, &w.tw_hi, &w.tw_lo}) {
-            HIPCHK(S.ar.get((void **)pw, ld * (ncol + 1) * sizeof(int32_t)));
-            HIPCHK(hipMemsetAsync(*pw, 0, ld * (ncol + 1) * sizeof(int32_t), st));
+            HIPCHK(S.ar.get((void **)pw, ld * plan.word_cols * sizeof(int32_t)));
+            HIPCHK(hipMemsetAsync(*pw, 0, ld * plan.word_cols * sizeof(int32_t), st));
         }
     }
     const int MT = (int)((ld + 63) / 64);
@@ -1003,6 +1044,7 @@ const char *psdp_status_string(psdp_status s) {
         case PSDP_E_DEVICE: return "HIP device error";
         case PSDP_E_NOMEM: return "out of device memory";
         case PSDP_E_UNSUPPORTED: return "unsupported combination";
+        case PSDP_E_INTERNAL: return "internal bookkeeping check failed";
     }
     return "unknown status";
 }
@@ -1010,6 +1052,22 @@ const char *psdp_status_string(psdp_status s) {
 const char *psdp_last_error(void) { return g_err.c_str(); }
 
 int32_t psdp_version(void) { return 10000; }
+
+psdp_status psdp_plan_columns(int64_t n, int32_t B, const psdp_params *prm_in, int32_t sparse_copy,
+                              psdp_column_plan *out) {
+    g_err.clear();
+    if (!out) return fail(PSDP_E_INVALID, "null out");
+    if (n < 1 || n > 65536 || B < 1) return fail(PSDP_E_INVALID, "n must be in [1, 65536] and B >= 1");
+    psdp_params prm;
+    psdp_params_default(&prm);
+    if (prm_in) {
+        if (prm_in->struct_size != sizeof(psdp_params)) return fail(PSDP_E_INVALID, "params.struct_size");
+        prm = *prm_in;
+    }
+    if (psdp_status s = check_params(prm)) return s;
+    *out = plan_columns(n, B, prm, sparse_copy != 0);
+    return PSDP_OK;
+}
 
 psdp_status psdp_solve_i32_ex(const int32_t *Q, const int32_t *b, int64_t n, const double *X0,
                               const double *p0, int32_t B, const psdp_params *prm, uint8_t *xhat,
@@ -1112,7 +1170,7 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     w.dq = dq;
     HIPCHK(S.ar.get((void **)&w.inst, count * sizeof(Inst)));
     HIPCHK(hipMemcpyAsync(w.inst, hin.data(), count * sizeof(Inst), hipMemcpyHostToDevice, st));
-    if (psdp_status s2 = alloc_columns(S, total, count, 1, st)) return s2;
+    if (psdp_status s2 = alloc_columns(S, total, plan_group(count), 1, st)) return s2;
     std::vector<Col> hcol(count);
     for (int i = 0; i < count; ++i) {
         Col &cc = hcol[i];
@@ -1294,7 +1352,12 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     std::vector<int64_t> rownnz;
     if (psdp_status s = qx_int_checks(Q, n, X, B, digits, Y, st, &rownnz)) return s;
     Arena ar;
-    const int64_t ld = (n + 63) / 64 * 64;
+    psdp_params prm;
+    psdp_params_default(&prm);
+    prm.qx_dtype = PSDP_I8;
+    const psdp_column_plan plan = plan_columns(n, B, prm, false);
+    if (!plan.ok) return fail(PSDP_E_INTERNAL, "a list-indexed buffer lacks the all-zero column");
+    const int64_t ld = plan.ld;
     const int64_t rows = (ld + kDigitRowsAlign - 1) / kDigitRowsAlign * kDigitRowsAlign;
     const int D = digits;
     int mt = 4, nb = 1;
@@ -1309,8 +1372,8 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     HIPCHK(ar.get((void **)&R, ld * 8));
     HIPCHK(ar.get((void **)&dq, ld * 8));
     HIPCHK(launch_prep_q(PSDP_I8, Q, n, ld, PSDP_PERTURB_NONE, 0.0, 0, Q8, R, dq, st));
-    HIPCHK(ar.get((void **)&dig, (int64_t)(B + 1) * D * ld));
-    HIPCHK(hipMemsetAsync(dig, 0, (int64_t)(B + 1) * D * ld, st));
+    HIPCHK(ar.get((void **)&dig, (int64_t)plan.digit_cols * D * ld));
+    HIPCHK(hipMemsetAsync(dig, 0, (int64_t)plan.digit_cols * D * ld, st));
     HIPCHK(ar.get((void **)&esc, (int64_t)B * sizeof(int32_t)));
     HIPCHK(launch_digits_from_vectors(X, n, n, B, D, dig, ld, esc, st));
     // the K slices add into one zeroed product buffer (two for 8 digits)
@@ -1321,11 +1384,12 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
         HIPCHK(ar.get((void **)&U1, slice * sizeof(int64_t)));
         HIPCHK(hipMemsetAsync(U1, 0, slice * sizeof(int64_t), st));
     }
-    std::vector<int32_t> iota(B + 1);
+    // the live list: every column, then the count at index B = zero_col
+    std::vector<int32_t> iota(plan.list_len);
     for (int c = 0; c < B; ++c) iota[c] = c;
     iota[B] = B;  // live count
-    HIPCHK(ar.get((void **)&act, (B + 1) * sizeof(int32_t)));
-    HIPCHK(hipMemcpyAsync(act, iota.data(), (B + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(ar.get((void **)&act, (size_t)plan.list_len * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(act, iota.data(), (size_t)plan.list_len * sizeof(int32_t), hipMemcpyHostToDevice, st));
     cnt = act + B;
     const DigitJob job{dig, act, cnt, U0, U1, B, ks, mt, B};
     HIPCHK(launch_digit(Q8, ld, n, ld, D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
@@ -1396,7 +1460,12 @@ psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t
     int64_t nnz = 0;
     if (!csr_rowptr(rownnz, &hrowptr, &nnz)) return fail(PSDP_E_UNSUPPORTED, "sparse Q needs fewer than 2^31 nonzeros");
     Arena ar;
-    const int64_t ld = (n + 63) / 64 * 64;
+    psdp_params prm;
+    psdp_params_default(&prm);
+    prm.qx_dtype = PSDP_I8;
+    const psdp_column_plan plan = plan_columns(n, B, prm, true);
+    if (!plan.ok) return fail(PSDP_E_INTERNAL, "a list-indexed buffer lacks the all-zero column");
+    const int64_t ld = plan.ld;
     const int D = digits;
     int8_t *Q8;
     double *R, *dq;
@@ -1412,18 +1481,22 @@ psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t
     HIPCHK(ar.get((void **)&pk, std::max<int64_t>(1, nnz) * sizeof(uint32_t)));
     HIPCHK(hipMemcpyAsync(rowptr, hrowptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIPCHK(launch_csr_fill(Q8, ld, n, rowptr, pk, st));
-    const int64_t slice = (int64_t)B * ld;
-    HIPCHK(ar.get((void **)&w0, slice * sizeof(int32_t)));
-    if (D == 8) HIPCHK(ar.get((void **)&w1, slice * sizeof(int32_t)));
+    const int64_t slice = (int64_t)B * ld, wslice = (int64_t)plan.word_cols * ld;
+    HIPCHK(ar.get((void **)&w0, wslice * sizeof(int32_t)));
+    HIPCHK(hipMemsetAsync(w0, 0, wslice * sizeof(int32_t), st));
+    if (D == 8) {
+        HIPCHK(ar.get((void **)&w1, wslice * sizeof(int32_t)));
+        HIPCHK(hipMemsetAsync(w1, 0, wslice * sizeof(int32_t), st));
+    }
     HIPCHK(ar.get((void **)&esc, (int64_t)B * sizeof(int32_t)));
     HIPCHK(launch_words_from_vectors(X, n, n, B, D, w0, w1, ld, esc, st));
     HIPCHK(ar.get((void **)&U0, slice * sizeof(int64_t)));
     if (D == 8) HIPCHK(ar.get((void **)&U1, slice * sizeof(int64_t)));
-    std::vector<int32_t> iota(B + 1);
+    std::vector<int32_t> iota(plan.list_len);
     for (int c = 0; c < B; ++c) iota[c] = c;
     iota[B] = B;  // live count
-    HIPCHK(ar.get((void **)&act, (B + 1) * sizeof(int32_t)));
-    HIPCHK(hipMemcpyAsync(act, iota.data(), (B + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(ar.get((void **)&act, (size_t)plan.list_len * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(act, iota.data(), (size_t)plan.list_len * sizeof(int32_t), hipMemcpyHostToDevice, st));
     const SparseJob job{1, rowptr, pk, n, w0, w1, ld, act, act + B, B, U0, U1, ld};
     HIPCHK(launch_sparse(D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
     HIPCHK(launch_digit_combine(U0, U1, n, ld, B, D, esc, Y, st));

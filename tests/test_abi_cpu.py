@@ -42,7 +42,7 @@ def test_params_defaults_and_struct_size(lib):
 
 
 def test_status_strings(lib):
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         s = lib.psdp_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.psdp_status_string(-99).decode() == "unknown status"
@@ -86,3 +86,42 @@ def test_product_path_has_no_oracle_or_fallback():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "workloads" not in txt, f
+
+
+@pytest.mark.parametrize("B", [1, 7, 256])
+def test_list_indexed_buffers_hold_the_zero_column(lib, B):
+    """Every buffer that the product kernels read through a live-column list
+    (the lists, the digit planes, the sparse operand words) holds the extra
+    all-zero column that an empty list slot names (index zero_col = ncol).
+    The solve allocates from this plan and refuses to run when the check
+    fails; here the plan is taken for B starts with every operand type, with
+    and without the sparse copy, and with queued starts."""
+    from paper_2408_04875_amd import binding
+    seen = 0
+    for qdt in ("i8", "f32", "f64", "bf16"):
+        for sparse in (False, True):
+            for slots in sorted({0, 1, 3, max(1, B // 2), B, 2 * B}):
+                if qdt == "bf16" and B > 1:
+                    continue
+                for n in (1, 63, 64, 2500):
+                    pl = binding.plan_columns(n, B, sparse_copy=sparse, qx_dtype=qdt, slots=slots)
+                    batched = B > 1 or qdt == "i8"
+                    ncol = slots if (batched and 0 < slots < B) else B
+                    assert pl["ncol"] == ncol
+                    assert pl["zero_col"] == ncol
+                    need = pl["zero_col"] + 1
+                    assert pl["list_len"] >= need
+                    if qdt == "i8":
+                        assert pl["digit_cols"] >= need
+                        assert pl["ld"] % 64 == 0 and pl["ld"] >= n
+                        assert pl["word_cols"] >= need if sparse else pl["word_cols"] == 0
+                    else:
+                        assert pl["digit_cols"] == 0 and pl["word_cols"] == 0
+                        assert pl["ld"] % 32 == 0 and pl["ld"] >= n
+                    assert pl["ok"] == 1
+                    seen += 1
+    assert seen > 0
+    with pytest.raises(binding.PSDPError, match="invalid"):
+        binding.plan_columns(0, B)
+    with pytest.raises(binding.PSDPError, match="slots"):
+        binding.plan_columns(10, B, slots=-1)
