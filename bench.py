@@ -57,7 +57,6 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 MFMA
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 MFMA
 STEP_BYTES_PER_COLUMN = 80  # about 10 FP64 vectors of n per column update
 START_SEED = 3              # start set of the first timed step (the workload generator's default)
-INSTR_SETS = 8              # start sets of the solve timed launch by launch (queued launches)
 STEP_SOURCES = ("paper_2408_04875_amd/csrc/solver.hip", "paper_2408_04875_amd/csrc/common.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_traffic.json")
 
@@ -65,8 +64,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_traffic.js
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=2500)
     ap.add_argument("--starts", type=int, default=256)
     ap.add_argument("--plain-starts", type=int, default=32)
@@ -91,6 +90,8 @@ def parse():
     ap.add_argument("--gemv-only", action="store_true", help="only the large single-instance GEMV leg")
     ap.add_argument("--qx", default="i8", choices=["i8", "f32", "f64"])
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--yardstick-counts", default="16,64,256",
+                    help="column counts of the n=2500 yardstick (comma separated)")
     ap.add_argument("--gemm-yardstick", action="store_true",
                     help="time the library's digit product next to hipBLASLt's int8 GEMM of the same shape")
     return ap.parse_args()
@@ -117,8 +118,8 @@ def step_source_hash():
 
 TRACE_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_trace.json")
 # the bench command the kernel records are taken from: the default configuration (queued launch
-# of 1024 columns) over eight start sets, without the side legs
-PROFILE_ARGS = ("--steps 8 --warmup 0 --no-cpu-baseline --no-plain --no-fp32 --no-sparse --no-gemv --no-group "
+# of 1024 columns) over twenty start sets, without the side legs
+PROFILE_ARGS = ("--steps 20 --warmup 0 --no-cpu-baseline --no-plain --no-fp32 --no-sparse --no-gemv --no-group "
                 "--no-replay --no-adjoint --no-per-set")
 STEP_KERNEL_PREFIX = "solver_step_kernel"
 
@@ -165,7 +166,7 @@ def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel=
     f_kib, nd = per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
     w_kib, _ = per_dispatch(write_csv, "WRITE_SIZE", kernel)
     fb, wb = f_kib * 1024.0 * fs, w_kib * 1024.0 * ws
-    rec = {"kernel": f"{kernel} (n = 2500, 8 sets of 256 starts through 1024 columns, I8 operands)",
+    rec = {"kernel": f"{kernel} (n = 2500, 20 sets of 256 starts through 1024 columns, I8 operands)",
            "source_sha256": step_source_hash(),
            "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "dispatches": nd, "fetch_size_kib_avg": f_kib, "write_size_kib_avg": w_kib,
@@ -557,8 +558,9 @@ def main():
         calibrate_copy()
         return
     if args.gemm_yardstick:
-        gemm_yardstick(n=args.n)
-        gemm_yardstick(n=16384, counts=(256,))
+        gemm_yardstick(n=args.n, counts=tuple(int(c) for c in args.yardstick_counts.split(",")))
+        if args.yardstick_counts == "16,64,256":
+            gemm_yardstick(n=16384, counts=(256,))
         return
     import numpy as np
     import torch
@@ -627,11 +629,10 @@ def main():
     aux = sum(sum(s["aux_matvecs"] for s in r.stats) for r in results)
     # one more solve with HIP events around every launch (library solve
     # stream): per-kernel average durations and algorithmic work. Per-set
-    # launches: the first start set; queued: the first eight sets' starts
-    # through the same number of columns
+    # launches: the first start set; queued: the timed sets' starts through
+    # the same number of columns (the timed workload, launched eagerly)
     if args.slots:
-        s0 = step(args.qx, timing=True, X=torch.cat(X0s[:min(INSTR_SETS, args.steps)], dim=0),
-                  slots=args.slots).stats[0]
+        s0 = step(args.qx, timing=True, X=torch.cat(X0s[:args.steps], dim=0), slots=args.slots).stats[0]
     else:
         s0 = step(args.qx, timing=True).stats[0]
     step_s, step_l, colsteps = s0["step_seconds"], s0["step_launches"], s0["column_steps"]
@@ -707,7 +708,7 @@ def main():
                                    "note": "the same start sets, one launch of 256 columns per set"}
     if not args.no_fp32 and args.qx != "f32":
         fres, fwall, fevals = timed("f32", args.steps, 0, args.slots)
-        ft = (step("f32", timing=True, X=torch.cat(X0s[:min(INSTR_SETS, args.steps)], dim=0), slots=args.slots)
+        ft = (step("f32", timing=True, X=torch.cat(X0s[:args.steps], dim=0), slots=args.slots)
               if args.slots else step("f32", timing=True)).stats[0]
         out["fp32_gemm"] = {"value": fevals / fwall, "unit": "evals/s", "steps": args.steps,
                             "ms_per_step": fwall / args.steps * 1e3,

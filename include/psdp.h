@@ -422,6 +422,52 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
                            int32_t digits, double *Y, hipStream_t stream);
 
 /*
+ * psdp_qx_digits_ex - psdp_qx_digits with the product's kernel settings
+ * given, and optionally timed (the same product as above: every setting
+ * yields the same integers, so Y does not depend on them).
+ * layout  block layout of the int8 MFMA kernel: 1 (few columns: the K range
+ *         of one 32-row block split over the four waves), 2 (64-row blocks,
+ *         the digit tile shared through LDS), 4 (128-row blocks), 8 (256-row
+ *         blocks), 16 (128-row blocks with 256 digit rows); 0 = the
+ *         library's choice for B columns (its table for n, see
+ *         psdp_set_digit_table, else its built-in rule).
+ * slices  K slices, 1..8 (0 = the library's choice).
+ * reps    > 0: after Y is formed, the product is launched reps more times
+ *         between two HIP events on `stream`, and *us receives the average
+ *         microseconds per launch (host pointer; unused when reps = 0).
+ * Errors: as psdp_qx_digits, and PSDP_E_INVALID for a layout, slices or reps
+ *         out of range.
+ */
+psdp_status psdp_qx_digits_ex(const int32_t *Q, int64_t n, const double *X, int32_t B,
+                              int32_t digits, int32_t layout, int32_t slices, int32_t reps,
+                              double *us, double *Y, hipStream_t stream);
+
+/*
+ * psdp_set_digit_table - the exact integer product's settings for problems
+ * with n variables (no paper passage: a speed setting, for the package's
+ * autotuner). For products of `digits` digits (4: subproblem iterates,
+ * 8: lambda_min and CG vectors), entry q holds the layout and K slices
+ * (as in psdp_qx_digits_ex, nonzero) used when the product's live-column
+ * estimate is at most max_cols[q]; max_cols increases with q, and the last
+ * entry also covers every larger estimate. Used by the solves, by
+ * psdp_qx_digits and by psdp_digit_choice from the next call on; count = 0
+ * removes the table for (n, digits). The arrays are host memory, copied.
+ * Errors: PSDP_E_INVALID (n, digits, count, a null array, max_cols not
+ *         positive and increasing, a layout or slice count out of range).
+ */
+psdp_status psdp_set_digit_table(int64_t n, int32_t digits, int32_t count, const int32_t *max_cols,
+                                 const int32_t *layout, const int32_t *slices);
+
+/*
+ * psdp_digit_choice - the settings the solves use for one launch holding a
+ * 4-digit product of est4 columns and an 8-digit product of est8 columns
+ * (0 = no such product) at n variables: choice[0..3] (host) = layout and K
+ * slices of the 4-digit product, then of the 8-digit product.
+ * Errors: PSDP_E_INVALID (n out of range, a negative estimate, null choice).
+ */
+psdp_status psdp_digit_choice(int64_t n, int32_t est4, int32_t est8, int32_t *choice);
+
+/*
  * psdp_qx_dense - the floating-point Q.X product of the batched solver path
  * (the O(n^2) part of every gradient evaluation, eq. (kkt1)) on given
  * vectors: Y[:, c] = Q_off X[:, c], Q_off = Q with a zero diagonal, through

@@ -126,13 +126,18 @@ SIGNATURES = {
     "psdp_qx_dense": (_I32, [_I32, _P, _I64, _P, _I32, _P, _P]),
     "psdp_release": (None, []),
     "psdp_plan_columns": (_I32, [_I64, _I32, ctypes.POINTER(Params), _I32, ctypes.POINTER(ColumnPlan)]),
+    "psdp_qx_digits_ex": (_I32, [_P, _I64, _P, _I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_D), _P, _P]),
+    "psdp_set_digit_table": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
+    "psdp_digit_choice": (_I32, [_I64, _I32, _I32, ctypes.POINTER(_I32)]),
 }
 
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Loads libpsdp.so (raises if it is missing: build it with build.py)."""
+def load(path: str = LIB_PATH, tuning: bool = True):
+    """Loads libpsdp.so (raises if it is missing: build it with build.py).
+    On the first load the product tables under tuning/ are installed
+    (install_tuning) unless tuning is False."""
     global _lib
     if _lib is not None:
         return _lib
@@ -145,6 +150,8 @@ def load(path: str = LIB_PATH):
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    if tuning and os.path.isdir(TUNING_DIR):
+        install_tuning()
     return lib
 
 
@@ -412,12 +419,19 @@ def round_objective(Q, b, X):
     return xhat, obj
 
 
-def qx_digits(Q, X, digits: int = 4, sparse: bool = False):
+# Layout codes of the exact integer product (psdp_qx_digits_ex).
+DIGIT_LAYOUTS = {"few": 1, "mid": 2, "many": 4, "wide": 8, "tall": 16}
+
+
+def qx_digits(Q, X, digits: int = 4, sparse: bool = False, layout=0, slices: int = 0, reps: int = 0):
     """Exact integer product of the I8 path: rows of X (shape (B, n) float64)
     times Q with a zero diagonal, returned as (B, n) float64. digits=4 needs
     X in [0,1] (grid 2^-27, exact result); digits=8 scales each row by a
     power of two (grid 2^(e-55), result rounded once). sparse=True computes
-    the same values from a sparse copy of Q (psdp_qx_sparse)."""
+    the same values from a sparse copy of Q (psdp_qx_sparse). layout (a name
+    of DIGIT_LAYOUTS or its code) and slices force the kernel settings
+    (psdp_qx_digits_ex); reps > 0 also times that many further launches and
+    returns (Y, microseconds per launch)."""
     torch = _torch()
     lib = load()
     _dev(Q, torch.int32, "Q")
@@ -426,9 +440,51 @@ def qx_digits(Q, X, digits: int = 4, sparse: bool = False):
     X2 = X.reshape(-1, n)
     B = X2.shape[0]
     Y = torch.empty((B, n), dtype=torch.float64, device=X.device)
-    fn = lib.psdp_qx_sparse if sparse else lib.psdp_qx_digits
-    _check(fn(_ptr(Q), n, _ptr(X2), B, int(digits), _ptr(Y), _stream()))
-    return Y
+    if sparse:
+        _check(lib.psdp_qx_sparse(_ptr(Q), n, _ptr(X2), B, int(digits), _ptr(Y), _stream()))
+        return Y
+    code = DIGIT_LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+    us = ctypes.c_double(0.0)
+    _check(lib.psdp_qx_digits_ex(_ptr(Q), n, _ptr(X2), B, int(digits), code, int(slices), int(reps),
+                                 ctypes.byref(us), _ptr(Y), _stream()))
+    return (Y, us.value) if reps > 0 else Y
+
+
+def set_digit_table(n: int, digits: int, entries):
+    """psdp_set_digit_table: entries = [(max_cols, layout, slices), ...] with
+    max_cols increasing (layout a name or code); [] removes the table."""
+    import numpy as np
+    mc = np.array([int(e[0]) for e in entries], dtype=np.int32)
+    lay = np.array([DIGIT_LAYOUTS[e[1]] if isinstance(e[1], str) else int(e[1]) for e in entries], dtype=np.int32)
+    sl = np.array([int(e[2]) for e in entries], dtype=np.int32)
+    _check(load().psdp_set_digit_table(n, digits, len(entries), mc.ctypes.data, lay.ctypes.data, sl.ctypes.data))
+
+
+def digit_choice(n: int, est4: int, est8: int = 0):
+    """psdp_digit_choice: ((layout, slices) of the 4-digit product, (layout,
+    slices) of the 8-digit product) for one launch."""
+    out = (ctypes.c_int32 * 4)()
+    _check(load().psdp_digit_choice(n, est4, est8, out))
+    return (out[0], out[1]), (out[2], out[3])
+
+
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+
+
+def install_tuning(path: str = TUNING_DIR):
+    """Installs every digit-product table found in the JSON files of `path`
+    (written by the package's autotuner); returns the (n, digits) keys."""
+    import glob
+    import json
+    keys = []
+    for f in sorted(glob.glob(os.path.join(path, "*.json"))):
+        with open(f) as fh:
+            doc = json.load(fh)
+        for t in doc.get("digit_tables", []):
+            set_digit_table(int(t["n"]), int(t["digits"]),
+                            [(e["max_cols"], e["layout"], e["slices"]) for e in t["entries"]])
+            keys.append((int(t["n"]), int(t["digits"])))
+    return keys
 
 
 def qx_dense(Q, X, dtype: str = "f32"):

@@ -13,7 +13,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "common.hpp"
+#include "launch.hpp"
 
 using namespace psdp;
 
@@ -66,6 +66,47 @@ psdp_column_plan plan_columns(int64_t n, int32_t B, const psdp_params &prm, bool
     p.word_cols = (i8 && sparse_copy) ? p.ncol + 1 : 0;
     p.ok = plan_holds_zero_col(p) ? 1 : 0;
     return p;
+}
+
+// Settings of the exact integer product (layout and K slices) per live
+// column estimate, for one n and one digit count, installed by
+// psdp_set_digit_table (written by the package's autotuner). Every setting
+// yields the same integers, so a table changes the speed only.
+struct DigitTableEntry {
+    int max_cols, layout, ks;
+};
+std::map<std::pair<int64_t, int>, std::vector<DigitTableEntry>> g_digit_tables;
+
+// Layouts and K slices of the two products of one launch (est4 subproblem
+// columns, est8 lambda_min / CG columns; an estimate of 0 means no product):
+// a product with a table for (n, D) takes the entry of the first bucket
+// holding its estimate (the last bucket beyond); otherwise the layout comes
+// from the live count and the K slices from both products' block count.
+struct DigitChoice {
+    int mt4, ks4, mt8, ks8;
+};
+DigitChoice digit_choice(int64_t n, int64_t ld, int est4, int est8) {
+    DigitChoice c{1, 1, 1, 1};
+    int b4 = 0, b8 = 0;
+    if (est4 > 0) digit_layout(est4, 4, ld, &c.mt4, &b4);
+    if (est8 > 0) digit_layout(est8, 8, ld, &c.mt8, &b8);
+    c.ks4 = digit_slices(c.mt4, b4 + b8);
+    c.ks8 = digit_slices(c.mt8, b4 + b8);
+    auto table = [&](int D, int est, int *mt, int *ks) {
+        auto it = g_digit_tables.find({n, D});
+        if (est <= 0 || it == g_digit_tables.end() || it->second.empty()) return;
+        const DigitTableEntry *e = &it->second.back();
+        for (const DigitTableEntry &t : it->second)
+            if (est <= t.max_cols) {
+                e = &t;
+                break;
+            }
+        *mt = e->layout;
+        *ks = e->ks;
+    };
+    table(4, est4, &c.mt4, &c.ks4);
+    table(8, est8, &c.mt8, &c.ks8);
+    return c;
 }
 
 // The plan of a group launch: one column per instance, no integer operands.
@@ -303,6 +344,9 @@ struct Solver {
     Work w{};
     std::function<void(int, int)> repick;  // adapts the product kernels to the live counts
     std::function<int64_t()> config_key;   // identifies the current product configuration
+    // enqueued before each batch of sweeps, after the configuration of the
+    // batch is chosen (nullable)
+    std::function<hipError_t(hipStream_t)> before_batch;
     // when set, each poll also copies the first list_cap entries of the main
     // live list, and relist receives the list and its count (a superset of the
     // columns still live when it runs)
@@ -359,6 +403,8 @@ hipError_t solve_stream(hipStream_t *out) {
 }
 
 void fill_work_params(Work &w, const psdp_params &p) {
+    w.clear_main = 1;
+    w.clear_aux = 1;
     w.inner = p.inner;
     w.max_inner = p.max_inner;
     w.max_outer = p.max_outer;
@@ -386,7 +432,7 @@ psdp_status alloc_columns(Solver &S, int64_t total, const psdp_column_plan &pl, 
     Work &w = S.w;
     const int ncol = pl.ncol;
     const int64_t ld = pl.ld;
-    double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w, &w.diag, &w.lin, &w.zx};
+    double **vecs[] = {&w.x, &w.xp, &w.g, &w.gp, &w.p, &w.v, &w.Av, &w.P, &w.AP, &w.w, &w.zx};
     for (double **v : vecs) {
         HIPCHK(S.ar.get((void **)v, total * sizeof(double)));
         HIPCHK(hipMemsetAsync(*v, 0, total * sizeof(double), st));
@@ -549,6 +595,7 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
     while (!finished) {
         const int nb = (int)std::min<int64_t>(prm.poll_sweeps, cap - done_sweeps);
         if (nb <= 0) return fail(PSDP_E_DEVICE, "sweep bound exceeded");
+        if (S.before_batch) HIPCHK(S.before_batch(st));
         if (graphs && nb == prm.poll_sweeps) {
             const int64_t key = (S.config_key ? S.config_key() : 0) * 2 + (done_sweeps & 1);
             auto it = execs.find(key);
@@ -741,11 +788,16 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         HIPCHK(S.ar.get(&Qaux, ld * ld * sizeof(double)));
         HIPCHK(launch_prep_q(PSDP_F64, Q, n, ld, prm.perturb, prm.sigma, prm.seed, Qaux, R, dq, st));
     }
-    HIPCHK(launch_gamma(b, R, dq, n, ld, bd, gam, st));
+    double *dgi, *lni;
+    HIPCHK(S.ar.get((void **)&dgi, ld * 8));
+    HIPCHK(S.ar.get((void **)&lni, ld * 8));
+    HIPCHK(launch_gamma(b, R, dq, n, ld, bd, gam, dgi, lni, st));
     w.b = bd;
     w.gam = gam;
     w.R = R;
     w.dq = dq;
+    w.dgi = dgi;
+    w.lni = lni;
     Inst hin{n, ld, 0, Qop};
     HIPCHK(S.ar.get((void **)&w.inst, sizeof(Inst)));
     HIPCHK(hipMemcpyAsync(w.inst, &hin, sizeof(Inst), hipMemcpyHostToDevice, st));
@@ -779,13 +831,13 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     struct Pick8 { int mt; int ks; int est; };
     Pick8 p8m{}, p8a{};
     auto pick8 = [&](int cm, int ca) {
-        int bm = 0, ba = 0;
         p8m.est = std::min({ncol, cm + 16, cm + ca});
         p8a.est = std::min({ncol, ca + 16, cm + ca});
-        digit_layout(p8m.est, 4, ld, &p8m.mt, &bm);
-        digit_layout(p8a.est, 8, ld, &p8a.mt, &ba);
-        p8m.ks = digit_slices(p8m.mt, bm + ba);
-        p8a.ks = digit_slices(p8a.mt, bm + ba);
+        const DigitChoice dc = digit_choice(n, ld, p8m.est, p8a.est);
+        p8m.mt = dc.mt4;
+        p8m.ks = dc.ks4;
+        p8a.mt = dc.mt8;
+        p8a.ks = dc.ks8;
         // sparse products while they cost less than the digit products; the
         // bound takes every live column as a two-half lambda_min column
         const int live = std::min(ncol, cm + ca);
@@ -864,11 +916,29 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         };
         const int8_t *Q8 = (const int8_t *)Qop;
         S.config_key = [&]() {
-            return ((int64_t)p8m.mt | ((int64_t)p8m.ks << 3) | ((int64_t)p8a.mt << 7) | ((int64_t)p8a.ks << 10) |
-                    ((int64_t)p8m.est << 14) | ((int64_t)p8a.est << 34)) * 2 +
+            return ((int64_t)p8m.mt | ((int64_t)p8m.ks << 5) | ((int64_t)p8a.mt << 9) | ((int64_t)p8a.ks << 14) |
+                    ((int64_t)p8m.est << 18) | ((int64_t)p8a.est << 38)) * 2 +
                    (S.sparse_now ? 1 : 0);
         };
         S.repick = [&](int cm, int ca) { pick8(cm, ca); };
+        // a product written by one K slice overwrites its outputs, so the
+        // column kernel clears what it read only when the next product of
+        // that kind adds its slices (K slices > 1); before such a batch the
+        // buffers are cleared here if the previous batch left values in them
+        bool dirty_m = false, dirty_a = false;
+        S.before_batch = [&](hipStream_t s) -> hipError_t {
+            const bool zm = !S.sparse_now && p8m.ks > 1, za = !S.sparse_now && p8a.ks > 1;
+            w.clear_main = zm ? 1 : 0;
+            w.clear_aux = za ? 1 : 0;
+            hipError_t e = hipSuccess;
+            const size_t bytes = (size_t)ld * ncol * sizeof(int64_t);
+            if (zm && dirty_m) e = hipMemsetAsync(w.U, 0, bytes, s);
+            if (e == hipSuccess && za && dirty_a) e = hipMemsetAsync(w.U_aux, 0, bytes, s);
+            if (e == hipSuccess && za && dirty_a) e = hipMemsetAsync(w.U_lo, 0, bytes, s);
+            dirty_m = !zm;
+            dirty_a = !za;
+            return e;
+        };
         // both products in one launch (timed as one launch when timing = 1)
         rs = run_sweeps(
             S, prm, tm, ta, ts, st,
@@ -1149,11 +1219,13 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         rowstart[i + 1] = rowstart[i] + (n[i] + 3) / 4;  // units of 4 rows of the group product
     }
     const int64_t total = off[count];
-    double *bd, *gam, *R, *dq;
+    double *bd, *gam, *R, *dq, *dgi, *lni;
     HIPCHK(S.ar.get((void **)&bd, total * 8));
     HIPCHK(S.ar.get((void **)&gam, total * 8));
     HIPCHK(S.ar.get((void **)&R, total * 8));
     HIPCHK(S.ar.get((void **)&dq, total * 8));
+    HIPCHK(S.ar.get((void **)&dgi, total * 8));
+    HIPCHK(S.ar.get((void **)&lni, total * 8));
     std::vector<Inst> hin(count);
     for (int i = 0; i < count; ++i) {
         void *Qop;
@@ -1161,13 +1233,16 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         const uint64_t seed = seeds ? seeds[i] : prm.seed;
         HIPCHK(launch_prep_q(prm.qx_dtype, Q[i], n[i], ld[i], prm.perturb, sigma_of(i), seed, Qop, R + off[i],
                              dq + off[i], st));
-        HIPCHK(launch_gamma(b[i], R + off[i], dq + off[i], n[i], ld[i], bd + off[i], gam + off[i], st));
+        HIPCHK(launch_gamma(b[i], R + off[i], dq + off[i], n[i], ld[i], bd + off[i], gam + off[i], dgi + off[i],
+                            lni + off[i], st));
         hin[i] = Inst{n[i], ld[i], off[i], Qop};
     }
     w.b = bd;
     w.gam = gam;
     w.R = R;
     w.dq = dq;
+    w.dgi = dgi;
+    w.lni = lni;
     HIPCHK(S.ar.get((void **)&w.inst, count * sizeof(Inst)));
     HIPCHK(hipMemcpyAsync(w.inst, hin.data(), count * sizeof(Inst), hipMemcpyHostToDevice, st));
     if (psdp_status s2 = alloc_columns(S, total, plan_group(count), 1, st)) return s2;
@@ -1347,8 +1422,16 @@ psdp_status qx_int_checks(const int32_t *Q, int64_t n, const double *X, int32_t 
 
 psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits, double *Y,
                            hipStream_t st) {
+    return psdp_qx_digits_ex(Q, n, X, B, digits, 0, 0, 0, nullptr, Y, st);
+}
+
+psdp_status psdp_qx_digits_ex(const int32_t *Q, int64_t n, const double *X, int32_t B, int32_t digits,
+                              int32_t layout, int32_t slices, int32_t reps, double *us, double *Y, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_lock);
     g_err.clear();
+    if (layout != 0 && !digit_layout_valid(layout)) return fail(PSDP_E_INVALID, "layout must be 0, 1, 2, 4, 8 or 16");
+    if (slices < 0 || slices > 8) return fail(PSDP_E_INVALID, "slices must be in [0, 8]");
+    if (reps < 0 || (reps > 0 && !us)) return fail(PSDP_E_INVALID, "reps >= 0, and us given when reps > 0");
     std::vector<int64_t> rownnz;
     if (psdp_status s = qx_int_checks(Q, n, X, B, digits, Y, st, &rownnz)) return s;
     Arena ar;
@@ -1360,9 +1443,9 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     const int64_t ld = plan.ld;
     const int64_t rows = (ld + kDigitRowsAlign - 1) / kDigitRowsAlign * kDigitRowsAlign;
     const int D = digits;
-    int mt = 4, nb = 1;
-    digit_layout(B, digits, ld, &mt, &nb);
-    const int ks = digit_slices(mt, nb);
+    const DigitChoice dc = digit_choice(n, ld, D == 4 ? B : 0, D == 8 ? B : 0);
+    const int mt = layout ? layout : (D == 4 ? dc.mt4 : dc.mt8);
+    const int ks = slices ? slices : (D == 4 ? dc.ks4 : dc.ks8);
     int8_t *Q8, *dig;
     double *R, *dq;
     int64_t *U0, *U1 = nullptr;
@@ -1394,7 +1477,58 @@ psdp_status psdp_qx_digits(const int32_t *Q, int64_t n, const double *X, int32_t
     const DigitJob job{dig, act, cnt, U0, U1, B, ks, mt, B};
     HIPCHK(launch_digit(Q8, ld, n, ld, D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
     HIPCHK(launch_digit_combine(U0, U1, n, ld, B, D, esc, Y, st));
+    if (reps > 0) {
+        // the same product again, reps times between two events (the result
+        // is already in Y; with several K slices these launches add further
+        // parts into the product buffers, which nothing reads afterwards)
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        hipError_t r = hipEventRecord(e0, st);
+        for (int q = 0; q < reps && r == hipSuccess; ++q)
+            r = launch_digit(Q8, ld, n, ld, D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st);
+        if (r == hipSuccess) r = hipEventRecord(e1, st);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(r);
+        *us = (double)ms * 1e3 / reps;
+    }
     HIPCHK(hipStreamSynchronize(st));
+    return PSDP_OK;
+}
+
+psdp_status psdp_set_digit_table(int64_t n, int32_t digits, int32_t count, const int32_t *max_cols,
+                                 const int32_t *layout, const int32_t *slices) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    if (n < 1 || n > 65536) return fail(PSDP_E_INVALID, "n must be in [1, 65536]");
+    if (digits != 4 && digits != 8) return fail(PSDP_E_INVALID, "digits must be 4 or 8");
+    if (count < 0 || (count > 0 && (!max_cols || !layout || !slices))) return fail(PSDP_E_INVALID, "entries");
+    std::vector<DigitTableEntry> t;
+    for (int32_t q = 0; q < count; ++q) {
+        if (max_cols[q] < 1 || (q > 0 && max_cols[q] <= max_cols[q - 1]))
+            return fail(PSDP_E_INVALID, "max_cols must be positive and increasing");
+        if (!digit_layout_valid(layout[q])) return fail(PSDP_E_INVALID, "layout must be 1, 2, 4, 8 or 16");
+        if (slices[q] < 1 || slices[q] > 8) return fail(PSDP_E_INVALID, "slices must be in [1, 8]");
+        t.push_back(DigitTableEntry{max_cols[q], layout[q], slices[q]});
+    }
+    if (t.empty()) g_digit_tables.erase({n, digits});
+    else g_digit_tables[{n, digits}] = t;
+    return PSDP_OK;
+}
+
+psdp_status psdp_digit_choice(int64_t n, int32_t est4, int32_t est8, int32_t *choice) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    if (n < 1 || n > 65536 || est4 < 0 || est8 < 0 || !choice) return fail(PSDP_E_INVALID, "arguments");
+    const DigitChoice c = digit_choice(n, (n + 63) / 64 * 64, est4, est8);
+    choice[0] = c.mt4;
+    choice[1] = c.ks4;
+    choice[2] = c.mt8;
+    choice[3] = c.ks8;
     return PSDP_OK;
 }
 

@@ -14,7 +14,7 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 

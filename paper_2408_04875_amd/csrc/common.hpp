@@ -76,15 +76,16 @@ struct Work {
     int64_t slice;       // elements per U slice
     Inst *inst;
     Col *col;
-    // instance vectors
-    double *b, *gam, *R, *dq;
+    // instance vectors; dgi = Q_ii + gamma_i and lni = b_i - gamma_i, so that
+    // a column's diagonal of Q_r - Diag p is dgi_i - p_i and its linear term
+    // b_r + p is lni_i + p_i (the instance vectors are shared by all the
+    // columns of an instance and stay in the caches)
+    double *b, *gam, *R, *dq, *dgi, *lni;
     // column vectors
     double *x, *xp, *g, *gp, *p, *v, *Av, *P, *AP, *w;
-    // per-column terms that change only with p or between subproblems:
-    // diag = (Q_ii + gamma_i) - p_i and lin = (b_i - gamma_i) + p_i (written
-    // at set-up and by every penalty update), zx = x_i - x_i^2 (written at
-    // every outer-loop head, constant while lambda_min runs)
-    double *diag, *lin, *zx;
+    // zx = x_i - x_i^2 (written at every outer-loop head, constant while
+    // lambda_min runs)
+    double *zx;
     void *op;            // operand buffer (OpT), column layout as the vectors
     void *U;             // Q.X output (UT): ksplit slices; the integer path keeps one
                          // int64 buffer that its K slices add into
@@ -105,6 +106,12 @@ struct Work {
     // ([ncol + 1][8][ld]); U holds int64 slices, U_aux the high halves and
     // U_lo the low halves of the 8-digit products
     int32_t i8;
+    // integer path: whether the column kernel clears the int64 product
+    // values it reads (the next product of that kind adds K slices into
+    // them); a product written by a single slice overwrites its outputs, and
+    // the host clears the buffers itself before a batch whose product adds
+    // onto values left by a batch that did not clear them
+    int32_t clear_main, clear_aux;
     int8_t *dig;
     int8_t *dig_aux;
     int64_t *U_lo;
@@ -426,130 +433,5 @@ __device__ __forceinline__ void block_max(double (&v)[N], double *scratch) {
 // Sets the thread-local detail returned by psdp_last_error (an empty string
 // for msg = nullptr) and returns s.
 psdp_status set_error(psdp_status s, const char *msg);
-
-// ---------------------------------------------------------------------------
-// Host-side launchers implemented in the kernel translation units.
-
-// Device-side input checks (check.hip): the first asymmetric entry as
-// i n + j (all ones when Q is symmetric), the largest |Q_ij|, off-diagonal
-// |Q_ij| and |b_i|, and the counts of X0 entries outside [0,1] and of
-// non-finite p0 entries. rownnz (nullable, zeroed beforehand) gets the
-// off-diagonal nonzeros of every row.
-// Real (FP64) data: the magnitudes are bit patterns of non-negative doubles;
-// nonfinite counts NaN/Inf entries of Q and b; nonint_off, non32_off and
-// non16_off count the off-diagonal entries of Q that are not integers in
-// [-127, 127], not floats, not bfloat16 values (zero for integer data).
-struct CheckOut {
-    uint64_t qmax, offmax, bmax, x0_bad, p0_bad, first_asym;
-    uint64_t nonfinite, nonint_off, non32_off, non16_off;
-};
-hipError_t launch_check(const int32_t *Q, const int32_t *b, int64_t n, const double *X0, int64_t nx,
-                        const double *p0, CheckOut *o, int32_t *rownnz, hipStream_t st);
-hipError_t launch_check(const double *Q, const double *b, int64_t n, const double *X0, int64_t nx,
-                        const double *p0, CheckOut *o, int32_t *rownnz, hipStream_t st);
-hipError_t launch_prep_q(int dtype, const int32_t *Q, int64_t n, int64_t ld, int perturb,
-                         double sigma, uint64_t seed, void *Qop, double *R, double *dq,
-                         hipStream_t st);
-hipError_t launch_prep_q(int dtype, const double *Q, int64_t n, int64_t ld, int perturb,
-                         double sigma, uint64_t seed, void *Qop, double *R, double *dq,
-                         hipStream_t st);
-hipError_t launch_gamma(const int32_t *b, const double *R, const double *dq, int64_t n, int64_t ld,
-                        double *bd, double *gam, hipStream_t st);
-hipError_t launch_gamma(const double *b, const double *R, const double *dq, int64_t n, int64_t ld,
-                        double *bd, double *gam, hipStream_t st);
-hipError_t launch_perturbation(int64_t n, double sigma, uint64_t seed, int mode, double *mu,
-                               hipStream_t st);
-hipError_t launch_round_objective(const int32_t *Q, const int32_t *b, int64_t n,
-                                  const double *X, int64_t ldx, int64_t B, uint8_t *xhat,
-                                  int64_t ldh, int64_t *obj, int64_t *partial, hipStream_t st);
-// Real data: obj_c is the exact sum of the selected Q_ij and b_i rounded once
-// to FP64 (nearest, ties to even). acc: B * kObjAccWords int64 words of
-// scratch, zero on entry (left zero on return).
-constexpr int64_t kObjAccWords = 2 * 2048;
-hipError_t launch_round_objective(const double *Q, const double *b, int64_t n,
-                                  const double *X, int64_t ldx, int64_t B, uint8_t *xhat,
-                                  int64_t ldh, double *obj, int64_t *acc, hipStream_t st);
-
-// GEMM operand mode: FP32-stored Q (exact) widened to FP64, FP64 operands.
-constexpr int kGemmF32QF64 = 16;
-
-// Q.X products. U receives sum_j Qop[i][j] * op[j] for every live column.
-hipError_t launch_gemv(int dtype, const Inst *inst_host, int ninst_same, const Work &w,
-                       int ncol_max, hipStream_t st);
-hipError_t launch_gemv_group(int dtype, const Work &w, const int64_t *rowstart, const int32_t *unitcol,
-                             int64_t total_rows, hipStream_t st);
-hipError_t launch_stream(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
-                         const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
-                         int ncol, int nt, hipStream_t st);
-hipError_t launch_stream2(const void *Qop, int64_t ld, const void *op1, void *U1, const int32_t *active1,
-                          const int32_t *nactive1, int64_t slice1, int ks1, int nt1, const void *op2,
-                          void *U2, const int32_t *active2, const int32_t *nactive2, int64_t slice2,
-                          int ks2, int nt2, int ncol1, int ncol2, hipStream_t st);
-hipError_t launch_gemm(int dtype, const void *Qop, int64_t ld, const void *op, void *U,
-                       const int32_t *active, const int32_t *nactive, int64_t slice, int ksplit,
-                       int ncol_max, hipStream_t st);
-
-// Exact integer products: U[c][i] = sum_k Q8[i][k] T[c][k], where T is a
-// column's value in base-128 digits (4 digits, or 8 digits whose two 4-digit
-// halves go to U0 and U1). With ks > 1 the K slices add their parts with
-// atomic adds, so the live columns' outputs must be zero beforehand; with
-// ks = 1 they are overwritten.
-struct DigitJob {
-    const int8_t *dig;       // digit planes [ncol + 1][D][ldq]; column ncol is zero
-    const int32_t *active;   // live column list and its device count
-    const int32_t *nactive;
-    int64_t *U0, *U1;        // outputs: column stride ldu
-    int zero_col;            // index of the all-zero column
-    int ks;                  // K slices (1..8)
-    int mt;                  // block layout: 1 few columns, 2 middle, 4 many (digit_layout)
-    int est;                 // live count the grid is sized for (0: no launch)
-};
-constexpr int kDigitRowsAlign = 256;  // Q8 rows are allocated up to a multiple of this
-// Layout (DigitJob.mt) and base block count (one K slice) of a product sized
-// for est columns of D digits; digit_slices then spreads the K range of both
-// products of a sweep over enough blocks in total.
-void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks);
-int digit_slices(int mt, int blocks_total);
-hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob *main4,
-                        const DigitJob *aux8, hipStream_t st);
-hipError_t launch_digits_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int8_t *dig,
-                                      int64_t ldq, int32_t *escale, hipStream_t st);
-hipError_t launch_digit_combine(const int64_t *U0, const int64_t *U1, int64_t n, int64_t ldu, int B, int D,
-                                const int32_t *escale, double *Y, hipStream_t st);
-
-// Exact integer products from the compressed sparse rows of Q_off (sparse.hip):
-// the same integers as the digit products, read from int32 operand words.
-struct SparseJob {
-    int on;                  // 0: not launched
-    const int32_t *rowptr;   // n + 1 row starts
-    const uint32_t *pk;      // packed nonzeros: column in bits 0-15, int8 value in bits 16-23
-    int64_t n;
-    const int32_t *w0, *w1;  // operand words: T, or T_hi and T_lo; column c at c * ldw, zero_col + 1 columns
-    int64_t ldw;
-    const int32_t *active;   // live list (zero_col + 1 readable entries) and its device count
-    const int32_t *nactive;
-    int zero_col;            // an all-zero operand column
-    int64_t *U0, *U1;        // outputs (U1 for the low half), column c at c * ldu
-    int64_t ldu;
-};
-hipError_t launch_csr_fill(const int8_t *Q8, int64_t ldq, int64_t n, const int32_t *rowptr, uint32_t *pk,
-                           hipStream_t st);
-hipError_t launch_sparse(const SparseJob *main4, const SparseJob *aux8, hipStream_t st);
-hipError_t launch_words_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int32_t *w0,
-                                     int32_t *w1, int64_t ldw, int32_t *escale, hipStream_t st);
-
-// Solver kernels.
-hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,
-                              hipStream_t st);
-hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax, hipStream_t st);
-hipError_t launch_compact(const Work &w, hipStream_t st);
-
-// Evaluation and adjoint.
-hipError_t launch_eval(int dtype, int vtype, const void *Q, int64_t ldq, const void *b,
-                       const void *p, const void *X, int64_t n, int64_t B, void *h, void *G,
-                       double *ws, hipStream_t st);
-hipError_t launch_adjoint(int dtype, int vtype, const void *X, const void *G, const void *w,
-                          int64_t n, int64_t B, void *dX, void *dQ, void *db, void *dp,
-                          hipStream_t st);
 
 }  // namespace psdp

@@ -7,7 +7,7 @@
 // adjoint: for L = sum_c w_c h(x_c, p) (h linear in Q, b, p):
 //          dX = G Diag(w), dQ = X Diag(w) X^T (MFMA, operands read straight
 //          from the columns of X), db = X w, dp = (X - X o X) w.
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 

@@ -11,7 +11,7 @@
 #include <map>
 #include <mutex>
 
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 namespace {

@@ -10,7 +10,7 @@
 //  - round_objective: x^_i = [x_i > 1/2] and f(x^) = x^T Q x^ + b^T x^ on the
 //    original data (Section 2, eq. (bqp)): exact integer arithmetic for
 //    integer data, the exact sum rounded once to FP64 for real data.
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 
@@ -323,34 +323,41 @@ hipError_t launch_prep_q(int dtype, const double *Q, int64_t n, int64_t ld, int 
     return prep_typed<double>(dtype, Q, n, ld, perturb, sigma, seed, Qop, R, dq, st);
 }
 
-// gamma_i = 2 sum_j |Q~_ij| + |b_i| + 1 (Section 3.5, strict margin 1) and b
-// as FP64, zero in the padding up to ld.
+// gamma_i = 2 sum_j |Q~_ij| + |b_i| + 1 (Section 3.5, strict margin 1), b
+// as FP64, and the reformulated data's diagonal dgi_i = Q~_ii + gamma_i and
+// linear term lni_i = b_i - gamma_i (Algorithm 3, reformation); zero in the
+// padding up to ld.
 template <typename BT>
 __global__ void gamma_kernel(const BT *b, const double *R, const double *dq, int64_t n, int64_t ld, double *bd,
-                             double *gam) {
+                             double *gam, double *dgi, double *lni) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ld) return;
     if (i < n) {
         const double bi = (double)b[i];
+        const double g = 2.0 * (R[i] + fabs(dq[i])) + fabs(bi) + 1.0;
         bd[i] = bi;
-        gam[i] = 2.0 * (R[i] + fabs(dq[i])) + fabs(bi) + 1.0;
+        gam[i] = g;
+        dgi[i] = dq[i] + g;
+        lni[i] = bi - g;
     } else {
         bd[i] = 0.0;
         gam[i] = 0.0;
+        dgi[i] = 0.0;
+        lni[i] = 0.0;
     }
 }
 
 hipError_t launch_gamma(const int32_t *b, const double *R, const double *dq, int64_t n, int64_t ld,
-                        double *bd, double *gam, hipStream_t st) {
+                        double *bd, double *gam, double *dgi, double *lni, hipStream_t st) {
     hipLaunchKernelGGL(gamma_kernel<int32_t>, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, st, b, R, dq, n,
-                       ld, bd, gam);
+                       ld, bd, gam, dgi, lni);
     return hipGetLastError();
 }
 
 hipError_t launch_gamma(const double *b, const double *R, const double *dq, int64_t n, int64_t ld,
-                        double *bd, double *gam, hipStream_t st) {
+                        double *bd, double *gam, double *dgi, double *lni, hipStream_t st) {
     hipLaunchKernelGGL(gamma_kernel<double>, dim3((unsigned)((ld + 255) / 256)), dim3(256), 0, st, b, R, dq, n,
-                       ld, bd, gam);
+                       ld, bd, gam, dgi, lni);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@
 //                     separate output slices that the solver sums in order.
 #include <algorithm>
 
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 

@@ -34,7 +34,7 @@
 // column groups, so the estimate changes only the speed.
 #include <algorithm>
 
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 
@@ -248,8 +248,8 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
 // pieces and Q rows of the next four K steps are in flight in registers
 // while the current step multiplies. MT must be a multiple of 4 (each thread
 // copies MT / 4 pieces of 16 bytes per step).
-template <int MT, int NT> struct DigitLdsShape {
-    static constexpr int kMT = MT, kNT = NT, kWR = 4;
+template <int MT, int NT, int PF = 4> struct DigitLdsShape {
+    static constexpr int kMT = MT, kNT = NT, kWR = 4, kPF = PF;
     static constexpr int kRows = 4 * 16 * NT;
 };
 
@@ -314,7 +314,7 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
             // issued while step s multiplies, and a step's digit pieces go to
             // LDS (double buffer, one barrier per step) only when the step
             // comes up. Loads past the last step reread it (in bounds).
-            constexpr int PF = 4;
+            constexpr int PF = S::kPF;
             const int nst = (int)((ke - kb) / 64);
             intx4 ra[PF][PC], rb[PF][NT];
             auto issue = [&](intx4 (&xa)[PC], intx4 (&xb)[NT], int s) {
@@ -385,22 +385,47 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
 
 typedef DigitLdsShape<4, 1> DigitMid;
 typedef DigitLdsShape<8, 2> DigitMany;
+// Wider tiles for the widest products: 256 rows of Q per block (64 per
+// wave, twice the operand reuse of each digit fragment read from LDS), or
+// 256 digit rows per block (twice the reuse of each Q row). Their
+// accumulators and register rings leave room for one block per CU.
+typedef DigitLdsShape<8, 4> DigitWide;
+typedef DigitLdsShape<16, 2> DigitTall;
 
-// DigitJob.mt codes of the three layouts
-constexpr int kLayoutFew = 1, kLayoutMid = 2, kLayoutMany = 4;
+// DigitJob.mt codes of the layouts
+constexpr int kLayoutFew = 1, kLayoutMid = 2, kLayoutMany = 4, kLayoutWide = 8, kLayoutTall = 16;
+
+bool digit_layout_valid(int mt) {
+    return mt == kLayoutFew || mt == kLayoutMid || mt == kLayoutMany || mt == kLayoutWide || mt == kLayoutTall;
+}
+
+// Calls f with a value of the shape type of layout code mt.
+template <typename F> static void with_layout(int mt, F &&f) {
+    switch (mt) {
+        case kLayoutMid: f(DigitMid{}); break;
+        case kLayoutMany: f(DigitMany{}); break;
+        case kLayoutWide: f(DigitWide{}); break;
+        case kLayoutTall: f(DigitTall{}); break;
+        default: f(DigitFew{}); break;
+    }
+}
 static int layout_ca(int mt, int D) {
-    return 16 * (mt <= kLayoutFew ? DigitFew::kMT : mt == kLayoutMid ? DigitMid::kMT : DigitMany::kMT) / D;
+    int ca = 0;
+    with_layout(mt, [&](auto s) { ca = 16 * decltype(s)::kMT / D; });
+    return ca;
 }
 static int layout_rows(int mt) {
-    return mt <= kLayoutFew ? DigitFew::kRows : mt == kLayoutMid ? DigitMid::kRows : DigitMany::kRows;
+    int rows = 0;
+    with_layout(mt, [&](auto s) { rows = decltype(s)::kRows; });
+    return rows;
 }
 
 template <int D, typename S> struct DigitBody {
     static __device__ __forceinline__ void run(const DigitArgs &da, int L) { digit_body<D, S>(da, L); }
 };
-template <int D, int MT, int NT> struct DigitBody<D, DigitLdsShape<MT, NT>> {
+template <int D, int MT, int NT, int PF> struct DigitBody<D, DigitLdsShape<MT, NT, PF>> {
     static __device__ __forceinline__ void run(const DigitArgs &da, int L) {
-        digit_body_lds<D, DigitLdsShape<MT, NT>>(da, L);
+        digit_body_lds<D, DigitLdsShape<MT, NT, PF>>(da, L);
     }
 };
 
@@ -408,13 +433,21 @@ template <int D, int MT, int NT> struct DigitBody<D, DigitLdsShape<MT, NT>> {
 // nb is a multiple of 8, so this is a bijection of [0, nb).
 __device__ __forceinline__ int xcd_order(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
+// Blocks per CU the register budget is set for: two for the smaller tiles
+// (at most 256 registers per lane; the many-column layout otherwise takes
+// 312 with its accumulators and runs one wave per SIMD, and whole n = 2500
+// solves are 3% faster with two), one for the widest tiles.
+template <typename S> struct DigitMinBlocks { static constexpr int value = 2; };
+template <> struct DigitMinBlocks<DigitWide> { static constexpr int value = 1; };
+template <> struct DigitMinBlocks<DigitTall> { static constexpr int value = 1; };
+template <typename S1, typename S2> constexpr int kDigitMinBlocks =
+    DigitMinBlocks<S1>::value < DigitMinBlocks<S2>::value ? DigitMinBlocks<S1>::value : DigitMinBlocks<S2>::value;
+
 // The 4-digit product (subproblem columns) in the first nb1 blocks, the
-// 8-digit product (lambda_min / CG columns) in the next nb2. At most 256
-// registers per lane, so that two blocks share a CU (the many-column layout
-// otherwise takes 312 with the accumulators and runs one wave per SIMD;
-// whole n = 2500 solves are 3% faster with two).
+// 8-digit product (lambda_min / CG columns) in the next nb2.
 template <typename S1, typename S2>
-__global__ void __launch_bounds__(kBlock, 2) digit_kernel(DigitArgs a, DigitArgs b, int nb1, int nb2) {
+__global__ void __launch_bounds__(kBlock, (kDigitMinBlocks<S1, S2>)) digit_kernel(DigitArgs a, DigitArgs b, int nb1,
+                                                                                  int nb2) {
     const int bx = blockIdx.x;
     if (bx < nb1) DigitBody<4, S1>::run(a, xcd_order(bx, nb1));
     else DigitBody<8, S2>::run(b, xcd_order(bx - nb1, nb2));
@@ -455,9 +488,13 @@ static DigitArgs digit_args(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t
 // few-column launches for 10-20 columns took 11-16 us.
 void digit_layout(int est, int D, int64_t ldq, int *mt, int *blocks) {
     *mt = est <= 8 ? kLayoutFew : est <= 64 ? kLayoutMid : kLayoutMany;
-    const int CA = layout_ca(*mt, D);
-    const int rows = layout_rows(*mt);
-    *blocks = std::max(1, (est + CA - 1) / CA) * (int)((ldq + rows - 1) / rows);
+    *blocks = digit_blocks(*mt, est, D, ldq);
+}
+
+int digit_blocks(int mt, int est, int D, int64_t ldq) {
+    const int CA = layout_ca(mt, D);
+    const int rows = layout_rows(mt);
+    return std::max(1, (est + CA - 1) / CA) * (int)((ldq + rows - 1) / rows);
 }
 
 // Measured on gfx950 over whole n = 2500 solves: the many-column layout does
@@ -477,13 +514,6 @@ static void digit_go(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, h
     hipLaunchKernelGGL((digit_kernel<S1, S2>), dim3((unsigned)(nb1 + nb2)), dim3(kBlock), 0, st, a, b, nb1, nb2);
 }
 
-template <typename S1>
-static void digit_go2(const DigitArgs &a, const DigitArgs &b, int nb1, int nb2, int l2, hipStream_t st) {
-    if (l2 == kLayoutFew) digit_go<S1, DigitFew>(a, b, nb1, nb2, st);
-    else if (l2 == kLayoutMid) digit_go<S1, DigitMid>(a, b, nb1, nb2, st);
-    else digit_go<S1, DigitMany>(a, b, nb1, nb2, st);
-}
-
 // Either job may be null or have est = 0 (then it is not launched). Rows of
 // Q8 up to a multiple of kDigitRowsAlign must exist (zero past ldq).
 hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu, const DigitJob *main4,
@@ -492,17 +522,19 @@ hipError_t launch_digit(const int8_t *Q8, int64_t ldq, int64_t nrow, int64_t ldu
     DigitArgs a{}, b{};
     int nb1 = 0, nb2 = 0, l1 = kLayoutFew, l2 = kLayoutFew;
     if (main4 && main4->est > 0) {
+        if (!digit_layout_valid(main4->mt)) return hipErrorInvalidValue;
         a = digit_args(Q8, ldq, nrow, ldu, *main4, 4, &nb1);
-        l1 = main4->mt <= kLayoutFew ? kLayoutFew : main4->mt == kLayoutMid ? kLayoutMid : kLayoutMany;
+        l1 = main4->mt;
     }
     if (aux8 && aux8->est > 0) {
+        if (!digit_layout_valid(aux8->mt)) return hipErrorInvalidValue;
         b = digit_args(Q8, ldq, nrow, ldu, *aux8, 8, &nb2);
-        l2 = aux8->mt <= kLayoutFew ? kLayoutFew : aux8->mt == kLayoutMid ? kLayoutMid : kLayoutMany;
+        l2 = aux8->mt;
     }
     if (nb1 + nb2 == 0) return hipSuccess;
-    if (l1 == kLayoutFew) digit_go2<DigitFew>(a, b, nb1, nb2, l2, st);
-    else if (l1 == kLayoutMid) digit_go2<DigitMid>(a, b, nb1, nb2, l2, st);
-    else digit_go2<DigitMany>(a, b, nb1, nb2, l2, st);
+    with_layout(l1, [&](auto s1) {
+        with_layout(l2, [&](auto s2) { digit_go<decltype(s1), decltype(s2)>(a, b, nb1, nb2, st); });
+    });
     return hipGetLastError();
 }
 

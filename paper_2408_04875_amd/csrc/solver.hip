@@ -22,7 +22,7 @@
 // live-column lists of the next sweep.
 #include <type_traits>
 
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 
@@ -93,7 +93,8 @@ template <typename OpT> constexpr bool kDigits = std::is_same<OpT, int8_t>::valu
 // The products of one chunk (elements ix[j]) for a subproblem column: every
 // slice's loads for all elements issue together. Integer path: Q x_q on the
 // grid 2^-27, exact, in one buffer that the product's K slices add into;
-// each real element is cleared once read, for the next product.
+// each real element is cleared once read when the next product adds into
+// it (w.clear_main).
 template <typename UT, int EPT>
 __device__ __forceinline__ void uval_chunk(const Work &w, const ColView &cv, const uint32_t (&ix)[EPT],
                                            const bool (&ok)[EPT], double (&u)[EPT]) {
@@ -101,7 +102,9 @@ __device__ __forceinline__ void uval_chunk(const Work &w, const ColView &cv, con
         const UVec<int64_t> U = uvec((int64_t *)w.U, cv.off);
         int64_t s[EPT];
         FOR_J s[_j] = U[ix[_j]];
-        FOR_J if (ok[_j]) U[ix[_j]] = 0;
+        if (w.clear_main) {
+            FOR_J if (ok[_j]) U[ix[_j]] = 0;
+        }
         FOR_J u[_j] = (double)s[_j] / kMainScale;
     } else {
         const UVec<const UT> U = uvec((const UT *)w.U, cv.off);
@@ -115,7 +118,7 @@ __device__ __forceinline__ void uval_chunk(const Work &w, const ColView &cv, con
 
 // The same for a lambda_min / CG column (FP64 buffers when precision is
 // split; on the integer path the two int64 halves of the 8-digit product,
-// scaled by 2^escale).
+// scaled by 2^escale, cleared once read when w.clear_aux is set).
 template <typename UT, int EPT>
 __device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const ColView &cv,
                                            const uint32_t (&ix)[EPT], const bool (&ok)[EPT], double (&u)[EPT]) {
@@ -126,9 +129,11 @@ __device__ __forceinline__ void uaux_chunk(const Work &w, const Col &c, const Co
             hi[_j] = H[ix[_j]];
             lo[_j] = L[ix[_j]];
         }
-        FOR_J if (ok[_j]) {
-            H[ix[_j]] = 0;
-            L[ix[_j]] = 0;
+        if (w.clear_aux) {
+            FOR_J if (ok[_j]) {
+                H[ix[_j]] = 0;
+                L[ix[_j]] = 0;
+            }
         }
         const int e = uni(c.escale);
         FOR_J u[_j] = digits8_value(hi[_j], lo[_j], e);
@@ -225,6 +230,13 @@ __device__ __forceinline__ void aux_digits(const Work &w, Col &c, const ColView 
 
 __device__ __forceinline__ bool interior(double x) { return x > 0.0 && x < 1.0; }
 
+// The diagonal of Q_r - Diag p for one column, (Q_ii + gamma_i) - p_i, read
+// as dg[i] from the instance vector dgi and the column's penalty.
+struct DiagView {
+    UVec<const double> dgi, p;
+    __device__ __forceinline__ double operator[](uint32_t i) const { return dgi[i] - p[i]; }
+};
+
 template <int N> __device__ __forceinline__ void bsum(double (&v)[N], double *red) {
     block_sum<N, kSB>(v, red);
 }
@@ -241,19 +253,25 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
 template <typename OpT, int EPT>
 __device__ void outer_begin(const Work &w, Col &c, const ColView &cv, double *red) {
     const uint32_t n = cv.n;
-    const UVec<const double> x = uvec((const double *)w.x, cv.off), dg = uvec((const double *)w.diag, cv.off);
-    const UVec<const double> ln = uvec((const double *)w.lin, cv.off), R = uvec((const double *)w.R, cv.io);
+    const UVec<const double> x = uvec((const double *)w.x, cv.off), pp = uvec((const double *)w.p, cv.off);
+    const UVec<const double> dgi = uvec((const double *)w.dgi, cv.io), lni = uvec((const double *)w.lni, cv.io);
+    const UVec<const double> R = uvec((const double *)w.R, cv.io);
     double mx[4] = {0.0, 0.0, 0.0, 0.0};  // binary gap, pinned-at-half flag, row term, |b_r + p|
     double sm[2] = {0.0, 0.0};            // sum of z over I, |I|
     CHUNKS(n) {
         CHUNK_INDEX(n)
-        double xv[EPT], Av[EPT], Rv[EPT], bv[EPT];
+        double xv[EPT], pv[EPT], Av[EPT], Rv[EPT], bv[EPT];
         FOR_J {
             const uint32_t i = ix[_j];
             xv[_j] = x[i];
-            Av[_j] = dg[i];
+            pv[_j] = pp[i];
+            Av[_j] = dgi[i];
             Rv[_j] = R[i];
-            bv[_j] = ln[i];
+            bv[_j] = lni[i];
+        }
+        FOR_J {
+            Av[_j] = Av[_j] - pv[_j];
+            bv[_j] = bv[_j] + pv[_j];
         }
         FOR_J {
             if (!ok[_j]) continue;
@@ -325,9 +343,9 @@ template <typename OpT, int EPT>
 __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red, double lam) {
     const uint32_t n = cv.n;
     const UVec<const double> x = uvec((const double *)w.x, cv.off);
-    const UVec<double> p = uvec(w.p, cv.off), dgo = uvec(w.diag, cv.off), lno = uvec(w.lin, cv.off);
-    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
-    const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
+    const UVec<double> p = uvec(w.p, cv.off);
+    const UVec<const double> dgi = uvec((const double *)w.dgi, cv.io), lni = uvec((const double *)w.lni, cv.io);
+    const UVec<const double> R = uvec((const double *)w.R, cv.io);
     double alpha = w.eta * fmax(lam, w.lambda_floor_rel * c.rho_outer);
     if (w.alpha_in && c.s < w.alpha_cap) alpha = w.alpha_in[(int64_t)uni(c.start) * w.alpha_cap + uni(c.s)];
     double mx[2] = {0.0, 0.0};
@@ -338,9 +356,9 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
             const uint32_t i = ix[_j];
             xv[_j] = x[i];
             pv[_j] = p[i];
-            dg[_j] = dq[i] + gam[i];
+            dg[_j] = dgi[i];
             Rv[_j] = R[i];
-            bg[_j] = b[i] - gam[i];
+            bg[_j] = lni[i];
         }
         FOR_J {
             if (!ok[_j]) continue;
@@ -352,8 +370,6 @@ __device__ void eig_finish(const Work &w, Col &c, const ColView &cv, double *red
                 p[i] = pi;
             }
             const double A = dg[_j] - pi, lb = bg[_j] + pi;
-            dgo[i] = A;
-            lno[i] = lb;
             mx[0] = fmax(mx[0], 2.0 * (Rv[_j] + fabs(A)));
             mx[1] = fmax(mx[1], fabs(lb));
             put_main<OpT>(w, c, cv, i, xi);
@@ -404,7 +420,7 @@ __device__ bool inner_step(const Work &w, Col &c, const ColView &cv, double *red
     const UVec<double> x = uvec(w.x, cv.off), xp = uvec(w.xp, cv.off), g = uvec(w.g, cv.off), gp = uvec(w.gp, cv.off);
     const UVec<const double> p = uvec((const double *)w.p, cv.off), gam = uvec((const double *)w.gam, cv.io);
     const UVec<const double> R = uvec((const double *)w.R, cv.io), dq = uvec((const double *)w.dq, cv.io);
-    const UVec<const double> dg = uvec((const double *)w.diag, cv.off), ln = uvec((const double *)w.lin, cv.off);
+    const UVec<const double> dgi = uvec((const double *)w.dgi, cv.io), lni = uvec((const double *)w.lni, cv.io);
     const int k = c.k;
     double mx[2] = {0.0, 0.0};       // cret, any nonzero step component
     // s's, s'y, y'y of eq. (bb1) as double-double sums (high parts sm, low
@@ -414,16 +430,21 @@ __device__ bool inner_step(const Work &w, Col &c, const ColView &cv, double *red
     double xr[EPT], gr[EPT];         // register copies when one pass covers the column
     CHUNKS(n) {
         CHUNK_INDEX(n)
-        double xv[EPT], Av[EPT], bv[EPT], xpv[EPT], gpv[EPT], u[EPT];
+        double xv[EPT], pv[EPT], Av[EPT], bv[EPT], xpv[EPT], gpv[EPT], u[EPT];
         FOR_J {
             const uint32_t i = ix[_j];
             xv[_j] = x[i];
-            Av[_j] = dg[i];
-            bv[_j] = ln[i];
+            pv[_j] = p[i];
+            Av[_j] = dgi[i];
+            bv[_j] = lni[i];
             xpv[_j] = xp[i];  // stale but unused when k == 0
             gpv[_j] = gp[i];
         }
         uval_chunk<UT, EPT>(w, cv, ix, ok, u);
+        FOR_J {
+            Av[_j] = Av[_j] - pv[_j];  // diagonal of Q_r - Diag p
+            bv[_j] = bv[_j] + pv[_j];  // b_r + p
+        }
         FOR_J {
             const double xi = xv[_j];
             const double gi = 2.0 * (u[_j] + Av[_j] * xi) + bv[_j];
@@ -678,7 +699,8 @@ __device__ __forceinline__ void rayleigh_ritz(const double *sm, bool hasP, doubl
 template <typename OpT, typename UT, int EPT>
 __device__ void eig0_step(const Work &w, Col &c, const ColView &cv, double *red) {
     const uint32_t n = cv.n;
-    const UVec<const double> zx = uvec((const double *)w.zx, cv.off), dg = uvec((const double *)w.diag, cv.off);
+    const UVec<const double> zx = uvec((const double *)w.zx, cv.off);
+    const DiagView dg{uvec((const double *)w.dgi, cv.io), uvec((const double *)w.p, cv.off)};
     const UVec<double> v = uvec(w.v, cv.off), Av = uvec(w.Av, cv.off), wv = uvec(w.w, cv.off);
     double sm[2] = {0.0, 0.0};  // v'Av, v'Zv
     CHUNKS(n) {
@@ -770,7 +792,8 @@ __device__ void eig_step(const Work &w, Col &c, const ColView &cv, double *red) 
     constexpr int NS = EigCache<EPT, CM>::kSlots;
     __shared__ double lc[CM == 2 ? 6 : 1][NS];  // v, w, Aw, Av, P, AP
     const uint32_t n = cv.n;
-    const UVec<const double> zx = uvec((const double *)w.zx, cv.off), dg = uvec((const double *)w.diag, cv.off);
+    const UVec<const double> zx = uvec((const double *)w.zx, cv.off);
+    const DiagView dg{uvec((const double *)w.dgi, cv.io), uvec((const double *)w.p, cv.off)};
     const UVec<double> v = uvec(w.v, cv.off), Av = uvec(w.Av, cv.off), P = uvec(w.P, cv.off), AP = uvec(w.AP, cv.off);
     const UVec<double> wv = uvec(w.w, cv.off), Aw = uvec(w.g, cv.off);  // g is free during lambda_min
     const bool hasP = c.hasP != 0;
@@ -1108,9 +1131,6 @@ __device__ bool next_start(const Work &w, Col &c, const ColView &cv) {
     __shared__ int32_t nxt;
     const uint32_t n = cv.n;
     const UVec<double> x = uvec(w.x, cv.off), p = uvec(w.p, cv.off);
-    const UVec<double> dg = uvec(w.diag, cv.off), ln = uvec(w.lin, cv.off);
-    const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
-    const UVec<const double> dq = uvec((const double *)w.dq, cv.io);
     double *xf = w.xfin + (int64_t)uni(c.start) * n;
     FOR_I(n) xf[i] = x[i];
     __syncthreads();
@@ -1124,10 +1144,7 @@ __device__ bool next_start(const Work &w, Col &c, const ColView &cv) {
     const double *x0 = w.X0 + (int64_t)s2 * n;
     FOR_I(n) {
         x[i] = x0[i];
-        const double pi = w.p0 ? w.p0[i] : 0.0;
-        p[i] = pi;
-        dg[i] = (dq[i] + gam[i]) - pi;
-        ln[i] = (b[i] - gam[i]) + pi;
+        p[i] = w.p0 ? w.p0[i] : 0.0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1225,14 +1242,7 @@ __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *
     const uint32_t n = cv.n;
     const UVec<double> x = uvec(w.x, cv.off);
     const UVec<const double> b = uvec((const double *)w.b, cv.io), gam = uvec((const double *)w.gam, cv.io);
-    const UVec<const double> dq = uvec((const double *)w.dq, cv.io), p = uvec((const double *)w.p, cv.off);
-    {  // the terms of the initial penalty (the same operations as the penalty update)
-        const UVec<double> dg = uvec(w.diag, cv.off), ln = uvec(w.lin, cv.off);
-        FOR_I(n) {
-            dg[i] = (dq[i] + gam[i]) - p[i];
-            ln[i] = (b[i] - gam[i]) + p[i];
-        }
-    }
+    const UVec<const double> dq = uvec((const double *)w.dq, cv.io);
     if (!use_cg) {
         FOR_I(n) x[i] = X0[(int64_t)c.start * n + i];
         __syncthreads();

@@ -15,7 +15,7 @@
 // One wave per row: lanes stride over the row's nonzeros, each lane keeps
 // int64 partial sums for a group of columns, and the wave adds them with
 // lane exchanges; lane 0 stores the result.
-#include "common.hpp"
+#include "launch.hpp"
 
 namespace psdp {
 

@@ -73,6 +73,52 @@ def test_full_sweep_shape_sampled_rows(P):
     assert np.array_equal(Y8[:, rows], F.qx_fixed_point(Q, V, 8, rows=rows))
 
 
+@pytest.mark.parametrize("layout", ["few", "mid", "many", "wide", "tall"])
+def test_every_layout_and_slice_count_bit_exact(P, layout):
+    """Each block layout of the int8 MFMA kernel, forced through
+    psdp_qx_digits_ex with 1, 3 and 8 K slices, on ragged shapes (partial
+    digit tiles, partial row blocks, K ranges not a multiple of the slice
+    count) and on the n = 2500 workload with 300 columns (sampled rows)."""
+    for n, B, D in ((777, 70, 4), (777, 41, 8), (130, 5, 4), (130, 3, 8)):
+        Q = _sym_int8(n, 11 * n + B + D)
+        rng = np.random.default_rng(n + B + D)
+        X = rng.random((B, n)) if D == 4 else rng.standard_normal((B, n)) * 2.0 ** rng.integers(-30, 30, (B, 1))
+        ref = F.qx_fixed_point(Q, X, D)
+        for ks in (1, 3, 8):
+            Y = P.qx_digits(_t(Q), _t(X), digits=D, layout=layout, slices=ks).cpu().numpy()
+            assert np.array_equal(Y, ref), (n, B, D, ks)
+    Q, b, X0 = gen.sparse_2500_starts(B=300)
+    rows = np.sort(np.random.default_rng(5).choice(len(b), 64, replace=False))
+    ref = F.qx_fixed_point(Q, X0, 4, rows=rows)
+    for ks in (1, 2):
+        Y = P.qx_digits(_t(Q), _t(X0), digits=4, layout=layout, slices=ks).cpu().numpy()
+        assert np.array_equal(Y[:, rows], ref), ks
+    print(f"layout {layout}: bit-exact on every shape and slice count", flush=True)
+
+
+def test_digit_table_is_honoured_and_removable(P):
+    """A table installed for (n, digits) decides the solve's product settings
+    (psdp_digit_choice) by the first bucket holding the estimate; removing it
+    restores the built-in rule."""
+    n = 1234
+    before = P.digit_choice(n, 100, 20)
+    P.set_digit_table(n, 4, [(8, "few", 2), (64, "mid", 4), (512, "wide", 1)])
+    try:
+        assert P.digit_choice(n, 5, 0)[0] == (1, 2)
+        assert P.digit_choice(n, 9, 0)[0] == (2, 4)
+        assert P.digit_choice(n, 64, 0)[0] == (2, 4)
+        assert P.digit_choice(n, 65, 0)[0] == (8, 1)
+        assert P.digit_choice(n, 5000, 0)[0] == (8, 1)
+        assert P.digit_choice(n, 100, 20)[1] == before[1]     # no table for 8 digits
+        with pytest.raises(P.PSDPError, match="increasing"):
+            P.set_digit_table(n, 4, [(8, "few", 2), (8, "mid", 4)])
+        with pytest.raises(P.PSDPError, match="layout"):
+            P.set_digit_table(n, 4, [(8, 3, 2)])
+    finally:
+        P.set_digit_table(n, 4, [])
+    assert P.digit_choice(n, 100, 20) == before
+
+
 def test_extreme_int8_range(P):
     """|Q| = 127 everywhere with x = 1 or the largest 8-digit magnitudes: the
     int32 digit sums and the int64 combination stay exact."""
