@@ -475,28 +475,36 @@ def sparse_leg(P, gen, torch, dev, n=8000, p_edge=0.005, B=16):
 def gemv_leg(P, gen, torch, dev, n=16384, outer=3):
     """Single-instance solves (one start) on a Q too large for the caches
     (n = 16384: 1.07 GB in FP32, 0.54 GB in BF16 against 256 MB of Infinity
-    Cache), a few penalty updates each: the product is the GEMV kernel
-    reading all of Q once per evaluation or lambda_min matvec."""
-    import numpy as np
+    Cache), a few penalty updates each, with the product reading Q's unique
+    half from packed upper tiles (the default at this size) and with the
+    row-by-row GEMV reading all of Q. Algorithmic bytes per product: the
+    unique half, n (n + 1) / 2 entries of Q."""
     Q, b = gen.sparse_int(n, 5)
     Qd, bd = torch.from_numpy(Q).to(dev), torch.from_numpy(b).to(dev)
     del Q
     x0 = torch.from_numpy(gen.random_box_points(n, 1, 6)).to(dev)
-    ld = (n + 15) // 16 * 16
+    ld = (n + 31) // 32 * 32
+    nb = (n + 127) // 128
     out = {"workload": f"one start, n={n}, 10% density ints +-[1,100], b=0, {outer} penalty updates"}
     for qx, eb in (("f32", 4), ("bf16", 2)):
-        r = P.solve(Qd, bd, X0=x0, qx_dtype=qx, max_outer=outer, timing=1)
-        s0 = r.stats[0]
-        products = s0["inner_iters"] + s0["aux_matvecs"]
-        secs = s0["qx_seconds"] + s0["aux_seconds"]
-        launches = s0["qx_launches"]
-        per = n * ld * eb  # Q bytes per product (x, 8n bytes, stays in cache)
-        out[qx] = {"kernel": f"gemv_kernel<{'float' if qx == 'f32' else '__hip_bfloat16'}, 4>",
-                   "bound": "hbm", "products": int(products), "launches": int(launches),
-                   "avg_launch_us": secs / max(launches, 1) * 1e6, "bytes_per_product": per,
-                   "achieved": products * per / secs / 1e9 if secs > 0 else 0.0, "peak": PEAK_HBM_GBS,
-                   "unit": "GB/s", "frac": products * per / secs / 1e9 / PEAK_HBM_GBS if secs > 0 else 0.0,
-                   "note": "bytes of the launches that had a live column over the time of all launches"}
+        for sym in (1, 0):
+            r = P.solve(Qd, bd, X0=x0, qx_dtype=qx, max_outer=outer, timing=1, gemv_sym=sym)
+            s0 = r.stats[0]
+            products = s0["inner_iters"] + s0["aux_matvecs"]
+            secs = s0["qx_seconds"] + s0["aux_seconds"]
+            launches = s0["qx_launches"]
+            unique = n * (n + 1) // 2 * eb
+            stored = (nb * (nb + 1) // 2 * 128 * 128 if sym else n * ld) * eb
+            name = ("symv_tile_kernel + symv_reduce_kernel" if sym else "gemv_kernel") + \
+                f"<{'float' if qx == 'f32' else '__hip_bfloat16'}>"
+            out[f"{qx}_{'tiles' if sym else 'rows'}"] = {
+                "kernel": name, "bound": "hbm", "products": int(products), "launches": int(launches),
+                "avg_launch_us": secs / max(launches, 1) * 1e6, "bytes_per_product": unique,
+                "stored_bytes_per_product": stored,
+                "achieved": products * unique / secs / 1e9 if secs > 0 else 0.0, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": products * unique / secs / 1e9 / PEAK_HBM_GBS if secs > 0 else 0.0,
+                "stored_gbs": products * stored / secs / 1e9 if secs > 0 else 0.0,
+                "note": "unique-half bytes of the products with a live column over the time of all product launches"}
     return out
 
 

@@ -124,6 +124,12 @@ typedef struct {
                                   columns and queues the other starts in index order, a column
                                   taking the next start when its own ends (each start performs the
                                   same arithmetic either way; outputs stay per start) */
+    int32_t gemv_sym;          /* single-instance solves (B = 1, floating-point operands): 1 reads
+                                  Q from its unique half, stored as 128 x 128 upper tiles (each tile
+                                  read once for its row and column contributions, partial sums
+                                  added in a fixed order); 0 reads full rows; -1 (default) takes the
+                                  tiles from n = 4096 on. Both are FP64 sums of exact products;
+                                  they differ in summation order only */
     double tol_kkt;            /* delta of eq. (cret) (1e-5) */
     double tol_binary;         /* Algorithm 3 loop tolerance (1e-5) */
     double eta;                /* eq. (alpha1) scaling, 0 < eta < 1 (0.999) */
@@ -487,6 +493,23 @@ psdp_status psdp_digit_choice(int64_t n, int32_t est4, int32_t est8, int32_t *ch
  */
 psdp_status psdp_qx_dense(int32_t dtype, const int32_t *Q, int64_t n, const double *X, int32_t B,
                           double *Y, hipStream_t stream);
+
+/*
+ * psdp_qx_single - the single-instance solver's product on one vector
+ * (the O(n^2) part of eq. (kkt1) and of the lambda_min and x^0 matvecs,
+ * eqs. (alpha) and (gamma)): y = Q_off x, Q_off = Q with a zero diagonal,
+ * stored as `dtype` (F64, F32 or BF16; exact for integer Q within the
+ * type's integer range) and multiplied and summed in FP64, through the
+ * row-by-row GEMV (sym = 0) or the product from the unique half of Q in
+ * packed 128 x 128 upper tiles (sym = 1; see psdp_params.gemv_sym).
+ * Q       device, int32, n x n row-major, symmetric (checked).
+ * x, y    device, double, n entries; y is the output.
+ * The call allocates its own workspace and synchronizes `stream`.
+ * Errors: PSDP_E_INVALID (dtype, sym, n, null pointer), PSDP_E_NOT_SYMMETRIC,
+ *         PSDP_E_DEVICE / PSDP_E_NOMEM.
+ */
+psdp_status psdp_qx_single(int32_t dtype, const int32_t *Q, int64_t n, const double *x, int32_t sym,
+                           double *y, hipStream_t stream);
 
 /*
  * psdp_qx_sparse - the same product as psdp_qx_digits (same arguments, same

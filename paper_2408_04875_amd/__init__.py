@@ -7,5 +7,5 @@ from .binding import (  # noqa: F401
     F32, F64, BF16, I8, PABB, PPA, EXIT_NAMES, PSDPError, Params, Stats,
     DIGIT_LAYOUTS, default_params, digit_choice, eval_penalty_grad, install_tuning, load, penalty_adjoint,
     penalty_fn, set_digit_table,
-    perturbation, plan_columns, qx_dense, qx_digits, round_objective, solve, solve_group, solve_host,
+    perturbation, plan_columns, qx_dense, qx_digits, qx_single, round_objective, solve, solve_group, solve_host,
 )

@@ -40,6 +40,7 @@ class Params(ctypes.Structure):
         ("sparse", ctypes.c_int32),
         ("lambda_reuse", ctypes.c_int32),
         ("slots", ctypes.c_int32),
+        ("gemv_sym", ctypes.c_int32),
         ("tol_kkt", ctypes.c_double),
         ("tol_binary", ctypes.c_double),
         ("eta", ctypes.c_double),
@@ -125,6 +126,7 @@ SIGNATURES = {
     "psdp_qx_sparse": (_I32, [_P, _I64, _P, _I32, _I32, _P, _P]),
     "psdp_qx_dense": (_I32, [_I32, _P, _I64, _P, _I32, _P, _P]),
     "psdp_release": (None, []),
+    "psdp_qx_single": (_I32, [_I32, _P, _I64, _P, _I32, _P, _P]),
     "psdp_plan_columns": (_I32, [_I64, _I32, ctypes.POINTER(Params), _I32, ctypes.POINTER(ColumnPlan)]),
     "psdp_qx_digits_ex": (_I32, [_P, _I64, _P, _I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_D), _P, _P]),
     "psdp_set_digit_table": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
@@ -485,6 +487,22 @@ def install_tuning(path: str = TUNING_DIR):
                             [(e["max_cols"], e["layout"], e["slices"]) for e in t["entries"]])
             keys.append((int(t["n"]), int(t["digits"])))
     return keys
+
+
+def qx_single(Q, x, dtype: str = "f32", sym: bool = False):
+    """The single-instance solver's product (psdp_qx_single): Q with a zero
+    diagonal stored as dtype ("f64", "f32", "bf16") times x (float64, (n,)),
+    summed in FP64, by full rows (sym=False) or from the unique half of Q in
+    packed upper tiles (sym=True); returns (n,) float64."""
+    torch = _torch()
+    lib = load()
+    _dev(Q, torch.int32, "Q")
+    _dev(x, torch.float64, "x")
+    n = Q.shape[0]
+    y = torch.empty(n, dtype=torch.float64, device=x.device)
+    code = {"f64": F64, "f32": F32, "bf16": BF16}[dtype]
+    _check(lib.psdp_qx_single(code, _ptr(Q), n, _ptr(x), 1 if sym else 0, _ptr(y), _stream()))
+    return y
 
 
 def qx_dense(Q, X, dtype: str = "f32"):

@@ -42,6 +42,10 @@ psdp_status hipfail(hipError_t e, const char *where) {
 // (32), zero padded, so that 16-byte loads of whole chunks stay in bounds.
 int64_t padld(int64_t n) { return (n + 31) / 32 * 32; }
 
+// Single-instance solves from this n on read Q from its packed upper tiles
+// (psdp_params.gemv_sym = -1).
+constexpr int64_t kSymAutoN = 4096;
+
 // Every list and every operand buffer that the product kernels read through
 // a list holds zero_col + 1 columns: an empty list slot names zero_col.
 bool plan_holds_zero_col(const psdp_column_plan &p) {
@@ -150,6 +154,7 @@ psdp_status check_params(const psdp_params &p) {
         !(p.lambda_floor_rel >= 0.0) || !(p.sigma >= 0.0) || !std::isfinite(p.sigma))
         return fail(PSDP_E_INVALID, "params: tolerance out of range");
     if (p.sparse < -1 || p.sparse > 1) return fail(PSDP_E_INVALID, "params.sparse must be -1, 0 or 1");
+    if (p.gemv_sym < -1 || p.gemv_sym > 1) return fail(PSDP_E_INVALID, "params.gemv_sym must be -1, 0 or 1");
     if (p.lambda_reuse < 0 || p.lambda_reuse > 1) return fail(PSDP_E_INVALID, "params.lambda_reuse must be 0 or 1");
     if (p.slots < 0) return fail(PSDP_E_INVALID, "params.slots must be >= 0");
     if (p.sparse == 1 && p.qx_dtype != PSDP_I8)
@@ -347,6 +352,7 @@ struct Solver {
     // enqueued before each batch of sweeps, after the configuration of the
     // batch is chosen (nullable)
     std::function<hipError_t(hipStream_t)> before_batch;
+    bool sym_gemv = false;  // the single-instance product reads the packed upper tiles
     // when set, each poll also copies the first list_cap entries of the main
     // live list, and relist receives the list and its count (a superset of the
     // columns still live when it runs)
@@ -955,8 +961,34 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
             },
             none);
     } else if (!batched) {
-        rs = run_sweeps(S, prm, tm, ta, ts, st, [&]() { return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st); },
-                        none);
+        // one column: the row-by-row GEMV, or the product from the unique
+        // half of Q (packed upper tiles) once Q outgrows the caches
+        const bool sym = prm.gemv_sym == 1 || (prm.gemv_sym == -1 && n >= kSymAutoN);
+        SymTiles sy{};
+        if (sym) {
+            sy.nb = symv_blocks(n);
+            sy.ntiles = (int64_t)sy.nb * (sy.nb + 1) / 2;
+            const std::vector<int32_t> tl = symv_tile_list(sy.nb);
+            void *P;
+            int2 *tiles;
+            HIPCHK(S.ar.get(&P, symv_packed_elems(sy.nb) * esize(qtype)));
+            HIPCHK(S.ar.get((void **)&tiles, tl.size() * sizeof(int32_t)));
+            HIPCHK(hipMemcpyAsync(tiles, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            HIPCHK(S.ar.get((void **)&sy.D, sy.ntiles * 128 * sizeof(double)));
+            HIPCHK(S.ar.get((void **)&sy.T, sy.ntiles * 128 * sizeof(double)));
+            sy.P = P;
+            sy.tiles = tiles;
+            HIPCHK(launch_symv_pack(qtype, Qop, ld, sy, st));
+            S.sym_gemv = true;
+        }
+        rs = run_sweeps(
+            S, prm, tm, ta, ts, st,
+            [&]() {
+                if (!sym) return launch_gemv(prm.qx_dtype, &hin, 1, w, 1, st);
+                sy.live = w.nactive;
+                return launch_symv(prm.qx_dtype, sy, (const double *)w.op, ld, n, (double *)w.U, st);
+            },
+            none);
     } else {
         const bool merge = w.split && prm.timing == 0 && main_gemm == PSDP_F32 && aux_gemm == kGemmF32QF64;
         S.config_key = [&]() {
@@ -1089,6 +1121,7 @@ void psdp_params_default(psdp_params *p) {
     p->gemm_variant = -1;
     p->graph = 1;
     p->sparse = -1;
+    p->gemv_sym = -1;
     p->lambda_reuse = 1;
     p->slots = 0;
     p->tol_kkt = 1e-5;
@@ -1529,6 +1562,67 @@ psdp_status psdp_digit_choice(int64_t n, int32_t est4, int32_t est8, int32_t *ch
     choice[1] = c.ks4;
     choice[2] = c.mt8;
     choice[3] = c.ks8;
+    return PSDP_OK;
+}
+
+psdp_status psdp_qx_single(int32_t dtype, const int32_t *Q, int64_t n, const double *x, int32_t sym, double *y,
+                           hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lock);
+    g_err.clear();
+    if (dtype != PSDP_F64 && dtype != PSDP_F32 && dtype != PSDP_BF16)
+        return fail(PSDP_E_INVALID, "dtype must be F64, F32 or BF16");
+    if (sym != 0 && sym != 1) return fail(PSDP_E_INVALID, "sym must be 0 or 1");
+    if (!Q || !x || !y) return fail(PSDP_E_INVALID, "null pointer");
+    if (n < 1 || n > 65536) return fail(PSDP_E_INVALID, "n must be in [1, 65536]");
+    psdp_params prm;
+    psdp_params_default(&prm);
+    prm.qx_dtype = dtype;
+    InstFacts facts;
+    if (psdp_status s = check_instance(Q, Q, n, nullptr, 0, nullptr, prm, st, &facts)) return s;
+    Arena ar;
+    const int64_t ld = padld(n);
+    void *Qop;
+    double *R, *dq, *op, *U;
+    int32_t *act;
+    HIPCHK(ar.get(&Qop, ld * ld * esize(dtype)));
+    HIPCHK(ar.get((void **)&R, ld * 8));
+    HIPCHK(ar.get((void **)&dq, ld * 8));
+    HIPCHK(launch_prep_q(dtype, Q, n, ld, PSDP_PERTURB_NONE, 0.0, 0, Qop, R, dq, st));
+    HIPCHK(ar.get((void **)&op, ld * sizeof(double)));
+    HIPCHK(hipMemsetAsync(op, 0, ld * sizeof(double), st));
+    HIPCHK(hipMemcpyAsync(op, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(ar.get((void **)&U, ld * sizeof(double)));
+    HIPCHK(ar.get((void **)&act, 2 * sizeof(int32_t)));
+    hipLaunchKernelGGL(iota_list_kernel, dim3(1), dim3(256), 0, st, act, 1);
+    HIPCHK(hipGetLastError());
+    if (sym) {
+        SymTiles sy{};
+        sy.nb = symv_blocks(n);
+        sy.ntiles = (int64_t)sy.nb * (sy.nb + 1) / 2;
+        const std::vector<int32_t> tl = symv_tile_list(sy.nb);
+        void *P;
+        int2 *tiles;
+        HIPCHK(ar.get(&P, symv_packed_elems(sy.nb) * esize(dtype)));
+        HIPCHK(ar.get((void **)&tiles, tl.size() * sizeof(int32_t)));
+        HIPCHK(hipMemcpyAsync(tiles, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(ar.get((void **)&sy.D, sy.ntiles * 128 * sizeof(double)));
+        HIPCHK(ar.get((void **)&sy.T, sy.ntiles * 128 * sizeof(double)));
+        sy.P = P;
+        sy.tiles = tiles;
+        sy.live = act + 1;
+        HIPCHK(launch_symv_pack(dtype, Qop, ld, sy, st));
+        HIPCHK(launch_symv(dtype, sy, op, ld, n, U, st));
+    } else {
+        Work w{};
+        w.op = op;
+        w.U = U;
+        w.active = act;
+        w.nactive = act + 1;
+        Inst hin{n, ld, 0, Qop};
+        HIPCHK(launch_gemv(dtype, &hin, 1, w, 1, st));
+    }
+    HIPCHK(hipMemcpyAsync(y, U, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     return PSDP_OK;
 }
 

@@ -2,6 +2,8 @@
 // the kernel translation units and called by the entry points (api.hip).
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace psdp {
@@ -118,6 +120,24 @@ hipError_t launch_csr_fill(const int8_t *Q8, int64_t ldq, int64_t n, const int32
 hipError_t launch_sparse(const SparseJob *main4, const SparseJob *aux8, hipStream_t st);
 hipError_t launch_words_from_vectors(const double *X, int64_t n, int64_t ldx, int B, int D, int32_t *w0,
                                      int32_t *w1, int64_t ldw, int32_t *escale, hipStream_t st);
+
+// Symmetric single-instance product from the unique half of Q (symv.hip):
+// packed upper tiles of 128 x 128, one block per tile, partial vectors
+// summed per row in a fixed order.
+struct SymTiles {
+    const void *P;        // packed tiles (Q's storage type)
+    const int2 *tiles;    // (bi, bj) of every tile, row-major upper-triangle order
+    int nb;               // tile rows: ceil(n / 128)
+    int64_t ntiles;       // nb (nb + 1) / 2
+    double *D, *T;        // staging: the direct and transposed partial vectors, ntiles x 128 each
+    const int32_t *live;  // nullable: the live count; nothing runs when it is 0
+};
+int symv_blocks(int64_t n);
+std::vector<int32_t> symv_tile_list(int nb);
+int64_t symv_packed_elems(int nb);
+hipError_t launch_symv_pack(int dtype, const void *Qop, int64_t ld, const SymTiles &s, hipStream_t st);
+hipError_t launch_symv(int dtype, const SymTiles &s, const double *x, int64_t ld, int64_t n, double *y,
+                       hipStream_t st);
 
 // Solver kernels.
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,

@@ -35,6 +35,7 @@ def test_params_defaults_and_struct_size(lib):
     assert p.poll_sweeps == 64 and p.sparse == -1 and p.graph == 1
     assert p.eig_tol == 1e-7 and p.eig_maxit == 500
     assert p.lambda_reuse == 1
+    assert p.gemv_sym == -1 and p.slots == 0
     q = binding.default_params(inner="ppa", qx_dtype="f32", perturb="diag", sigma=0.5)
     assert (q.inner, q.qx_dtype, q.perturb, q.sigma) == (1, 1, 2, 0.5)
     with pytest.raises(TypeError):
