@@ -40,6 +40,7 @@ class Params(ctypes.Structure):
         ("sparse", ctypes.c_int32),
         ("lambda_reuse", ctypes.c_int32),
         ("slots", ctypes.c_int32),
+        ("lanes", ctypes.c_int32),
         ("gemv_sym", ctypes.c_int32),
         ("tol_kkt", ctypes.c_double),
         ("tol_binary", ctypes.c_double),

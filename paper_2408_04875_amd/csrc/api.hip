@@ -8,6 +8,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -45,6 +46,10 @@ int64_t padld(int64_t n) { return (n + 31) / 32 * 32; }
 // Single-instance solves from this n on read Q from its packed upper tiles
 // (psdp_params.gemv_sym = -1).
 constexpr int64_t kSymAutoN = 4096;
+
+// Batched integer-product solves with at least this many columns run them as
+// two lanes (psdp_params.lanes = 0).
+constexpr int kLaneAutoCols = 512;
 
 // Every list and every operand buffer that the product kernels read through
 // a list holds zero_col + 1 columns: an empty list slot names zero_col.
@@ -155,6 +160,7 @@ psdp_status check_params(const psdp_params &p) {
         return fail(PSDP_E_INVALID, "params: tolerance out of range");
     if (p.sparse < -1 || p.sparse > 1) return fail(PSDP_E_INVALID, "params.sparse must be -1, 0 or 1");
     if (p.gemv_sym < -1 || p.gemv_sym > 1) return fail(PSDP_E_INVALID, "params.gemv_sym must be -1, 0 or 1");
+    if (p.lanes < 0 || p.lanes > 2) return fail(PSDP_E_INVALID, "params.lanes must be 0, 1 or 2");
     if (p.lambda_reuse < 0 || p.lambda_reuse > 1) return fail(PSDP_E_INVALID, "params.lambda_reuse must be 0 or 1");
     if (p.slots < 0) return fail(PSDP_E_INVALID, "params.slots must be >= 0");
     if (p.sparse == 1 && p.qx_dtype != PSDP_I8)
@@ -392,17 +398,17 @@ void set_parity(Solver &S, int p) {
 // One default-priority stream per device for the solve work: the caller's
 // stream may be the null stream, which cannot be captured into a graph.
 // Created under the library lock and kept until the process ends.
-hipError_t solve_stream(hipStream_t *out) {
-    static std::map<int, hipStream_t> streams;
+hipError_t solve_stream(hipStream_t *out, int index = 0) {
+    static std::map<std::pair<int, int>, hipStream_t> streams;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    auto it = streams.find(dev);
+    auto it = streams.find({dev, index});
     if (it == streams.end()) {
         hipStream_t s;
         e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
         if (e != hipSuccess) return e;
-        it = streams.emplace(dev, s).first;
+        it = streams.emplace(std::make_pair(dev, index), s).first;
     }
     *out = it->second;
     return hipSuccess;
@@ -471,6 +477,8 @@ psdp_status alloc_columns(Solver &S, int64_t total, const psdp_column_plan &pl, 
     HIPCHK(hipMemsetAsync(S.sweeps, 0, 64, st));
     w.sweeps = S.sweeps;
     w.ncol = ncol;
+    w.col_base = 0;
+    w.col_count = ncol;
     if (S.w.split) {
         w.ksplit_aux = 1;
         w.slice_aux = total;
@@ -518,6 +526,10 @@ struct QxTimer {
         return r;
     }
     // Accumulates every recorded pair; call after the stream is synchronized.
+    void add(const QxTimer &o) {
+        seconds += o.seconds;
+        launches += o.launches;
+    }
     hipError_t collect() {
         for (size_t q = 0; q + 1 < used; q += 2) {
             float ms = 0.f;
@@ -531,56 +543,58 @@ struct QxTimer {
     }
 };
 
-// Runs sweeps until no column is live. `apply` enqueues the Q.X product of
-// the main live list, `apply_aux` (split precision only) the FP64 product of
-// the lambda_min / CG list.
+// The sweeps of one launch sequence until no column is live: `apply`
+// enqueues the Q.X product of the main live list, `apply_aux` (split
+// precision only) the FP64 product of the lambda_min / CG list. Batches of
+// poll_sweeps sweeps are replayed as graphs (one per product configuration:
+// the kernels' arguments are fixed inside a graph); the live counts are read
+// back after every batch and consumed one batch later (the next batch is
+// queued first), and the product configuration is re-chosen from them.
+// advance() queues one batch and processes the previous one's counts; a
+// solve runs one loop to the end, or several loops (one per stream) in turn,
+// so that their kernels overlap.
 template <typename Apply, typename ApplyAux>
-psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &ta, QxTimer &ts, hipStream_t st,
-                       const Apply &apply, const ApplyAux &apply_aux) {
-    Work &w = S.w;
-    int32_t *host_cnt = nullptr;
-    HIPCHK(hipHostMalloc((void **)&host_cnt, 4 * sizeof(int32_t), hipHostMallocDefault));
-    struct HostFree {
-        int32_t *p;
-        ~HostFree() { (void)hipHostFree(p); }
-    } hf{host_cnt};
-    int32_t *host_list = nullptr;
-    if (S.relist) HIPCHK(hipHostMalloc((void **)&host_list, 2 * (size_t)S.list_cap * sizeof(int32_t), hipHostMallocDefault));
-    struct ListFree {
-        int32_t *p;
-        ~ListFree() {
-            if (p) (void)hipHostFree(p);
-        }
-    } lf{host_list};
-    hipEvent_t evs[2];
-    HIPCHK(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
-    struct EvFree {
-        hipEvent_t *e;
-        ~EvFree() {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    } ef{evs};
-    // hard bound from the per-column caps (every sweep advances every live column)
-    const int64_t cap = ((int64_t)prm.cg_maxit +
-                         (int64_t)(prm.max_outer + 1) * ((int64_t)prm.eig_maxit + prm.max_inner + 2) + 2) *
-                        S.rounds;
-    int64_t done_sweeps = 0;
+struct SweepLoop {
+    Solver &S;
+    const psdp_params &prm;
+    QxTimer &tm, &ta, &ts;
+    hipStream_t st;
+    const Apply &apply;
+    const ApplyAux &apply_aux;
+    int32_t *host_cnt = nullptr, *host_list = nullptr;
+    hipEvent_t evs[2] = {nullptr, nullptr};
+    int64_t cap = 0, done_sweeps = 0;
     int batch = 0;
-    bool finished = false;
-    // batches of poll_sweeps sweeps replayed as graphs, one per product
-    // configuration (the kernels' arguments are fixed inside a graph)
-    const bool graphs = prm.graph != 0 && !tm.on;
+    bool finished = false, graphs = false;
     std::map<int64_t, hipGraphExec_t> execs;
-    struct ExecFree {
-        std::map<int64_t, hipGraphExec_t> *m;
-        ~ExecFree() {
-            for (auto &kv : *m) (void)hipGraphExecDestroy(kv.second);
-        }
-    } xf{&execs};
+
+    SweepLoop(Solver &S_, const psdp_params &prm_, QxTimer &tm_, QxTimer &ta_, QxTimer &ts_, hipStream_t st_,
+              const Apply &apply_, const ApplyAux &apply_aux_)
+        : S(S_), prm(prm_), tm(tm_), ta(ta_), ts(ts_), st(st_), apply(apply_), apply_aux(apply_aux_) {}
+    ~SweepLoop() {
+        for (auto &kv : execs) (void)hipGraphExecDestroy(kv.second);
+        for (hipEvent_t e : evs)
+            if (e) (void)hipEventDestroy(e);
+        if (host_cnt) (void)hipHostFree(host_cnt);
+        if (host_list) (void)hipHostFree(host_list);
+    }
+
+    psdp_status init() {
+        HIPCHK(hipHostMalloc((void **)&host_cnt, 4 * sizeof(int32_t), hipHostMallocDefault));
+        if (S.relist)
+            HIPCHK(hipHostMalloc((void **)&host_list, 2 * (size_t)S.list_cap * sizeof(int32_t), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
+        // hard bound from the per-column caps (every sweep advances every live column)
+        cap = ((int64_t)prm.cg_maxit + (int64_t)(prm.max_outer + 1) * ((int64_t)prm.eig_maxit + prm.max_inner + 2) + 2) *
+              S.rounds;
+        graphs = prm.graph != 0 && !tm.on;
+        return PSDP_OK;
+    }
+
     // sweep s reads the lists of parity s % 2 (the initial lists are parity 0)
-    auto enqueue_sweeps = [&](int nb) -> hipError_t {
+    hipError_t enqueue_sweeps(int nb) {
+        Work &w = S.w;
         for (int q = 0; q < nb; ++q) {
             set_parity(S, (int)((done_sweeps + q) & 1));
             hipError_t e;
@@ -597,8 +611,10 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
             if ((e = ts.end(st)) != hipSuccess) return e;
         }
         return hipSuccess;
-    };
-    while (!finished) {
+    }
+
+    psdp_status advance() {
+        Work &w = S.w;
         const int nb = (int)std::min<int64_t>(prm.poll_sweeps, cap - done_sweeps);
         if (nb <= 0) return fail(PSDP_E_DEVICE, "sweep bound exceeded");
         if (S.before_batch) HIPCHK(S.before_batch(st));
@@ -647,12 +663,26 @@ psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &
             HIPCHK(ts.collect());
         }
         ++batch;
+        return PSDP_OK;
     }
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(tm.collect());
-    HIPCHK(ta.collect());
-    HIPCHK(ts.collect());
-    return PSDP_OK;
+
+    psdp_status finish() {
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(tm.collect());
+        HIPCHK(ta.collect());
+        HIPCHK(ts.collect());
+        return PSDP_OK;
+    }
+};
+
+template <typename Apply, typename ApplyAux>
+psdp_status run_sweeps(Solver &S, const psdp_params &prm, QxTimer &tm, QxTimer &ta, QxTimer &ts, hipStream_t st,
+                       const Apply &apply, const ApplyAux &apply_aux) {
+    SweepLoop<Apply, ApplyAux> L(S, prm, tm, ta, ts, st, apply, apply_aux);
+    if (psdp_status e = L.init()) return e;
+    while (!L.finished)
+        if (psdp_status e = L.advance()) return e;
+    return L.finish();
 }
 
 void fill_stats(const std::vector<Col> &cols, int64_t sweeps, const QxTimer &tm, double flops_total,
@@ -832,24 +862,56 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         if (!batched) return Pick{false, 4, 1, std::min({ncol, ncols + 16, live})};
         return pick_product(ncol, ncols, live, gemm_dtype, prm.gemm_variant, MT);
     };
-    // integer path: layouts from the estimated live counts, K slices from
-    // the blocks of both products (they share one launch)
+    // Integer path: the columns may run as two lanes, concurrent launch
+    // sequences on two streams, each over half the columns and half the
+    // starts with its own live lists, counters and queue (the step kernels of
+    // one lane then overlap the products of the other). Every start performs
+    // the same arithmetic in any lane. Each lane picks its products' layouts
+    // from its estimated live counts and their K slices from the blocks of
+    // both products (they share one launch).
     struct Pick8 { int mt; int ks; int est; };
-    Pick8 p8m{}, p8a{};
-    auto pick8 = [&](int cm, int ca) {
-        p8m.est = std::min({ncol, cm + 16, cm + ca});
-        p8a.est = std::min({ncol, ca + 16, cm + ca});
-        const DigitChoice dc = digit_choice(n, ld, p8m.est, p8a.est);
-        p8m.mt = dc.mt4;
-        p8m.ks = dc.ks4;
-        p8a.mt = dc.mt8;
-        p8a.ks = dc.ks8;
+    struct Lane {
+        Solver *S = nullptr;
+        int ncols = 0;
+        Pick8 p8m{}, p8a{};
+        bool dirty_m = false, dirty_a = false;
+        hipStream_t st = nullptr;
+        QxTimer tm, ta, ts;
+    };
+    const int nlanes = (i8 && ncol >= 2 && (prm.lanes == 2 || (prm.lanes == 0 && ncol >= kLaneAutoCols))) ? 2 : 1;
+    const int nc0 = nlanes == 2 ? ncol / 2 : ncol, nc1 = ncol - nc0;
+    // lane 0 takes starts [0, B0), lane 1 [B0, B); each range holds at least
+    // the lane's columns
+    const int32_t B0 = nlanes == 2 ? std::max<int32_t>(nc0, std::min<int32_t>(B - nc1, (int32_t)(((int64_t)B * nc0 +
+                                                                                             ncol / 2) / ncol)))
+                                   : B;
+    std::unique_ptr<Solver> S1;
+    if (nlanes == 2) S1.reset(new Solver());
+    std::vector<std::unique_ptr<Lane>> lanes;
+    for (int l = 0; l < nlanes; ++l) {
+        lanes.emplace_back(new Lane());
+        lanes[l]->S = l == 0 ? &S : S1.get();
+        lanes[l]->ncols = l == 0 ? nc0 : nc1;
+    }
+    if (S1) {
+        S1->rowptr = S.rowptr;
+        S1->pk = S.pk;
+        S1->nnz = S.nnz;
+    }
+    auto pick8 = [&](Lane &L, int cm, int ca) {
+        L.p8m.est = std::min({L.ncols, cm + 16, cm + ca});
+        L.p8a.est = std::min({L.ncols, ca + 16, cm + ca});
+        const DigitChoice dc = digit_choice(n, ld, L.p8m.est, L.p8a.est);
+        L.p8m.mt = dc.mt4;
+        L.p8m.ks = dc.ks4;
+        L.p8a.mt = dc.mt8;
+        L.p8a.ks = dc.ks8;
         // sparse products while they cost less than the digit products; the
         // bound takes every live column as a two-half lambda_min column
-        const int live = std::min(ncol, cm + ca);
-        S.sparse_now = S.rowptr != nullptr && (prm.sparse == 1 || sparse_batch(n, S.nnz, live));
+        const int live = std::min(L.ncols, cm + ca);
+        L.S->sparse_now = L.S->rowptr != nullptr && (prm.sparse == 1 || sparse_batch(n, L.S->nnz, live));
     };
-    pick8(ncol, ncol);
+    for (auto &L : lanes) pick8(*L, L->ncols, L->ncols);
     Pick pm = pick(ncol, ncol, main_gemm), pa = pick(ncol, ncol, aux_gemm);
     // integer path: the column kernel reads one buffer, whatever the
     // product's K slices
@@ -865,7 +927,7 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         cc.off = (int64_t)c * ld;
         cc.ioff = 0;
         cc.id = c;
-        cc.start = c;
+        cc.start = c < nc0 ? c : B0 + (c - nc0);
         cc.phase = PH_INNER;  // placeholder, set by the init kernel
     }
     HIPCHK(S.ar.get((void **)&w.col, ncol * sizeof(Col)));
@@ -873,14 +935,14 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     hipLaunchKernelGGL(fill_p_kernel, dim3((unsigned)((ld * ncol + 255) / 256)), dim3(256), 0, st, w.p, p0, n,
                        ld, ncol);
     if (queued) {
-        S.rounds = (B + ncol - 1) / ncol;
+        S.rounds = (B0 + nc0 - 1) / nc0;
         int32_t *q;
         HIPCHK(S.ar.get((void **)&q, 64));
-        HIPCHK(hipMemcpyAsync(q, &ncol, sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(q, &nc0, sizeof(int32_t), hipMemcpyHostToDevice, st));
         HIPCHK(S.ar.get((void **)&w.xfin, (size_t)n * B * sizeof(double)));
         HIPCHK(S.ar.get((void **)&w.fin, (size_t)B * sizeof(Col)));
         w.queue = q;
-        w.nstart = B;
+        w.nstart = B0;
         w.X0 = X0;
         w.p0 = p0;
     }
@@ -899,67 +961,147 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         w.alpha_in = da;
         w.alpha_cap = alpha_cap;
     }
-    HIPCHK(launch_solver_init(S.optype, w, X0, X0 ? 0 : 1, st));
-    HIPCHK(launch_compact(w, st));
-
     // optional per-phase timing of the column kernel (diagnostics, env PSDP_PHASE_PROFILE=1)
     const bool phase_prof = getenv("PSDP_PHASE_PROFILE") != nullptr;
     if (phase_prof) {
         HIPCHK(S.ar.get((void **)&w.phase_prof, 16 * sizeof(unsigned long long)));
         HIPCHK(hipMemsetAsync(w.phase_prof, 0, 16 * sizeof(unsigned long long), st));
     }
+    lanes[0]->st = st;
+    if (S1) {
+        // lane 1: the shared buffers and parameters, its own lists, counters,
+        // sweep counter and queue, and columns [nc0, ncol)
+        Solver &LS = *S1;
+        LS.w = w;
+        LS.optype = S.optype;
+        LS.utype = S.utype;
+        LS.nmax = S.nmax;
+        for (int p = 0; p < 2; ++p) {
+            HIPCHK(S.ar.get((void **)&LS.act[p], (size_t)plan.list_len * sizeof(int32_t)));
+            if (w.split) HIPCHK(S.ar.get((void **)&LS.act_aux[p], (size_t)plan.list_len * sizeof(int32_t)));
+            else LS.act_aux[p] = LS.act[p];
+        }
+        HIPCHK(S.ar.get((void **)&LS.cnt, 64));
+        HIPCHK(hipMemsetAsync(LS.cnt, 0, 64, st));
+        HIPCHK(S.ar.get((void **)&LS.sweeps, 64));
+        HIPCHK(hipMemsetAsync(LS.sweeps, 0, 64, st));
+        LS.w.sweeps = LS.sweeps;
+        set_parity(LS, 0);
+        LS.w.col_base = nc0;
+        LS.w.col_count = nc1;
+        if (queued) {
+            const int32_t q1v = B0 + nc1;
+            int32_t *q1;
+            HIPCHK(S.ar.get((void **)&q1, 64));
+            HIPCHK(hipMemcpyAsync(q1, &q1v, sizeof(int32_t), hipMemcpyHostToDevice, st));
+            LS.w.queue = q1;
+            LS.w.nstart = B;
+            LS.rounds = (B - B0 + nc1 - 1) / nc1;
+        }
+        w.col_count = nc0;
+        HIPCHK(solve_stream(&lanes[1]->st, 1));
+    }
+    for (auto &L : lanes) {
+        HIPCHK(launch_solver_init(S.optype, L->S->w, X0, X0 ? 0 : 1, st));
+        HIPCHK(launch_compact(L->S->w, st));
+        L->tm.on = L->ta.on = L->ts.on = prm.timing != 0;
+    }
+    if (S1) {
+        // lane 1 starts once the set-up on the first stream is done
+        hipEvent_t ready;
+        HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(ready, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(lanes[1]->st, ready, 0);
+        (void)hipEventDestroy(ready);
+        HIPCHK(e);
+    }
     QxTimer tm, ta, ts;
     tm.on = ta.on = ts.on = prm.timing != 0;
     auto none = []() { return hipSuccess; };
     psdp_status rs;
     if (i8) {
-        auto job_main = [&]() {
-            return DigitJob{w.dig, w.active, w.nactive, (int64_t *)w.U, nullptr, ncol, p8m.ks, p8m.mt, p8m.est};
-        };
-        auto job_aux = [&]() {
-            return DigitJob{w.dig_aux, w.active_aux, w.nactive_aux, (int64_t *)w.U_aux, w.U_lo, ncol, p8a.ks, p8a.mt,
-                            p8a.est};
-        };
         const int8_t *Q8 = (const int8_t *)Qop;
-        S.config_key = [&]() {
-            return ((int64_t)p8m.mt | ((int64_t)p8m.ks << 5) | ((int64_t)p8a.mt << 9) | ((int64_t)p8a.ks << 14) |
-                    ((int64_t)p8m.est << 18) | ((int64_t)p8a.est << 38)) * 2 +
-                   (S.sparse_now ? 1 : 0);
-        };
-        S.repick = [&](int cm, int ca) { pick8(cm, ca); };
-        // a product written by one K slice overwrites its outputs, so the
-        // column kernel clears what it read only when the next product of
-        // that kind adds its slices (K slices > 1); before such a batch the
-        // buffers are cleared here if the previous batch left values in them
-        bool dirty_m = false, dirty_a = false;
-        S.before_batch = [&](hipStream_t s) -> hipError_t {
-            const bool zm = !S.sparse_now && p8m.ks > 1, za = !S.sparse_now && p8a.ks > 1;
-            w.clear_main = zm ? 1 : 0;
-            w.clear_aux = za ? 1 : 0;
-            hipError_t e = hipSuccess;
-            const size_t bytes = (size_t)ld * ncol * sizeof(int64_t);
-            if (zm && dirty_m) e = hipMemsetAsync(w.U, 0, bytes, s);
-            if (e == hipSuccess && za && dirty_a) e = hipMemsetAsync(w.U_aux, 0, bytes, s);
-            if (e == hipSuccess && za && dirty_a) e = hipMemsetAsync(w.U_lo, 0, bytes, s);
-            dirty_m = !zm;
-            dirty_a = !za;
-            return e;
-        };
-        // both products in one launch (timed as one launch when timing = 1)
-        rs = run_sweeps(
-            S, prm, tm, ta, ts, st,
-            [&]() {
-                if (S.sparse_now) {
-                    const SparseJob sm{p8m.est > 0, S.rowptr, S.pk, n, w.tw, nullptr, ld, w.active, w.nactive, ncol,
-                                       (int64_t *)w.U, nullptr, ld};
-                    const SparseJob sa{p8a.est > 0, S.rowptr, S.pk, n, w.tw_hi, w.tw_lo, ld, w.active_aux,
-                                       w.nactive_aux, ncol, (int64_t *)w.U_aux, w.U_lo, ld};
-                    return launch_sparse(&sm, &sa, st);
+        for (auto &Lp : lanes) {
+            Lane *L = Lp.get();
+            Solver &LS = *L->S;
+            LS.config_key = [&LS, L]() {
+                return ((int64_t)L->p8m.mt | ((int64_t)L->p8m.ks << 5) | ((int64_t)L->p8a.mt << 9) |
+                        ((int64_t)L->p8a.ks << 14) | ((int64_t)L->p8m.est << 18) | ((int64_t)L->p8a.est << 38)) * 2 +
+                       (LS.sparse_now ? 1 : 0);
+            };
+            LS.repick = [&pick8, L](int cm, int ca) { pick8(*L, cm, ca); };
+            // a product written by one K slice overwrites its outputs, so the
+            // column kernel clears what it read only when the next product of
+            // that kind adds its slices (K slices > 1); before such a batch the
+            // lane's columns of the buffers are cleared here if the previous
+            // batch left values in them
+            LS.before_batch = [&LS, L, ld](hipStream_t s) -> hipError_t {
+                Work &lw = LS.w;
+                const bool zm = !LS.sparse_now && L->p8m.ks > 1, za = !LS.sparse_now && L->p8a.ks > 1;
+                lw.clear_main = zm ? 1 : 0;
+                lw.clear_aux = za ? 1 : 0;
+                hipError_t e = hipSuccess;
+                const int64_t off = (int64_t)lw.col_base * ld;
+                const size_t bytes = (size_t)ld * lw.col_count * sizeof(int64_t);
+                if (zm && L->dirty_m) e = hipMemsetAsync((int64_t *)lw.U + off, 0, bytes, s);
+                if (e == hipSuccess && za && L->dirty_a) e = hipMemsetAsync(lw.U_aux + off, 0, bytes, s);
+                if (e == hipSuccess && za && L->dirty_a) e = hipMemsetAsync(lw.U_lo + off, 0, bytes, s);
+                L->dirty_m = !zm;
+                L->dirty_a = !za;
+                return e;
+            };
+        }
+        // both products of a lane's sweep in one launch (timed as one launch
+        // when timing = 1)
+        auto make_apply = [&](Lane *L) {
+            return [&, L]() -> hipError_t {
+                Solver &LS = *L->S;
+                const Work &lw = LS.w;
+                if (LS.sparse_now) {
+                    const SparseJob sm{L->p8m.est > 0, LS.rowptr, LS.pk, n, lw.tw, nullptr, ld, lw.active, lw.nactive,
+                                       ncol, (int64_t *)lw.U, nullptr, ld};
+                    const SparseJob sa{L->p8a.est > 0, LS.rowptr, LS.pk, n, lw.tw_hi, lw.tw_lo, ld, lw.active_aux,
+                                       lw.nactive_aux, ncol, (int64_t *)lw.U_aux, lw.U_lo, ld};
+                    return launch_sparse(&sm, &sa, L->st);
                 }
-                const DigitJob jm = job_main(), ja = job_aux();
-                return launch_digit(Q8, ld, n, ld, &jm, &ja, st);
-            },
-            none);
+                const DigitJob jm{lw.dig, lw.active, lw.nactive, (int64_t *)lw.U, nullptr, ncol,
+                                  L->p8m.ks, L->p8m.mt, L->p8m.est};
+                const DigitJob ja{lw.dig_aux, lw.active_aux, lw.nactive_aux, (int64_t *)lw.U_aux, lw.U_lo, ncol,
+                                  L->p8a.ks, L->p8a.mt, L->p8a.est};
+                return launch_digit(Q8, ld, n, ld, &jm, &ja, L->st);
+            };
+        };
+        using ApplyT = decltype(make_apply(nullptr));
+        using LoopT = SweepLoop<ApplyT, decltype(none)>;
+        std::vector<ApplyT> applies;
+        applies.reserve(lanes.size());
+        std::vector<std::unique_ptr<LoopT>> loops;
+        rs = PSDP_OK;
+        for (auto &L : lanes) {
+            applies.push_back(make_apply(L.get()));
+            loops.emplace_back(new LoopT(*L->S, prm, L->tm, L->ta, L->ts, L->st, applies.back(), none));
+            if (rs == PSDP_OK) rs = loops.back()->init();
+        }
+        // the lanes in turn, one batch each: a lane's next batch is queued
+        // before its previous batch's counts are waited for
+        for (bool more = true; rs == PSDP_OK && more;) {
+            more = false;
+            for (auto &L : loops) {
+                if (L->finished) continue;
+                rs = L->advance();
+                if (rs != PSDP_OK) break;
+                more = more || !L->finished;
+            }
+        }
+        for (auto &L : loops) {
+            const psdp_status f = L->finish();
+            if (rs == PSDP_OK) rs = f;
+        }
+        for (auto &L : lanes) {
+            tm.add(L->tm);
+            ta.add(L->ta);
+            ts.add(L->ts);
+        }
     } else if (!batched) {
         // one column: the row-by-row GEMV, or the product from the unique
         // half of Q (packed upper tiles) once Q outgrows the caches
@@ -1058,8 +1200,9 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
                                 hipMemcpyDeviceToDevice, st));
     hcol.resize(B);
     HIPCHK(hipMemcpyAsync(hcol.data(), queued ? w.fin : w.col, B * sizeof(Col), hipMemcpyDeviceToHost, st));
-    int64_t nsweeps = 0;
+    int64_t nsweeps = 0, nsweeps1 = 0;
     HIPCHK(hipMemcpyAsync(&nsweeps, S.sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (S1) HIPCHK(hipMemcpyAsync(&nsweeps1, S1->sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     std::vector<ObjT> hobj;
     if (best) {
         hobj.resize(B);
@@ -1069,6 +1212,7 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         HIPCHK(hipMemcpyAsync(trace, w.trace, (size_t)B * trace_cap * 6 * sizeof(double),
                               hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    nsweeps = std::max(nsweeps, nsweeps1);
     if (best) {
         int32_t bi = 0;
         for (int c = 1; c < B; ++c)
@@ -1084,7 +1228,8 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
             aflops += apart ? 2.0 * (double)n * (double)n * (double)cc.aux : 0.0;
         }
         fill_stats(hcol, nsweeps, tm, flops, ta, aflops, ts, stats);
-        for (int64_t c = 0; c < B; ++c) stats[c].sparse_sweeps = S.sparse_sweeps;
+        const int64_t ssw = std::max(S.sparse_sweeps, S1 ? S1->sparse_sweeps : (int64_t)0);
+        for (int64_t c = 0; c < B; ++c) stats[c].sparse_sweeps = ssw;
     }
     return PSDP_OK;
 }
@@ -1122,6 +1267,7 @@ void psdp_params_default(psdp_params *p) {
     p->graph = 1;
     p->sparse = -1;
     p->gemv_sym = -1;
+    p->lanes = 0;
     p->lambda_reuse = 1;
     p->slots = 0;
     p->tol_kkt = 1e-5;

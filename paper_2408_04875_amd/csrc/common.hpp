@@ -71,7 +71,11 @@ struct Col {
 
 // Flat solver workspace (device pointers), passed to every solver kernel.
 struct Work {
-    int32_t ncol;
+    int32_t ncol;         // columns of the solve (index ncol: the all-zero operand column)
+    // the columns this launch sequence advances, [col_base, col_base + col_count)
+    // (a solve may run its columns as several concurrent sequences, each with
+    // its own live lists, counters and queue)
+    int32_t col_base, col_count;
     int32_t ksplit;      // number of U slices to sum (split-K)
     int64_t slice;       // elements per U slice
     Inst *inst;

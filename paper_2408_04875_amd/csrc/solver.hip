@@ -1062,10 +1062,10 @@ __device__ bool cg_step(const Work &w, Col &c, const ColView &cv, double *red) {
 template <int NT>
 __device__ void compact_lists(const Work &w) {
     __shared__ int32_t cnt[2][NT];
-    const int ncol = w.ncol;
+    const int ncol = w.col_count;
     const int chunk = (ncol + NT - 1) / NT;
-    const int lo = threadIdx.x * chunk;
-    const int hi = min(ncol, lo + chunk);
+    const int lo = w.col_base + threadIdx.x * chunk;
+    const int hi = min(w.col_base + ncol, lo + chunk);
     int my0 = 0, my1 = 0;
     for (int ci = lo; ci < hi; ++ci) {
         const int ph = __atomic_load_n(&w.col[ci].phase, __ATOMIC_RELAXED);
@@ -1162,7 +1162,7 @@ __device__ bool next_start(const Work &w, Col &c, const ColView &cv) {
 
 template <typename OpT, typename UT, int EPT, bool CI, int CE>
 __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
-    const int ci = blockIdx.x;
+    const int ci = w.col_base + (int)blockIdx.x;
     __shared__ Col c;
     __shared__ double red[12 * kSWaves];
     if (threadIdx.x == 0) c = w.col[ci];
@@ -1222,7 +1222,7 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
             }
         }
     }
-    if (ci == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.clear_cnt[0] = 0;
         w.clear_cnt[1] = 0;
         if (w.sweeps) *w.sweeps += 1;
@@ -1233,7 +1233,7 @@ __global__ void __launch_bounds__(kSB) solver_step_kernel(Work w) {
 // dimension n) and the first outer step, or the CG start x = 0, r = gamma - b.
 template <typename OpT, int EPT>
 __global__ void __launch_bounds__(kSB) solver_init_kernel(Work w, const double *X0, int use_cg) {
-    const int ci = blockIdx.x;
+    const int ci = w.col_base + (int)blockIdx.x;
     __shared__ Col c;
     __shared__ double red[12 * kSWaves];
     if (threadIdx.x == 0) c = w.col[ci];
@@ -1279,7 +1279,7 @@ __global__ void __launch_bounds__(kSB) compact_kernel(Work w) { compact_lists<kS
 
 template <typename OpT, typename UT, int EPT, bool CI, int CE>
 static hipError_t step_launch(const Work &w, hipStream_t st) {
-    hipLaunchKernelGGL((solver_step_kernel<OpT, UT, EPT, CI, CE>), dim3(w.ncol), dim3(kSB), 0, st, w);
+    hipLaunchKernelGGL((solver_step_kernel<OpT, UT, EPT, CI, CE>), dim3(w.col_count), dim3(kSB), 0, st, w);
     return hipGetLastError();
 }
 
@@ -1308,7 +1308,7 @@ hipError_t launch_solver_step(int optype, int utype, const Work &w, int64_t nmax
 
 template <typename OpT>
 static hipError_t init_launch(const Work &w, const double *X0, int use_cg, hipStream_t st) {
-    hipLaunchKernelGGL((solver_init_kernel<OpT, 4>), dim3(w.ncol), dim3(kSB), 0, st, w, X0, use_cg);
+    hipLaunchKernelGGL((solver_init_kernel<OpT, 4>), dim3(w.col_count), dim3(kSB), 0, st, w, X0, use_cg);
     return hipGetLastError();
 }
 
