@@ -505,6 +505,26 @@ def gemv_leg(P, gen, torch, dev, n=16384, outer=3):
                 "unit": "GB/s", "frac": products * unique / secs / 1e9 / PEAK_HBM_GBS if secs > 0 else 0.0,
                 "stored_gbs": products * stored / secs / 1e9 if secs > 0 else 0.0,
                 "note": "unique-half bytes of the products with a live column over the time of all product launches"}
+    # vendor yardstick: torch.mv (the vendor BLAS GEMV) on the same Q, full storage
+    Qf = Qd.to(torch.float32)
+    for qx, dt, eb in (("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2)):
+        A = Qf.to(dt)
+        v = x0[0].to(dt)
+        torch.mv(A, v)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            torch.mv(A, v)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[f"vendor_mv_{qx}"] = {"us": us, "stored_gbs": n * n * eb / us * 1e-3,
+                                  "unique_gbs": n * (n + 1) // 2 * eb / us * 1e-3,
+                                  "note": "torch.mv on the full matrix (vendor BLAS), events over 20 calls"}
+        del A
+    del Qf
     return out
 
 

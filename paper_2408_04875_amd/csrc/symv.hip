@@ -7,12 +7,13 @@
 // (bi, bj) with bi <= bj, each tile row-major and contiguous, in row-major
 // order of the upper triangle; entries past n are zero.
 //
-// A block (512 threads) reads one tile once and forms both of its
-// contributions: the direct one, tile x_bj, to rows bi*T.., and (off the
-// diagonal) the transposed one, tile^T x_bi, to rows bj*T... Thread t holds
-// 4 consecutive columns (t % 32) * 4 of rows t / 32 + 16 k (k < 8); a row's
-// direct sum is completed across its 32 lanes by a fixed butterfly, a
-// column's transposed sum across the 16 row groups through LDS in fixed
+// A block reads one tile once and forms both of its contributions: the
+// direct one, tile x_bj, to rows bi*T.., and (off the diagonal) the
+// transposed one, tile^T x_bi, to rows bj*T... Each thread holds a few
+// consecutive columns of a few rows spaced evenly through the tile (the
+// shape per storage type is SymShape below); a row's direct sum is
+// completed across the lanes of its row group by a fixed butterfly, a
+// column's transposed sum across the row groups through LDS in fixed
 // order. Every tile writes its two partial vectors to staging buffers, and a
 // second kernel adds them per row in a fixed order (symv_reduce_kernel):
 // the direct parts of the tiles (bi, bj >= bi), then the transposed parts
@@ -40,95 +41,132 @@ __global__ void __launch_bounds__(kBlock) symv_pack_kernel(const QT *Qop, int64_
     }
 }
 
-// Raw loads of 4 consecutive entries (kept in their storage type until used,
-// so that a thread holds its 8 rows in few registers) and their FP64 values.
-template <typename QT> struct Raw4;
-template <> struct Raw4<double> {
+// Raw loads of CW consecutive entries of one row (kept in their storage
+// type until used, so that a thread holds its 8 rows in few registers) and
+// their FP64 values.
+template <typename QT, int CW> struct RawRow;
+template <> struct RawRow<double, 4> {
     double2 a, b;
     __device__ __forceinline__ void load(const double *q) { a = *(const double2 *)q; b = *(const double2 *)(q + 2); }
     __device__ __forceinline__ double operator[](int u) const { return u == 0 ? a.x : u == 1 ? a.y : u == 2 ? b.x : b.y; }
 };
-template <> struct Raw4<float> {
+__device__ __forceinline__ double sym_f32(const float4 &a, int u) {
+    return (double)(u == 0 ? a.x : u == 1 ? a.y : u == 2 ? a.z : a.w);
+}
+template <> struct RawRow<float, 4> {
     float4 a;
     __device__ __forceinline__ void load(const float *q) { a = *(const float4 *)q; }
-    __device__ __forceinline__ double operator[](int u) const {
-        return (double)(u == 0 ? a.x : u == 1 ? a.y : u == 2 ? a.z : a.w);
-    }
+    __device__ __forceinline__ double operator[](int u) const { return sym_f32(a, u); }
 };
-template <> struct Raw4<__hip_bfloat16> {
+template <> struct RawRow<float, 8> {
+    float4 a, b;
+    __device__ __forceinline__ void load(const float *q) { a = *(const float4 *)q; b = *(const float4 *)(q + 4); }
+    __device__ __forceinline__ double operator[](int u) const { return u < 4 ? sym_f32(a, u) : sym_f32(b, u - 4); }
+};
+// a BF16 value is the high half of an FP32 word
+__device__ __forceinline__ double sym_bf16(uint32_t w, int odd) {
+    return (double)__uint_as_float(odd ? (w & 0xffff0000u) : (w << 16));
+}
+template <> struct RawRow<__hip_bfloat16, 4> {
     uint2 a;
     __device__ __forceinline__ void load(const __hip_bfloat16 *q) { a = *(const uint2 *)q; }
+    __device__ __forceinline__ double operator[](int u) const { return sym_bf16(u < 2 ? a.x : a.y, u & 1); }
+};
+template <> struct RawRow<__hip_bfloat16, 8> {
+    uint4 a;
+    __device__ __forceinline__ void load(const __hip_bfloat16 *q) { a = *(const uint4 *)q; }
     __device__ __forceinline__ double operator[](int u) const {
-        const uint32_t w = u < 2 ? a.x : a.y;
-        return (double)__uint_as_float((u & 1) ? (w & 0xffff0000u) : (w << 16));
+        return sym_bf16(u < 2 ? a.x : u < 4 ? a.y : u < 6 ? a.z : a.w, u & 1);
     }
 };
 
-constexpr int kSymThreads = 512;  // 16 row groups of 32 lanes; 8 rows per thread
+// Shape of the tile kernel by storage type: CW columns and R rows per
+// thread, in G = T / R row groups of L = T / CW lanes. FP32 and BF16 threads
+// hold 8 columns of 4 rows (32 or 16 bytes of a row per load), FP64 threads
+// 4 columns of 8 rows (32 bytes), so that the loads of a tile are issued at
+// once from few registers; the BF16 kernel is held to 5 waves per SIMD
+// (measured at n = 16384: 8 x 4 per thread read 1.3x faster than 4 x 8 in
+// both FP32 and BF16).
+template <typename QT> struct SymShape {
+    static constexpr int CW = sizeof(QT) == 8 ? 4 : 8;
+    static constexpr int R = sizeof(QT) == 8 ? 8 : 4;
+    static constexpr int L = kSymT / CW, G = kSymT / R, threads = L * G;
+    static constexpr int waves = sizeof(QT) == 2 ? 5 : 4;  // minimum per SIMD
+};
 
-// One block per tile (grid = the tile count): two blocks per CU.
+// One block per tile (grid = the tile count): lane l of row group g holds
+// columns l CW .. l CW + CW - 1 of rows g + G k (k < R).
 template <typename QT>
-__global__ void __launch_bounds__(kSymThreads) symv_tile_kernel(const QT *P, const int2 *tiles, int64_t ntiles,
-                                                                const double *x, int64_t ld, double *Dp, double *Tp,
-                                                                const int32_t *live) {
-    __shared__ double part[16][kSymT];
+__global__ void __launch_bounds__(SymShape<QT>::threads, SymShape<QT>::waves)
+    symv_tile_kernel(const QT *P, const int2 *tiles, int64_t ntiles, const double *x, int64_t ld, double *Dp,
+                     double *Tp, const int32_t *live) {
+    using S = SymShape<QT>;
+    constexpr int CW = S::CW, R = S::R, L = S::L, G = S::G;
+    static_assert(R >= 2 && R <= L && (R & (R - 1)) == 0 && L <= 64 && (L & (L - 1)) == 0, "tile kernel shape");
+    static_assert(S::threads >= 2 * kSymT, "one thread per output of the tile");
+    __shared__ double part[G][kSymT];
     __shared__ double dpart[kSymT];
     const int64_t t = blockIdx.x;
     if ((live && *live == 0) || t >= ntiles) return;
     const int2 bij = tiles[t];
     const int bi = bij.x, bj = bij.y;
-    const int tid = threadIdx.x, l = tid & 31, rg = tid >> 5;
-    const int c4 = l * 4;
+    const int tid = threadIdx.x, l = tid % L, rg = tid / L;
+    const int c0 = l * CW;
     const QT *tp = P + t * kSymT * kSymT;
-    // the thread's rows rg + 16 k of the tile: every load is issued first
-    Raw4<QT> q[8];
+    // the thread's rows of the tile: every load is issued first
+    RawRow<QT, CW> q[R];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) q[k].load(tp + (rg + 16 * k) * kSymT + c4);
-    double xj[4], xi[8];
+    for (int k = 0; k < R; ++k) q[k].load(tp + (rg + G * k) * kSymT + c0);
+    double xj[CW], xi[R];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t j = (int64_t)bj * kSymT + c4 + u;
+    for (int u = 0; u < CW; ++u) {
+        const int64_t j = (int64_t)bj * kSymT + c0 + u;
         xj[u] = j < ld ? x[j] : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int64_t i = (int64_t)bi * kSymT + rg + 16 * k;
+    for (int k = 0; k < R; ++k) {
+        const int64_t i = (int64_t)bi * kSymT + rg + G * k;
         xi[k] = i < ld ? x[i] : 0.0;
     }
-    double d[8], tc[4] = {0.0, 0.0, 0.0, 0.0};
+    double d[R], tc[CW];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double v0 = q[k][0], v1 = q[k][1], v2 = q[k][2], v3 = q[k][3];
-        d[k] = fma(v3, xj[3], fma(v2, xj[2], fma(v1, xj[1], v0 * xj[0])));
-        tc[0] = fma(v0, xi[k], tc[0]);
-        tc[1] = fma(v1, xi[k], tc[1]);
-        tc[2] = fma(v2, xi[k], tc[2]);
-        tc[3] = fma(v3, xi[k], tc[3]);
+    for (int u = 0; u < CW; ++u) tc[u] = 0.0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        double s = q[k][0] * xj[0];
+#pragma unroll
+        for (int u = 1; u < CW; ++u) s = fma(q[k][u], xj[u], s);
+        d[k] = s;
+#pragma unroll
+        for (int u = 0; u < CW; ++u) tc[u] = fma(q[k][u], xi[k], tc[u]);
     }
-    // direct sums: butterfly over the 32 lanes of a row group (offsets 16,
-    // 8, 4 halve the rows a lane holds, offsets 2 and 1 add the remaining
-    // lanes); lanes with equal bits 4..2 then hold row k = 4 b4 + 2 b3 + b2
+    // direct sums: butterfly over the L lanes of a row group. The offsets
+    // L/2, L/4, .. (log2 R of them) halve the rows a lane holds: at offset o
+    // a lane with bit o set keeps the upper half of its rows, one without
+    // the lower half, each adding its partner's copy. The smaller offsets
+    // then add the lanes that hold the same row, which is
+    // k = sum over those halving steps of bit(l, o) * (rows halved away).
+    int k = 0;
 #pragma unroll
-    for (int s = 0, off = 16; s < 3; ++s, off >>= 1) {
-        const int h = 4 >> s;
+    for (int h = R / 2, off = L / 2; h >= 1; h >>= 1, off >>= 1) {
         const bool up = (l & off) != 0;
+        if (up) k += h;
 #pragma unroll
-        for (int k = 0; k < h; ++k) {
-            const double send = up ? d[k] : d[k + h];
-            const double keep = up ? d[k + h] : d[k];
-            d[k] = keep + __shfl_xor(send, off, 64);
+        for (int r = 0; r < h; ++r) {
+            const double send = up ? d[r] : d[r + h];
+            const double keep = up ? d[r + h] : d[r];
+            d[r] = keep + __shfl_xor(send, off, 64);
         }
     }
-    d[0] = d[0] + __shfl_xor(d[0], 2, 64);
-    d[0] = d[0] + __shfl_xor(d[0], 1, 64);
-    const int k = ((l >> 4) & 1) * 4 + ((l >> 3) & 1) * 2 + ((l >> 2) & 1);
-    if ((l & 3) == 0) dpart[rg + 16 * k] = d[0];
+#pragma unroll
+    for (int off = L / (2 * R); off >= 1; off >>= 1) d[0] = d[0] + __shfl_xor(d[0], off, 64);
+    if (l % (L / R) == 0) dpart[rg + G * k] = d[0];
     // transposed sums (off the diagonal: a diagonal tile holds both
-    // triangles, so its direct part is its whole product): the 16 row
-    // groups of each column, in group order
+    // triangles, so its direct part is its whole product): the G row groups
+    // of each column, in group order
     if (bi != bj) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) part[rg][c4 + u] = tc[u];
+        for (int u = 0; u < CW; ++u) part[rg][c0 + u] = tc[u];
     }
     __syncthreads();
     if (tid < kSymT) {
@@ -137,7 +175,7 @@ __global__ void __launch_bounds__(kSymThreads) symv_tile_kernel(const QT *P, con
         const int c = tid - kSymT;
         double sm = part[0][c];
 #pragma unroll
-        for (int g = 1; g < 16; ++g) sm += part[g][c];
+        for (int g = 1; g < G; ++g) sm += part[g][c];
         Tp[t * kSymT + c] = sm;
     }
 }
@@ -233,13 +271,13 @@ hipError_t launch_symv(int dtype, const SymTiles &s, const double *x, int64_t ld
                        hipStream_t st) {
     const unsigned grid = (unsigned)s.ntiles;
     if (dtype == PSDP_F64)
-        hipLaunchKernelGGL(symv_tile_kernel<double>, dim3(grid), dim3(kSymThreads), 0, st,
+        hipLaunchKernelGGL(symv_tile_kernel<double>, dim3(grid), dim3(SymShape<double>::threads), 0, st,
                            (const double *)s.P, s.tiles, s.ntiles, x, ld, s.D, s.T, s.live);
     else if (dtype == PSDP_F32)
-        hipLaunchKernelGGL(symv_tile_kernel<float>, dim3(grid), dim3(kSymThreads), 0, st,
+        hipLaunchKernelGGL(symv_tile_kernel<float>, dim3(grid), dim3(SymShape<float>::threads), 0, st,
                            (const float *)s.P, s.tiles, s.ntiles, x, ld, s.D, s.T, s.live);
     else if (dtype == PSDP_BF16)
-        hipLaunchKernelGGL(symv_tile_kernel<__hip_bfloat16>, dim3(grid), dim3(kSymThreads), 0, st,
+        hipLaunchKernelGGL(symv_tile_kernel<__hip_bfloat16>, dim3(grid), dim3(SymShape<__hip_bfloat16>::threads), 0, st,
                            (const __hip_bfloat16 *)s.P, s.tiles, s.ntiles, x, ld, s.D, s.T, s.live);
     else
         return hipErrorInvalidValue;
