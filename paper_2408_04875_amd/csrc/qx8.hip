@@ -242,8 +242,9 @@ __device__ __forceinline__ void digit_body(const DigitArgs &da, int L) {
 
 // Many-column layout with the digit tile in LDS: the block's 4 waves own 4
 // consecutive 16 NT-row blocks of Q and share MT digit tiles, which the whole
-// block copies into LDS once per K step of 64 (double-buffered, rows padded
-// to 80 bytes so that the 16-byte fragment reads do not collide in banks).
+// block copies into LDS once per K step of 64 (double-buffered, in the
+// swizzled layout of digit_lds_off so that neither the copies nor the
+// 16-byte fragment reads collide in banks).
 // Each wave then loads only its own Q rows from global memory. The digit
 // pieces and Q rows of the next four K steps are in flight in registers
 // while the current step multiplies. MT must be a multiple of 4 (each thread
@@ -253,11 +254,21 @@ template <int MT, int NT, int PF = 4> struct DigitLdsShape {
     static constexpr int kRows = 4 * 16 * NT;
 };
 
+// Byte offset of 16-byte chunk c of digit row r in an LDS stage: rows of 64
+// bytes, chunk c stored at slot c ^ ((r >> 1) & 3). Of the layouts measured
+// on gfx950 with the LDS bank-conflict counter (row strides 64 to 256 bytes,
+// several XOR swizzles) this is the one whose fragment reads (lane: row
+// l % 16, chunk l / 16) and tile writes (lane: row l / 4, chunk l % 4) both
+// count no conflict cycles; the former 80-byte padded rows counted 3.8 per
+// read and 8.0 per write instruction.
+__device__ __forceinline__ int digit_lds_off(int r, int c) { return r * 64 + 16 * (c ^ ((r >> 1) & 3)); }
+constexpr int kDigitLdsRow = 64;
+
 template <int D, typename S>
 __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
     constexpr int MT = S::kMT, NT = S::kNT, PC = MT / 4;
     constexpr int RA = 16 * MT, CA = RA / D;
-    constexpr int ROWB = 80;
+    constexpr int ROWB = kDigitLdsRow;
     static_assert(MT % 4 == 0, "MT must be a multiple of 4");
     __shared__ __attribute__((aligned(16))) int8_t As[2][RA * ROWB];
     if (L >= da.AG * da.IB * da.KS) return;
@@ -302,7 +313,7 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
             const int r = pce >> 2, cb = pce & 3;
             const int64_t c = (ag * RA + r) / D < nact ? (int64_t)cr[q] : (int64_t)da.zero_col;
             af[q] = da.dig + (c * D + ((ag * RA + r) % D)) * ldq + 16 * cb;
-            ao[q] = r * ROWB + 16 * cb;
+            ao[q] = digit_lds_off(r, cb);
         }
         intx4 acc[MT][NT];
 #pragma unroll
@@ -346,7 +357,7 @@ __device__ __forceinline__ void digit_body_lds(const DigitArgs &da, int L) {
                 if (refill) issue(ra[u], rb[u], snext);
                 intx4 a[MT];
 #pragma unroll
-                for (int s = 0; s < MT; ++s) a[s] = *(const intx4 *)&As[u & 1][(s * 16 + m) * ROWB + 16 * g];
+                for (int s = 0; s < MT; ++s) a[s] = *(const intx4 *)&As[u & 1][digit_lds_off(s * 16 + m, g)];
 #pragma unroll
                 for (int s = 0; s < MT; ++s)
 #pragma unroll
