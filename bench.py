@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--slots", type=int, default=1024,
                     help="solve the timed steps' start sets as one queued launch with this many columns "
                          "(0: one launch per start set)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes of the queued integer-product solve (psdp_params.lanes; 0: the library's choice)")
     ap.add_argument("--no-per-set", action="store_true",
                     help="skip the comparison with one launch per start set")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -617,7 +619,8 @@ def main():
     torch.cuda.synchronize()
 
     def step(qx, timing=False, X=None, slots=0):
-        return P.solve(Qd, bd, X0=X0d if X is None else X, qx_dtype=qx, timing=1 if timing else 0, slots=slots)
+        return P.solve(Qd, bd, X0=X0d if X is None else X, qx_dtype=qx, timing=1 if timing else 0, slots=slots,
+                       lanes=args.lanes)
 
     class SetView:
         """One start set's share of a queued launch (the fields used below)."""

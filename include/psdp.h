@@ -124,11 +124,12 @@ typedef struct {
                                   columns and queues the other starts in index order, a column
                                   taking the next start when its own ends (each start performs the
                                   same arithmetic either way; outputs stay per start) */
-    int32_t lanes;             /* batched solves with integer products: 2 runs the columns as two
-                                  lanes, concurrent launch sequences on two streams, each over half
-                                  the columns and half the starts (each start performs the same
-                                  arithmetic either way); 1 one sequence; 0 (default) two from 512
-                                  columns on */
+    int32_t lanes;             /* batched solves with integer products: L = 2 to 4 runs the
+                                  columns as L lanes, concurrent launch sequences on L streams,
+                                  each over 1/L of the columns and of the starts (each start
+                                  performs the same arithmetic either way); 1 one sequence; 0
+                                  (default) two from 512 columns on. Values outside 0..4 are
+                                  rejected (PSDP_E_INVALID) */
     int32_t gemv_sym;          /* single-instance solves (B = 1, floating-point operands): 1 reads
                                   Q from its unique half, stored as 128 x 128 upper tiles (each tile
                                   read once for its row and column contributions, partial sums

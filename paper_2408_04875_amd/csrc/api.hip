@@ -48,8 +48,9 @@ int64_t padld(int64_t n) { return (n + 31) / 32 * 32; }
 constexpr int64_t kSymAutoN = 4096;
 
 // Batched integer-product solves with at least this many columns run them as
-// two lanes (psdp_params.lanes = 0).
+// two lanes (psdp_params.lanes = 0); at most kMaxLanes lanes.
 constexpr int kLaneAutoCols = 512;
+constexpr int kMaxLanes = 4;
 
 // Every list and every operand buffer that the product kernels read through
 // a list holds zero_col + 1 columns: an empty list slot names zero_col.
@@ -160,7 +161,7 @@ psdp_status check_params(const psdp_params &p) {
         return fail(PSDP_E_INVALID, "params: tolerance out of range");
     if (p.sparse < -1 || p.sparse > 1) return fail(PSDP_E_INVALID, "params.sparse must be -1, 0 or 1");
     if (p.gemv_sym < -1 || p.gemv_sym > 1) return fail(PSDP_E_INVALID, "params.gemv_sym must be -1, 0 or 1");
-    if (p.lanes < 0 || p.lanes > 2) return fail(PSDP_E_INVALID, "params.lanes must be 0, 1 or 2");
+    if (p.lanes < 0 || p.lanes > kMaxLanes) return fail(PSDP_E_INVALID, "params.lanes must be 0 (automatic) to 4");
     if (p.lambda_reuse < 0 || p.lambda_reuse > 1) return fail(PSDP_E_INVALID, "params.lambda_reuse must be 0 or 1");
     if (p.slots < 0) return fail(PSDP_E_INVALID, "params.slots must be >= 0");
     if (p.sparse == 1 && p.qx_dtype != PSDP_I8)
@@ -862,10 +863,10 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         if (!batched) return Pick{false, 4, 1, std::min({ncol, ncols + 16, live})};
         return pick_product(ncol, ncols, live, gemm_dtype, prm.gemm_variant, MT);
     };
-    // Integer path: the columns may run as two lanes, concurrent launch
-    // sequences on two streams, each over half the columns and half the
-    // starts with its own live lists, counters and queue (the step kernels of
-    // one lane then overlap the products of the other). Every start performs
+    // Integer path: the columns may run as up to four lanes, concurrent
+    // launch sequences on as many streams, each over its share of the columns
+    // and of the starts with its own live lists, counters and queue (the step
+    // kernels of one lane then overlap the products of another). Every start performs
     // the same arithmetic in any lane. Each lane picks its products' layouts
     // from its estimated live counts and their K slices from the blocks of
     // both products (they share one launch).
@@ -878,25 +879,33 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         hipStream_t st = nullptr;
         QxTimer tm, ta, ts;
     };
-    const int nlanes = (i8 && ncol >= 2 && (prm.lanes == 2 || (prm.lanes == 0 && ncol >= kLaneAutoCols))) ? 2 : 1;
-    const int nc0 = nlanes == 2 ? ncol / 2 : ncol, nc1 = ncol - nc0;
-    // lane 0 takes starts [0, B0), lane 1 [B0, B); each range holds at least
-    // the lane's columns
-    const int32_t B0 = nlanes == 2 ? std::max<int32_t>(nc0, std::min<int32_t>(B - nc1, (int32_t)(((int64_t)B * nc0 +
-                                                                                             ncol / 2) / ncol)))
-                                   : B;
-    std::unique_ptr<Solver> S1;
-    if (nlanes == 2) S1.reset(new Solver());
+    const int want = prm.lanes == 0 ? (ncol >= kLaneAutoCols ? 2 : 1) : prm.lanes;
+    const int nlanes = i8 ? std::max(1, std::min({want, kMaxLanes, ncol})) : 1;
+    // lane l runs columns [cb[l], cb[l + 1]) over starts [sb[l], sb[l + 1]):
+    // start ranges in proportion to the columns, each holding at least its
+    // lane's columns
+    std::vector<int32_t> cb(nlanes + 1), sb(nlanes + 1);
+    for (int l = 0; l <= nlanes; ++l) cb[l] = (int32_t)((int64_t)ncol * l / nlanes);
+    sb[0] = 0;
+    sb[nlanes] = B;
+    for (int l = 1; l < nlanes; ++l) {
+        const int32_t lo = sb[l - 1] + (cb[l] - cb[l - 1]), hi = B - (ncol - cb[l]);
+        const int32_t prop = (int32_t)(((int64_t)B * cb[l] + ncol / 2) / ncol);
+        sb[l] = std::max(lo, std::min(hi, prop));
+    }
+    const int32_t nc0 = cb[1];
+    std::vector<std::unique_ptr<Solver>> extra;
     std::vector<std::unique_ptr<Lane>> lanes;
     for (int l = 0; l < nlanes; ++l) {
+        if (l > 0) {
+            extra.emplace_back(new Solver());
+            extra.back()->rowptr = S.rowptr;
+            extra.back()->pk = S.pk;
+            extra.back()->nnz = S.nnz;
+        }
         lanes.emplace_back(new Lane());
-        lanes[l]->S = l == 0 ? &S : S1.get();
-        lanes[l]->ncols = l == 0 ? nc0 : nc1;
-    }
-    if (S1) {
-        S1->rowptr = S.rowptr;
-        S1->pk = S.pk;
-        S1->nnz = S.nnz;
+        lanes[l]->S = l == 0 ? &S : extra.back().get();
+        lanes[l]->ncols = cb[l + 1] - cb[l];
     }
     auto pick8 = [&](Lane &L, int cm, int ca) {
         L.p8m.est = std::min({L.ncols, cm + 16, cm + ca});
@@ -927,7 +936,9 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         cc.off = (int64_t)c * ld;
         cc.ioff = 0;
         cc.id = c;
-        cc.start = c < nc0 ? c : B0 + (c - nc0);
+        int l = 0;
+        while (c >= cb[l + 1]) ++l;
+        cc.start = sb[l] + (c - cb[l]);
         cc.phase = PH_INNER;  // placeholder, set by the init kernel
     }
     HIPCHK(S.ar.get((void **)&w.col, ncol * sizeof(Col)));
@@ -935,14 +946,14 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
     hipLaunchKernelGGL(fill_p_kernel, dim3((unsigned)((ld * ncol + 255) / 256)), dim3(256), 0, st, w.p, p0, n,
                        ld, ncol);
     if (queued) {
-        S.rounds = (B0 + nc0 - 1) / nc0;
+        S.rounds = (sb[1] + nc0 - 1) / nc0;
         int32_t *q;
         HIPCHK(S.ar.get((void **)&q, 64));
         HIPCHK(hipMemcpyAsync(q, &nc0, sizeof(int32_t), hipMemcpyHostToDevice, st));
         HIPCHK(S.ar.get((void **)&w.xfin, (size_t)n * B * sizeof(double)));
         HIPCHK(S.ar.get((void **)&w.fin, (size_t)B * sizeof(Col)));
         w.queue = q;
-        w.nstart = B0;
+        w.nstart = sb[1];
         w.X0 = X0;
         w.p0 = p0;
     }
@@ -968,10 +979,11 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         HIPCHK(hipMemsetAsync(w.phase_prof, 0, 16 * sizeof(unsigned long long), st));
     }
     lanes[0]->st = st;
-    if (S1) {
-        // lane 1: the shared buffers and parameters, its own lists, counters,
-        // sweep counter and queue, and columns [nc0, ncol)
-        Solver &LS = *S1;
+    for (int l = 1; l < nlanes; ++l) {
+        // lane l: the shared buffers and parameters, its own lists,
+        // counters, sweep counter and queue, and columns [cb[l], cb[l + 1])
+        Solver &LS = *lanes[l]->S;
+        const int32_t ncl = cb[l + 1] - cb[l];
         LS.w = w;
         LS.optype = S.optype;
         LS.utype = S.utype;
@@ -987,31 +999,31 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         HIPCHK(hipMemsetAsync(LS.sweeps, 0, 64, st));
         LS.w.sweeps = LS.sweeps;
         set_parity(LS, 0);
-        LS.w.col_base = nc0;
-        LS.w.col_count = nc1;
+        LS.w.col_base = cb[l];
+        LS.w.col_count = ncl;
         if (queued) {
-            const int32_t q1v = B0 + nc1;
-            int32_t *q1;
-            HIPCHK(S.ar.get((void **)&q1, 64));
-            HIPCHK(hipMemcpyAsync(q1, &q1v, sizeof(int32_t), hipMemcpyHostToDevice, st));
-            LS.w.queue = q1;
-            LS.w.nstart = B;
-            LS.rounds = (B - B0 + nc1 - 1) / nc1;
+            const int32_t qv = sb[l] + ncl;
+            int32_t *ql;
+            HIPCHK(S.ar.get((void **)&ql, 64));
+            HIPCHK(hipMemcpyAsync(ql, &qv, sizeof(int32_t), hipMemcpyHostToDevice, st));
+            LS.w.queue = ql;
+            LS.w.nstart = sb[l + 1];
+            LS.rounds = (sb[l + 1] - sb[l] + ncl - 1) / ncl;
         }
-        w.col_count = nc0;
-        HIPCHK(solve_stream(&lanes[1]->st, 1));
+        HIPCHK(solve_stream(&lanes[l]->st, l));
     }
+    w.col_count = nc0;
     for (auto &L : lanes) {
         HIPCHK(launch_solver_init(S.optype, L->S->w, X0, X0 ? 0 : 1, st));
         HIPCHK(launch_compact(L->S->w, st));
         L->tm.on = L->ta.on = L->ts.on = prm.timing != 0;
     }
-    if (S1) {
-        // lane 1 starts once the set-up on the first stream is done
+    if (nlanes > 1) {
+        // the other lanes start once the set-up on the first stream is done
         hipEvent_t ready;
         HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
         hipError_t e = hipEventRecord(ready, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(lanes[1]->st, ready, 0);
+        for (int l = 1; l < nlanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(lanes[l]->st, ready, 0);
         (void)hipEventDestroy(ready);
         HIPCHK(e);
     }
@@ -1200,9 +1212,10 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
                                 hipMemcpyDeviceToDevice, st));
     hcol.resize(B);
     HIPCHK(hipMemcpyAsync(hcol.data(), queued ? w.fin : w.col, B * sizeof(Col), hipMemcpyDeviceToHost, st));
-    int64_t nsweeps = 0, nsweeps1 = 0;
-    HIPCHK(hipMemcpyAsync(&nsweeps, S.sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    if (S1) HIPCHK(hipMemcpyAsync(&nsweeps1, S1->sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    std::vector<int64_t> lane_sweeps(1 + extra.size(), 0);
+    HIPCHK(hipMemcpyAsync(&lane_sweeps[0], S.sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    for (size_t l = 0; l < extra.size(); ++l)
+        HIPCHK(hipMemcpyAsync(&lane_sweeps[l + 1], extra[l]->sweeps, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     std::vector<ObjT> hobj;
     if (best) {
         hobj.resize(B);
@@ -1212,7 +1225,7 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         HIPCHK(hipMemcpyAsync(trace, w.trace, (size_t)B * trace_cap * 6 * sizeof(double),
                               hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    nsweeps = std::max(nsweeps, nsweeps1);
+    const int64_t nsweeps = *std::max_element(lane_sweeps.begin(), lane_sweeps.end());
     if (best) {
         int32_t bi = 0;
         for (int c = 1; c < B; ++c)
@@ -1228,7 +1241,8 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
             aflops += apart ? 2.0 * (double)n * (double)n * (double)cc.aux : 0.0;
         }
         fill_stats(hcol, nsweeps, tm, flops, ta, aflops, ts, stats);
-        const int64_t ssw = std::max(S.sparse_sweeps, S1 ? S1->sparse_sweeps : (int64_t)0);
+        int64_t ssw = S.sparse_sweeps;
+        for (const auto &X : extra) ssw = std::max(ssw, X->sparse_sweeps);
         for (int64_t c = 0; c < B; ++c) stats[c].sparse_sweeps = ssw;
     }
     return PSDP_OK;

@@ -66,7 +66,8 @@ def test_invalid_arguments_fail_before_device_work(lib):
     st = lib.psdp_solve_i32(dummy, dummy, 4, None, None, 1, ctypes.byref(wrong), dummy, dummy, None, None,
                             None, None)
     assert st == -1 and "struct_size" in lib.psdp_last_error().decode()
-    for kw, code, word in ((dict(sparse=2), -1, "sparse"), (dict(sparse=1, qx_dtype="f64"), -7, "I8")):
+    for kw, code, word in ((dict(sparse=2), -1, "sparse"), (dict(sparse=1, qx_dtype="f64"), -7, "I8"),
+                           (dict(lanes=5), -1, "lanes"), (dict(lanes=-1), -1, "lanes")):
         sp = binding.default_params(**kw)
         st = lib.psdp_solve_i32(dummy, dummy, 4, None, None, 1, ctypes.byref(sp), dummy, dummy, None, None,
                                 None, None)

@@ -1,7 +1,7 @@
 """Queued starts (psdp_params.slots): fewer columns than starts, a column
 taking the next start when its own ends; and lanes (psdp_params.lanes):
-the columns run as two concurrent launch sequences over halves of the
-columns and starts. Every start performs the same
+the columns run as two to four concurrent launch sequences over shares of
+the columns and starts. Every start performs the same
 arithmetic as in a launch where it has its own column (the columns are
 independent and every reduction has a fixed order), so the results of each
 start must be identical bit for bit: final iterate, rounded point,
@@ -76,25 +76,27 @@ def test_queued_starts_full_size(P):
           f"{q.stats[0]['sweeps']}", flush=True)
 
 
+@pytest.mark.parametrize("lanes", [2, 3, 4])
 @pytest.mark.parametrize("slots", [0, 6, 9])
-def test_two_lanes_equal_one_lane(P, slots):
-    """Two lanes (each with half the columns and half the starts, its own
-    lists, queue and stream) against one, with and without queued starts:
-    every start identical bit for bit."""
+def test_lanes_equal_one_lane(P, slots, lanes):
+    """Two to four lanes (each with its share of the columns and of the
+    starts, its own lists, queue and stream) against one, with and without
+    queued starts: every start identical bit for bit."""
     Q, b, X0 = gen.sparse_2500_starts(n=300, B=24)
     one = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", trace_cap=60, slots=slots, lanes=1)
-    two = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", trace_cap=60, slots=slots, lanes=2)
-    _same(two, one)
+    many = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", trace_cap=60, slots=slots, lanes=lanes)
+    _same(many, one)
 
 
-def test_two_lanes_full_size_queued(P):
-    """512 starts of the n = 2500 workload through 512 columns in two lanes
-    against the same starts with a column each (two launches of 256)."""
+@pytest.mark.parametrize("lanes", [2, 4])
+def test_lanes_full_size_queued(P, lanes):
+    """512 starts of the n = 2500 workload through 300 columns in two or four
+    lanes against the same starts with a column each (two launches of 256)."""
     Q, b, X0 = gen.sparse_2500_starts(B=512)
     halves = [P.solve(_t(Q), _t(b), X0=_t(X0[h * 256:(h + 1) * 256]), qx_dtype="i8") for h in range(2)]
-    q = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", slots=300, lanes=2)
+    q = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", slots=300, lanes=lanes)
     obj = np.concatenate([h.obj.cpu().numpy() for h in halves])
     assert np.array_equal(q.obj.cpu().numpy(), obj)
     assert np.array_equal(q.X.cpu().numpy(), np.concatenate([h.X.cpu().numpy() for h in halves]))
     assert [s["inner_iters"] for s in q.stats] == [s["inner_iters"] for h in halves for s in h.stats]
-    print(f"512 starts, two lanes of 150 columns: {q.stats[0]['sweeps']} sweeps", flush=True)
+    print(f"512 starts, {lanes} lanes of {300 // lanes} columns: {q.stats[0]['sweeps']} sweeps", flush=True)
