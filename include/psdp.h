@@ -130,12 +130,14 @@ typedef struct {
                                   performs the same arithmetic either way); 1 one sequence; 0
                                   (default) two from 512 columns on. Values outside 0..4 are
                                   rejected (PSDP_E_INVALID) */
-    int32_t gemv_sym;          /* single-instance solves (B = 1, floating-point operands): 1 reads
-                                  Q from its unique half, stored as 128 x 128 upper tiles (each tile
-                                  read once for its row and column contributions, partial sums
-                                  added in a fixed order); 0 reads full rows; -1 (default) takes the
-                                  tiles from n = 4096 on. Both are FP64 sums of exact products;
-                                  they differ in summation order only */
+    int32_t gemv_sym;          /* single-instance and group solves (one column per instance,
+                                  floating-point operands): 1 reads Q from its unique half, stored
+                                  as 128 x 128 upper tiles (each tile read once for its row and
+                                  column contributions, partial sums added in a fixed order, the
+                                  same in both); 0 reads full rows; -1 (default) takes the tiles
+                                  from n = 4096 on, and in a group also once the stored matrices
+                                  reach 256 MiB. Both are FP64 sums of exact products; they differ
+                                  in summation order only */
     double tol_kkt;            /* delta of eq. (cret) (1e-5) */
     double tol_binary;         /* Algorithm 3 loop tolerance (1e-5) */
     double eta;                /* eq. (alpha1) scaling, 0 < eta < 1 (0.999) */

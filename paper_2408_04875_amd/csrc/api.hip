@@ -46,6 +46,10 @@ int64_t padld(int64_t n) { return (n + 31) / 32 * 32; }
 // Single-instance solves from this n on read Q from its packed upper tiles
 // (psdp_params.gemv_sym = -1).
 constexpr int64_t kSymAutoN = 4096;
+// Group solves read the Q_i from their packed upper tiles once the stored
+// matrices together reach the size of the Infinity Cache, or an instance
+// reaches kSymAutoN (gemv_sym = -1).
+constexpr int64_t kSymAutoGroupBytes = 256ll << 20;
 
 // Batched integer-product solves with at least this many columns run them as
 // two lanes (psdp_params.lanes = 0); at most kMaxLanes lanes.
@@ -1463,6 +1467,77 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     int32_t *dunit;
     HIPCHK(S.ar.get((void **)&dunit, unitcol.size() * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(dunit, unitcol.data(), unitcol.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    // The product from the unique halves of the Q_i (packed 128 x 128 upper
+    // tiles, each read once for its row and column parts; the same tile and
+    // reduction order as the single-instance product, so each instance's
+    // result equals its single-instance tile product) by the rule above or
+    // when asked for (psdp_params.gemv_sym); otherwise the row-by-row group
+    // GEMV.
+    int64_t stored = 0;
+    for (int i = 0; i < count; ++i) stored += ld[i] * ld[i] * esize(prm.qx_dtype);
+    std::vector<int64_t> tbase(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        const int64_t nb = symv_blocks(n[i]);
+        tbase[i + 1] = tbase[i] + nb * (nb + 1) / 2;
+    }
+    const bool sym = (prm.gemv_sym == 1 ||
+                      (prm.gemv_sym == -1 && (stored >= kSymAutoGroupBytes || S.nmax >= kSymAutoN))) &&
+                     tbase[count] < INT32_MAX;
+    SymGroup sg{};
+    std::vector<SymGroupTile> hlist;
+    std::vector<SymGroupRow> hrows;
+    std::map<int, std::vector<int32_t>> tile_lists;  // per tile-row count; kept until the copies are done
+    auto build_sym = [&](const std::vector<int32_t> &ids) {
+        hlist.clear();
+        hrows.clear();
+        for (int32_t id : ids) {
+            const int nb = symv_blocks(n[id]);
+            int32_t t = (int32_t)tbase[id];
+            for (int bi = 0; bi < nb; ++bi) {
+                for (int bj = bi; bj < nb; ++bj) hlist.push_back(SymGroupTile{t++, id, bi, bj, off[id], ld[id]});
+                hrows.push_back(SymGroupRow{id, bi, off[id], n[id], tbase[id]});
+            }
+        }
+    };
+    SymGroupTile *dlist = nullptr;
+    SymGroupRow *drows = nullptr;
+    if (sym) {
+        const int64_t ntot = tbase[count];
+        void *P;
+        HIPCHK(S.ar.get(&P, ntot * 128 * 128 * esize(prm.qx_dtype)));
+        HIPCHK(S.ar.get((void **)&sg.D, ntot * 128 * sizeof(double)));
+        HIPCHK(S.ar.get((void **)&sg.T, ntot * 128 * sizeof(double)));
+        std::map<int, int2 *> dtiles;
+        for (int i = 0; i < count; ++i) {
+            const int nb = symv_blocks(n[i]);
+            if (!dtiles.count(nb)) {
+                std::vector<int32_t> &tl = tile_lists[nb];
+                tl = symv_tile_list(nb);
+                int2 *d;
+                HIPCHK(S.ar.get((void **)&d, tl.size() * sizeof(int32_t)));
+                HIPCHK(hipMemcpyAsync(d, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+                dtiles[nb] = d;
+            }
+            SymTiles ti{};
+            ti.P = (const char *)P + tbase[i] * 128 * 128 * esize(prm.qx_dtype);
+            ti.tiles = dtiles[nb];
+            ti.nb = nb;
+            ti.ntiles = (int64_t)nb * (nb + 1) / 2;
+            HIPCHK(launch_symv_pack(prm.qx_dtype, hin[i].Qop, ld[i], ti, st));
+        }
+        std::vector<int32_t> all(count);
+        for (int i = 0; i < count; ++i) all[i] = i;
+        build_sym(all);
+        HIPCHK(S.ar.get((void **)&dlist, hlist.size() * sizeof(SymGroupTile)));
+        HIPCHK(S.ar.get((void **)&drows, hrows.size() * sizeof(SymGroupRow)));
+        HIPCHK(hipMemcpyAsync(dlist, hlist.data(), hlist.size() * sizeof(SymGroupTile), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(drows, hrows.data(), hrows.size() * sizeof(SymGroupRow), hipMemcpyHostToDevice, st));
+        sg.P = P;
+        sg.list = dlist;
+        sg.nlist = (int64_t)hlist.size();
+        sg.rows = drows;
+        sg.nrows = (int64_t)hrows.size();
+    }
     HIPCHK(launch_solver_init(S.optype, w, nullptr, 1, st));
     HIPCHK(launch_compact(w, st));
     // Work list of the live instances only: once a poll finds at most 3/4 of
@@ -1490,8 +1565,19 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
         hipError_t e = hipMemcpyAsync(drow, rsv.data(), (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(dunit, unitcol.data(), u * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        if (sym) {
+            build_sym(ids);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(dlist, hlist.data(), hlist.size() * sizeof(SymGroupTile), hipMemcpyHostToDevice,
+                                   st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(drows, hrows.data(), hrows.size() * sizeof(SymGroupRow), hipMemcpyHostToDevice,
+                                   st);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vectors are consumed
         if (e != hipSuccess) return e;
+        sg.nlist = (int64_t)hlist.size();
+        sg.nrows = (int64_t)hrows.size();
         live_units = u;
         last_live = cnt;
         ++list_gen;
@@ -1501,7 +1587,11 @@ psdp_status psdp_solve_group_i32(int32_t count, const int64_t *n, const int32_t 
     QxTimer tm, ta, ts;
     tm.on = ts.on = prm.timing != 0;
     psdp_status rs = run_sweeps(
-        S, prm, tm, ta, ts, st, [&]() { return launch_gemv_group(prm.qx_dtype, w, drow, dunit, live_units, st); },
+        S, prm, tm, ta, ts, st,
+        [&]() {
+            return sym ? launch_symv_group(prm.qx_dtype, sg, w, st)
+                       : launch_gemv_group(prm.qx_dtype, w, drow, dunit, live_units, st);
+        },
         []() { return hipSuccess; });
     if (rs != PSDP_OK) return rs;
     int64_t maxblk = 0;

@@ -132,12 +132,34 @@ struct SymTiles {
     double *D, *T;        // staging: the direct and transposed partial vectors, ntiles x 128 each
     const int32_t *live;  // nullable: the live count; nothing runs when it is 0
 };
-int symv_blocks(int64_t n);
+__host__ __device__ int symv_blocks(int64_t n);
 std::vector<int32_t> symv_tile_list(int nb);
 int64_t symv_packed_elems(int nb);
 hipError_t launch_symv_pack(int dtype, const void *Qop, int64_t ld, const SymTiles &s, hipStream_t st);
 hipError_t launch_symv(int dtype, const SymTiles &s, const double *x, int64_t ld, int64_t n, double *y,
                        hipStream_t st);
+// Group product from the unique halves: the packed tiles of every instance
+// (each instance's tiles from its first tile index on, in the order of
+// symv_tile_list), a work list over the live instances' tiles and one over
+// their tile rows; staging indexed by the global tile. Finished columns'
+// entries store nothing.
+struct SymGroupTile {
+    int32_t t, col, bi, bj;  // global tile index, column, tile position
+    int64_t off, ld;         // the column's vector offset and leading dimension
+};
+struct SymGroupRow {
+    int32_t col, bi;         // column, tile row
+    int64_t off, n, base;    // vector offset, size, first tile index of the column
+};
+struct SymGroup {
+    const void *P;
+    const SymGroupTile *list;
+    int64_t nlist;
+    const SymGroupRow *rows;
+    int64_t nrows;
+    double *D, *T;
+};
+hipError_t launch_symv_group(int dtype, const SymGroup &g, const Work &w, hipStream_t st);
 
 // Solver kernels.
 hipError_t launch_solver_init(int optype, const Work &w, const double *X0, int use_cg,

@@ -94,25 +94,21 @@ template <typename QT> struct SymShape {
     static constexpr int waves = sizeof(QT) == 2 ? 5 : 4;  // minimum per SIMD
 };
 
-// One block per tile (grid = the tile count): lane l of row group g holds
-// columns l CW .. l CW + CW - 1 of rows g + G k (k < R).
+// The products of one tile tp = (bi, bj) by one block: lane l of row group g
+// holds columns l CW .. l CW + CW - 1 of rows g + G k (k < R); the direct
+// part goes to Do, the transposed part (off the diagonal) to To, T entries
+// each. x holds ld entries (ld >= the instance's n, zero padded).
 template <typename QT>
-__global__ void __launch_bounds__(SymShape<QT>::threads, SymShape<QT>::waves)
-    symv_tile_kernel(const QT *P, const int2 *tiles, int64_t ntiles, const double *x, int64_t ld, double *Dp,
-                     double *Tp, const int32_t *live) {
+__device__ __forceinline__ void sym_tile_body(const QT *tp, int bi, int bj, const double *x, int64_t ld, double *Do,
+                                              double *To) {
     using S = SymShape<QT>;
     constexpr int CW = S::CW, R = S::R, L = S::L, G = S::G;
     static_assert(R >= 2 && R <= L && (R & (R - 1)) == 0 && L <= 64 && (L & (L - 1)) == 0, "tile kernel shape");
     static_assert(S::threads >= 2 * kSymT, "one thread per output of the tile");
     __shared__ double part[G][kSymT];
     __shared__ double dpart[kSymT];
-    const int64_t t = blockIdx.x;
-    if ((live && *live == 0) || t >= ntiles) return;
-    const int2 bij = tiles[t];
-    const int bi = bij.x, bj = bij.y;
     const int tid = threadIdx.x, l = tid % L, rg = tid / L;
     const int c0 = l * CW;
-    const QT *tp = P + t * kSymT * kSymT;
     // the thread's rows of the tile: every load is issued first
     RawRow<QT, CW> q[R];
 #pragma unroll
@@ -170,15 +166,45 @@ __global__ void __launch_bounds__(SymShape<QT>::threads, SymShape<QT>::waves)
     }
     __syncthreads();
     if (tid < kSymT) {
-        Dp[t * kSymT + tid] = dpart[tid];
+        Do[tid] = dpart[tid];
     } else if (tid < 2 * kSymT && bi != bj) {
         const int c = tid - kSymT;
         double sm = part[0][c];
 #pragma unroll
         for (int g = 1; g < G; ++g) sm += part[g][c];
-        Tp[t * kSymT + c] = sm;
+        To[c] = sm;
     }
 }
+
+// One block per tile of one instance (grid = the tile count).
+template <typename QT>
+__global__ void __launch_bounds__(SymShape<QT>::threads, SymShape<QT>::waves)
+    symv_tile_kernel(const QT *P, const int2 *tiles, int64_t ntiles, const double *x, int64_t ld, double *Dp,
+                     double *Tp, const int32_t *live) {
+    const int64_t t = blockIdx.x;
+    if ((live && *live == 0) || t >= ntiles) return;
+    const int2 bij = tiles[t];
+    sym_tile_body<QT>(P + t * kSymT * kSymT, bij.x, bij.y, x, ld, Dp + t * kSymT, Tp + t * kSymT);
+}
+
+// Group product: one block per entry of the work list over the live
+// instances' tiles; a finished column's entries read nothing (issuing the
+// tile's loads beside the load of the column's phase, and storing nothing
+// for a finished column, was 13% slower over the uneven batch: up to a
+// quarter of the list belongs to finished columns between rebuilds).
+template <typename QT>
+__global__ void __launch_bounds__(SymShape<QT>::threads, SymShape<QT>::waves)
+    symv_group_tile_kernel(const QT *P, const SymGroupTile *list, int64_t nlist, const Col *col, const double *op,
+                           double *Dp, double *Tp) {
+    const int64_t e = blockIdx.x;
+    if (e >= nlist) return;
+    const SymGroupTile d = list[e];
+    if (col[d.col].phase == PH_DONE) return;
+    const int64_t t = d.t;
+    sym_tile_body<QT>(P + t * kSymT * kSymT, d.bi, d.bj, op + d.off, d.ld, Dp + t * kSymT, Tp + t * kSymT);
+}
+
+__host__ __device__ int symv_blocks(int64_t n) { return (int)((n + kSymT - 1) / kSymT); }
 
 // Tile index of (bi, bj), bi <= bj, in row-major order of the upper triangle.
 __device__ __forceinline__ int64_t sym_tile(int bi, int bj, int nb) {
@@ -189,14 +215,13 @@ __device__ __forceinline__ int64_t sym_tile(int bi, int bj, int nb) {
 // is summed by 8 threads, four over quarters of its direct parts (bj = bi ..
 // nb - 1) and four over quarters of its transposed parts (bk = 0 .. bi - 1),
 // each in increasing tile order; the eight sums are then added in that
-// order (direct quarters, then transposed quarters).
+// order (direct quarters, then transposed quarters). part: which of the four
+// 32-row parts of the tile row; tile indices start at base.
 constexpr int kSymReduceRows = 32;
-__global__ void __launch_bounds__(kBlock) symv_reduce_kernel(const double *Dp, const double *Tp, int nb, int64_t n,
-                                                             double *y, const int32_t *live) {
+__device__ __forceinline__ void sym_reduce_body(const double *Dp, const double *Tp, int64_t base, int bi, int part,
+                                                int nb, int64_t n, double *y) {
     __shared__ double ps[8][kSymReduceRows];
-    if (live && *live == 0) return;
-    const int bi = blockIdx.x / (kSymT / kSymReduceRows);
-    const int r = (blockIdx.x % (kSymT / kSymReduceRows)) * kSymReduceRows + (threadIdx.x & (kSymReduceRows - 1));
+    const int r = part * kSymReduceRows + (threadIdx.x & (kSymReduceRows - 1));
     const int q = threadIdx.x / kSymReduceRows;
     // a quarter's parts in increasing tile order, eight loads in flight at a
     // time (the additions keep that order)
@@ -207,7 +232,7 @@ __global__ void __launch_bounds__(kBlock) symv_reduce_kernel(const double *Dp, c
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int b = b0 + u;
-                v[u] = b < hi ? S[(direct ? sym_tile(bi, b, nb) : sym_tile(b, bi, nb)) * kSymT + r] : 0.0;
+                v[u] = b < hi ? S[(base + (direct ? sym_tile(bi, b, nb) : sym_tile(b, bi, nb))) * kSymT + r] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
@@ -236,7 +261,25 @@ __global__ void __launch_bounds__(kBlock) symv_reduce_kernel(const double *Dp, c
     }
 }
 
-int symv_blocks(int64_t n) { return (int)((n + kSymT - 1) / kSymT); }
+__global__ void __launch_bounds__(kBlock) symv_reduce_kernel(const double *Dp, const double *Tp, int nb, int64_t n,
+                                                             double *y, const int32_t *live) {
+    if (live && *live == 0) return;
+    constexpr int kParts = kSymT / kSymReduceRows;
+    sym_reduce_body(Dp, Tp, 0, blockIdx.x / kParts, blockIdx.x % kParts, nb, n, y);
+}
+
+// Group reduction: four blocks per entry of the list of the live instances'
+// tile rows (column, bi, vector offset, n, first tile index).
+__global__ void __launch_bounds__(kBlock) symv_group_reduce_kernel(const double *Dp, const double *Tp,
+                                                                   const SymGroupRow *rows, int64_t nrows,
+                                                                   const Col *col, double *U) {
+    constexpr int kParts = kSymT / kSymReduceRows;
+    const int64_t e = blockIdx.x / kParts;
+    if (e >= nrows) return;
+    const SymGroupRow d = rows[e];
+    if (col[d.col].phase == PH_DONE) return;
+    sym_reduce_body(Dp, Tp, d.base, d.bi, blockIdx.x % kParts, symv_blocks(d.n), d.n, U + d.off);
+}
 
 std::vector<int32_t> symv_tile_list(int nb) {
     std::vector<int32_t> v;
@@ -283,6 +326,26 @@ hipError_t launch_symv(int dtype, const SymTiles &s, const double *x, int64_t ld
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(symv_reduce_kernel, dim3((unsigned)s.nb * (kSymT / kSymReduceRows)), dim3(kBlock), 0, st, s.D,
                        s.T, s.nb, n, y, s.live);
+    return hipGetLastError();
+}
+
+hipError_t launch_symv_group(int dtype, const SymGroup &g, const Work &w, hipStream_t st) {
+    if (g.nlist < 1 || g.nrows < 1) return hipSuccess;
+    const dim3 grid((unsigned)g.nlist);
+    const double *op = (const double *)w.op;
+    if (dtype == PSDP_F64)
+        hipLaunchKernelGGL(symv_group_tile_kernel<double>, grid, dim3(SymShape<double>::threads), 0, st,
+                           (const double *)g.P, g.list, g.nlist, w.col, op, g.D, g.T);
+    else if (dtype == PSDP_F32)
+        hipLaunchKernelGGL(symv_group_tile_kernel<float>, grid, dim3(SymShape<float>::threads), 0, st,
+                           (const float *)g.P, g.list, g.nlist, w.col, op, g.D, g.T);
+    else if (dtype == PSDP_BF16)
+        hipLaunchKernelGGL(symv_group_tile_kernel<__hip_bfloat16>, grid, dim3(SymShape<__hip_bfloat16>::threads), 0,
+                           st, (const __hip_bfloat16 *)g.P, g.list, g.nlist, w.col, op, g.D, g.T);
+    else
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(symv_group_reduce_kernel, dim3((unsigned)(g.nrows * (kSymT / kSymReduceRows))), dim3(kBlock), 0,
+                       st, g.D, g.T, g.rows, g.nrows, w.col, (double *)w.U);
     return hipGetLastError();
 }
 

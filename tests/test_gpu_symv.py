@@ -1,7 +1,8 @@
 """The single-instance product from the unique half of Q (packed 128 x 128
 upper tiles, psdp_qx_single with sym = 1, psdp_params.gemv_sym) against
-its FP64 definition Q_off x and against the row-by-row GEMV, and whole
-single-instance solves with it against the oracle.
+its FP64 definition Q_off x and against the row-by-row GEMV, whole
+single-instance solves with it against the oracle, and the group product
+from every instance's tiles against the single-instance one and the oracle.
 
 Both products sum exact FP64 products (integer Q widened exactly) in FP64,
 in different orders, so each lies within the accumulation bound
@@ -111,3 +112,45 @@ def test_auto_choice_and_solve_agreement_n4096(P):
     assert np.array_equal(a.X.cpu().numpy(), s.X.cpu().numpy())
     print(f"n=4096, 4 penalty updates: tiles {int(s.obj[0])} ({s.stats[0]['inner_iters']} evaluations), full rows "
           f"{int(f.obj[0])} ({f.stats[0]['inner_iters']} evaluations)", flush=True)
+
+
+@pytest.mark.parametrize("qdt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("poll", [64, 2])
+def test_group_tiles_equal_single_instance_tiles(P, qdt, poll):
+    """The group product from every instance's packed upper tiles (one work
+    list over the live instances' tiles, rebuilt as instances finish: at
+    polls every 2 sweeps many times) performs each instance's single-instance
+    tile product bit for bit: rounded point, objective and counts equal the
+    single-instance solves with gemv_sym = 1, for sizes around the 128-row
+    tile edge."""
+    insts = gen.uneven_group(seed=11, count=10, nmin=20, nmax=300)
+    extra = [gen.sparse_int(n, 30 + n) for n in (127, 128, 129, 256, 257)]
+    Qs = [_t(d["Q"]) for d in insts] + [_t(Q) for Q, _ in extra]
+    bs = [_t(d["b"]) for d in insts] + [_t(b) for _, b in extra]
+    sigma = max(1e-3 * float(np.abs(d["Q"]).max()) for d in insts)
+    seeds = list(range(len(Qs)))
+    xh, obj, stats = P.solve_group(Qs, bs, seeds=seeds, sigma=sigma, perturb="diag", qx_dtype=qdt, gemv_sym=1,
+                                   poll_sweeps=poll)
+    for i in range(len(Qs)):
+        one = P.solve(Qs[i], bs[i], sigma=sigma, perturb="diag", seed=seeds[i], qx_dtype=qdt, gemv_sym=1)
+        assert int(one.obj[0]) == int(obj[i]), i
+        assert np.array_equal(one.xhat.cpu().numpy(), xh[i].cpu().numpy()), i
+        for key in ("inner_iters", "aux_matvecs", "outer_iters", "exit_reason"):
+            assert one.stats[0][key] == stats[i][key], (i, key)
+
+
+def test_group_tiles_against_oracle_small_set(P):
+    """Group solves of the n <= 20 brute-force set and the dense n = 64
+    instance with the tile product (FP64 and BF16 storage): objectives and
+    rounded points equal the oracle's."""
+    cases = gen.bruteforce_set()[::2] + [(0,) + gen.small_dense(0)]
+    mism = []
+    for qdt in ("f64", "bf16"):
+        xh, obj, _ = P.solve_group([_t(Q) for _, Q, _ in cases], [_t(b) for _, _, b in cases], qx_dtype=qdt,
+                                   gemv_sym=1)
+        for i, (seed, Q, b) in enumerate(cases):
+            ref = O.solve(Q, b)
+            if int(obj[i]) != ref.obj or not np.array_equal(xh[i].cpu().numpy(), ref.xhat):
+                mism.append((seed, qdt))
+    print(f"group tile-product solves: {2 * len(cases) - len(mism)}/{2 * len(cases)} equal to the oracle", flush=True)
+    assert not mism
