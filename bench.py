@@ -58,7 +58,12 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 MFMA
 STEP_BYTES_PER_COLUMN = 80  # about 10 FP64 vectors of n per column update
 START_SEED = 3              # start set of the first timed step (the workload generator's default)
 STEP_SOURCES = ("paper_2408_04875_amd/csrc/solver.hip", "paper_2408_04875_amd/csrc/common.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_traffic.json")
+DIGIT_SOURCES = ("paper_2408_04875_amd/csrc/qx8.hip", "paper_2408_04875_amd/csrc/launch.hpp",
+                 "paper_2408_04875_amd/csrc/common.hpp")
+# the kernels whose rocprofv3 records (kernel trace, HBM counters) the bench line cites, by the
+# name fragment that selects their dispatches, with the sources each record is keyed to
+RECORDED_KERNELS = {"psdp::solver_step_kernel<": STEP_SOURCES, "psdp::digit_kernel<": DIGIT_SOURCES}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernels_n2500_b256_traffic.json")
 
 
 def parse():
@@ -81,10 +86,11 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-replay", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--record-trace", nargs=2, metavar=("STATS_CSV", "KERNEL"),
-                    help="write the step kernel's rocprofv3 kernel-trace record from a kernel_stats.csv")
+    ap.add_argument("--record-trace", nargs=1, metavar="STATS_CSV",
+                    help="write the step and digit kernels' rocprofv3 kernel-trace record from a kernel_stats.csv")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
-                    help="write the step kernel's HBM traffic record from four rocprofv3 counter_collection.csv")
+                    help="write the step and digit kernels' HBM traffic record from four rocprofv3 "
+                         "counter_collection.csv")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-gemv", action="store_true")
     ap.add_argument("--no-group", action="store_true")
@@ -110,20 +116,25 @@ def code_only(text: str) -> str:
     return "\n".join(out)
 
 
-def step_source_hash():
+def source_hash(sources=STEP_SOURCES):
     h = hashlib.sha256()
-    for rel in STEP_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
             h.update(code_only(f.read()).encode())
     return h.hexdigest()
 
 
-TRACE_FILE = os.path.join(ROOT, "profiles", "step_kernel_n2500_b256_trace.json")
+def step_source_hash():
+    return source_hash(STEP_SOURCES)
+
+
+TRACE_FILE = os.path.join(ROOT, "profiles", "kernels_n2500_b256_trace.json")
 # the bench command the kernel records are taken from: the default configuration (queued launch
 # of 1024 columns) over twenty start sets, without the side legs
 PROFILE_ARGS = ("--steps 20 --warmup 0 --no-cpu-baseline --no-plain --no-fp32 --no-sparse --no-gemv --no-group "
                 "--no-replay --no-adjoint --no-per-set")
-STEP_KERNEL_PREFIX = "solver_step_kernel"
+STEP_KERNEL_PREFIX = "psdp::solver_step_kernel<"
+DIGIT_KERNEL_PREFIX = "psdp::digit_kernel<"
 
 
 def _csv_rows(path):
@@ -132,31 +143,36 @@ def _csv_rows(path):
         return list(csv.DictReader(f))
 
 
-def record_trace(stats_csv, kernel=STEP_KERNEL_PREFIX):
+def record_trace(stats_csv):
     """Writes TRACE_FILE from a rocprofv3 --kernel-trace --stats summary
-    (kernel_stats.csv): calls and average duration of the kernels whose name
-    contains `kernel`, keyed to the step kernel's source."""
-    rows = [r for r in _csv_rows(stats_csv) if kernel in r["Name"]]
-    calls = sum(int(r["Calls"]) for r in rows)
-    total = sum(float(r["TotalDurationNs"]) for r in rows)
-    rec = {"kernel": [r["Name"] for r in rows], "source_sha256": step_source_hash(), "calls": calls,
-           "avg_ns": total / max(calls, 1),
+    (kernel_stats.csv): calls and average duration of each recorded kernel
+    (all its instantiations), keyed to that kernel's sources."""
+    rows = _csv_rows(stats_csv)
+    recs = {}
+    for frag, sources in RECORDED_KERNELS.items():
+        sel = [r for r in rows if frag in r["Name"]]
+        calls = sum(int(r["Calls"]) for r in sel)
+        total = sum(float(r["TotalDurationNs"]) for r in sel)
+        recs[frag] = {"kernel": [r["Name"] for r in sel], "source_sha256": source_hash(sources), "calls": calls,
+                      "avg_ns": total / max(calls, 1)}
+    rec = {"records": recs,
            "command": "cd /tmp && rocprofv3 --kernel-trace --stats -d <out> -o run -- python -u <repo>/bench.py "
                       + PROFILE_ARGS,
-           "note": "both queued solves of the run (the timed one and the one with HIP events around every launch)"}
+           "note": "both queued solves of the run (the timed one and the one with HIP events around every launch); "
+                   "the two lanes run concurrently, so launch durations include time shared with the other lane"}
     with open(TRACE_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
 
-def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel=STEP_KERNEL_PREFIX):
+def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
     """Writes TRAFFIC_FILE from four rocprofv3 --pmc counter runs: FETCH_SIZE
     and WRITE_SIZE (KiB per dispatch) over the bench command and over
     --calibrate-copy (1 GiB copied three times); each counter is scaled so
     that it reads 1 GiB for the 1 GiB copy."""
-    def per_dispatch(path, counter, name_prefix):
+    def per_dispatch(path, counter, frag):
         vals = [float(r["Counter_Value"]) for r in _csv_rows(path)
-                if r["Counter_Name"] == counter and name_prefix in r["Kernel_Name"]]
+                if r["Counter_Name"] == counter and frag in r["Kernel_Name"]]
         return sum(vals) / max(len(vals), 1), len(vals)
     # the copy run launches one kind of large kernel: take every dispatch above 1 MiB
     cf = [float(r["Counter_Value"]) for r in _csv_rows(copy_fetch_csv) if r["Counter_Name"] == "FETCH_SIZE"]
@@ -165,49 +181,50 @@ def record_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel=
     cw = [v for v in cw if v > 1024.0]
     gib_kib = (1 << 30) / 1024.0
     fs, ws = gib_kib / (sum(cf) / len(cf)), gib_kib / (sum(cw) / len(cw))
-    f_kib, nd = per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
-    w_kib, _ = per_dispatch(write_csv, "WRITE_SIZE", kernel)
-    fb, wb = f_kib * 1024.0 * fs, w_kib * 1024.0 * ws
-    rec = {"kernel": f"{kernel} (n = 2500, 20 sets of 256 starts through 1024 columns, I8 operands)",
-           "source_sha256": step_source_hash(),
-           "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-           "dispatches": nd, "fetch_size_kib_avg": f_kib, "write_size_kib_avg": w_kib,
+    recs = {}
+    for frag, sources in RECORDED_KERNELS.items():
+        f_kib, nd = per_dispatch(fetch_csv, "FETCH_SIZE", frag)
+        w_kib, _ = per_dispatch(write_csv, "WRITE_SIZE", frag)
+        fb, wb = f_kib * 1024.0 * fs, w_kib * 1024.0 * ws
+        recs[frag] = {"source_sha256": source_hash(sources), "bytes_per_launch": fb + wb,
+                      "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "dispatches": nd,
+                      "fetch_size_kib_avg": f_kib, "write_size_kib_avg": w_kib}
+    rec = {"workload": "n = 2500, 20 sets of 256 starts through 1024 columns in two lanes, I8 operands",
+           "records": recs,
            "copy_calibration": {"bytes": 1 << 30, "fetch_size_kib": sum(cf) / len(cf),
                                 "write_size_kib": sum(cw) / len(cw), "fetch_scale": fs, "write_scale": ws},
            "commands": [f"cd /tmp && rocprofv3 --pmc {c} --output-format csv -d <out> -o run -- python -u "
                         f"<repo>/bench.py {a}" for c in ("FETCH_SIZE", "WRITE_SIZE")
                         for a in (PROFILE_ARGS, "--calibrate-copy")],
            "note": "bytes = FETCH_SIZE KiB x 1024 x fetch_scale + WRITE_SIZE KiB x 1024 x write_scale, averaged "
-                   "over the step-kernel dispatches of both solves of the run (timed and instrumented)"}
+                   "over the kernel's dispatches of both solves of the run (timed and instrumented)"}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
 
-def measured_step_avg_ns():
-    """Average step-kernel duration from the committed rocprofv3 kernel-trace
-    record, or None when it is missing or the kernel source changed since."""
+def _record(path, frag, key):
+    """One field of a kernel's committed record, or None when the record is
+    missing or the kernel's sources changed since it was taken."""
     try:
-        with open(TRACE_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != step_source_hash():
+    r = t.get("records", {}).get(frag)
+    if not r or r.get("source_sha256") != source_hash(RECORDED_KERNELS[frag]):
         return None
-    return t.get("avg_ns")
+    return r.get(key)
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    runs, or None when they are missing or the kernel source changed since."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != step_source_hash():
-        return None
-    return t.get("bytes_per_launch")
+def measured_avg_ns(frag=STEP_KERNEL_PREFIX):
+    """Average launch duration from the committed rocprofv3 kernel trace."""
+    return _record(TRACE_FILE, frag, "avg_ns")
+
+
+def measured_traffic(frag=STEP_KERNEL_PREFIX):
+    """HBM bytes per launch from the committed rocprofv3 counter runs."""
+    return _record(TRAFFIC_FILE, frag, "bytes_per_launch")
 
 
 def calibrate_copy():
@@ -681,17 +698,20 @@ def main():
     # launches: the first start set; queued: the timed sets' starts through
     # the same number of columns (the timed workload, launched eagerly)
     if args.slots:
-        s0 = step(args.qx, timing=True, X=torch.cat(X0s[:args.steps], dim=0), slots=args.slots).stats[0]
+        inst = step(args.qx, timing=True, X=torch.cat(X0s[:args.steps], dim=0), slots=args.slots)
     else:
-        s0 = step(args.qx, timing=True).stats[0]
+        inst = step(args.qx, timing=True)
+    s0 = inst.stats[0]
+    inst_evals = sum(s["inner_iters"] for s in inst.stats)
+    inst_aux = sum(s["aux_matvecs"] for s in inst.stats)
     step_s, step_l, colsteps = s0["step_seconds"], s0["step_launches"], s0["column_steps"]
     step_bytes = STEP_BYTES_PER_COLUMN * n * colsteps
     qx_s = s0["qx_seconds"] + s0["aux_seconds"]
     qx_f = s0["qx_flops"] + s0["aux_flops"]
     qx_l = s0["qx_launches"]
-    rp_ns = measured_step_avg_ns()
+    rp_ns = measured_avg_ns(STEP_KERNEL_PREFIX)
     step_rl = {"bound": "hbm", "achieved": step_bytes / step_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-               "frac": step_bytes / step_s / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic(),
+               "frac": step_bytes / step_s / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic(STEP_KERNEL_PREFIX),
                "frac_rocprof": (step_bytes / max(step_l, 1) / (rp_ns * 1e-9) / 1e9 / PEAK_HBM_GBS
                                 if rp_ns else None),
                "avg_launch_us_rocprof": rp_ns * 1e-3 if rp_ns else None,
@@ -708,9 +728,21 @@ def main():
         qx_peak, qx_unit, qx_name = PEAK_FP64_TFLOPS, "TFLOP/s", "stream/gemm kernels (FP64 MFMA)"
     qx_rl = {"bound": "mfma", "achieved": qx_f / qx_s / 1e12 if qx_s > 0 else 0.0, "peak": qx_peak,
              "unit": qx_unit, "frac": (qx_f / qx_s / 1e12 / qx_peak) if qx_s > 0 else 0.0,
+             "traffic": measured_traffic(DIGIT_KERNEL_PREFIX) if args.qx == "i8" else None,
              "kernel": qx_name, "launches": qx_l, "seconds": qx_s,
+             "avg_launch_us": qx_s / max(qx_l, 1) * 1e6,
              "work": "2 n^2 multiply-adds per column product (algorithmic; the int8 path executes 4 or 8 "
                      "digit products per column)"}
+    if args.qx == "i8":
+        # the int8 MFMA work the digit kernel executes: 4 digit rows per subproblem column and 8 per
+        # lambda_min column, each against the whole padded Q (ldq x ldq)
+        ldq = (n + 63) // 64 * 64
+        ex = 2.0 * ldq * ldq * (4.0 * inst_evals + 8.0 * inst_aux)
+        dk_ns = measured_avg_ns(DIGIT_KERNEL_PREFIX)
+        qx_rl.update({"executed_tops": ex / qx_s / 1e12 if qx_s > 0 else 0.0,
+                      "executed_frac": ex / qx_s / 1e12 / qx_peak if qx_s > 0 else 0.0,
+                      "avg_launch_us_rocprof": dk_ns * 1e-3 if dk_ns else None,
+                      "frac_rocprof": (qx_f / max(qx_l, 1) / (dk_ns * 1e-9) / 1e12 / qx_peak if dk_ns else None)})
     dominant, other = (step_rl, qx_rl) if step_s >= qx_s else (qx_rl, step_rl)
     first = results[0]
     objs = first.obj.cpu().numpy()

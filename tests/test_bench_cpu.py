@@ -1,5 +1,5 @@
-"""Host-side pieces of bench.py: the keying of the stored HBM-traffic record
-to the step kernel's source, and the one-GPU contract."""
+"""Host-side pieces of bench.py: the keying of the stored kernel-trace and
+HBM-traffic records to each kernel's sources, and the one-GPU contract."""
 import json
 import os
 import subprocess
@@ -16,23 +16,30 @@ def test_code_only_drops_comments_and_blank_lines():
 
 
 def test_traffic_record_is_keyed_to_the_source(tmp_path, monkeypatch):
-    rec = {"source_sha256": bench.step_source_hash(), "bytes_per_launch": 123.0}
+    step, digit = bench.STEP_KERNEL_PREFIX, bench.DIGIT_KERNEL_PREFIX
+    rec = {"records": {step: {"source_sha256": bench.step_source_hash(), "bytes_per_launch": 123.0},
+                       digit: {"source_sha256": bench.source_hash(bench.DIGIT_SOURCES), "bytes_per_launch": 7.0}}}
     path = tmp_path / "traffic.json"
     path.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
-    assert bench.measured_traffic() == 123.0
-    rec["source_sha256"] = "0" * 64
+    assert bench.measured_traffic(step) == 123.0
+    assert bench.measured_traffic(digit) == 7.0
+    rec["records"][step]["source_sha256"] = "0" * 64
     path.write_text(json.dumps(rec))
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(step) is None
+    assert bench.measured_traffic(digit) == 7.0
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(step) is None
 
 
-def test_committed_traffic_record_matches_the_committed_source():
-    with open(bench.TRAFFIC_FILE) as f:
-        rec = json.load(f)
-    assert rec["source_sha256"] == bench.step_source_hash()
-    assert rec["bytes_per_launch"] > 0
+def test_committed_kernel_records_match_the_committed_sources():
+    for path, key in ((bench.TRAFFIC_FILE, "bytes_per_launch"), (bench.TRACE_FILE, "avg_ns")):
+        with open(path) as f:
+            rec = json.load(f)
+        for frag, sources in bench.RECORDED_KERNELS.items():
+            r = rec["records"][frag]
+            assert r["source_sha256"] == bench.source_hash(sources), (path, frag)
+            assert r[key] > 0
 
 
 def test_more_than_one_gpu_is_refused():
