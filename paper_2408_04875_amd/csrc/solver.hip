@@ -48,6 +48,12 @@ struct UVec {
         return *reinterpret_cast<T *>(reinterpret_cast<char *>(const_cast<typename std::remove_const<T>::type *>(p)) +
                                       i * (uint32_t)sizeof(T));
     }
+    // entries i and i + 1 as one V (i even: the vectors' bases are aligned
+    // to 256 bytes, so a pair of 8-byte entries is one 16-byte access)
+    template <typename V> __device__ __forceinline__ V &pair(uint32_t i) const {
+        return *reinterpret_cast<V *>(reinterpret_cast<char *>(const_cast<typename std::remove_const<T>::type *>(p)) +
+                                      i * (uint32_t)sizeof(T));
+    }
 };
 template <typename T> __device__ __forceinline__ UVec<T> uvec(T *base, int64_t off) { return UVec<T>{base + off}; }
 
@@ -74,9 +80,11 @@ __device__ __forceinline__ ColView view(const Col &c) {
 // unconditional and in bounds and all of them issue before the first wait; a
 // branch per element would make the loads wait element by element. Results
 // of clamped elements are discarded (selects, guarded stores), in the same
-// per-thread order as before, so the arithmetic is unchanged. Every element
-// is read and written by the same thread in every pass of a kernel, so the
-// threads of a block exchange nothing through global memory.
+// per-thread order as before, so the arithmetic is unchanged. Within a pass
+// (and between the passes of one step, which keep values in registers or
+// LDS) every element is read and written by the same thread; a later phase
+// of the same launch may map elements to threads differently (the subproblem
+// passes use the pairs below) and reads them only after a block barrier.
 #define CHUNKS(n) for (uint32_t _b = 0; _b < (n); _b += (uint32_t)(EPT * kSB))
 #define CHUNK_INDEX(n)                                                 \
     uint32_t ix[EPT];                                                  \
@@ -88,6 +96,85 @@ __device__ __forceinline__ ColView view(const Col &c) {
     }
 #define FOR_J _Pragma("unroll") for (int _j = 0; _j < EPT; ++_j)
 
+// The subproblem passes (PAIR: an even EPT) map a chunk in pairs instead:
+// thread t holds elements 2 (t + k kSB) and 2 (t + k kSB) + 1 (k < EPT / 2),
+// so that each access of the thread to a column vector moves two entries at
+// once (16 bytes for 8-byte entries). The passes issue one memory instruction
+// per entry and vector, and a CU's memory pipeline takes a 16-byte access per
+// lane about as fast as an 8-byte one, so pairs halve the time the pipeline
+// is busy with a column. A pair past n repeats the last pair of the column
+// (in bounds: when n is odd its second entry is padding, since ld > n), and
+// entries past n are discarded as above; a stored pair whose second entry is
+// past n stores zero there (padding entries stay zero).
+template <int EPT> constexpr bool kPair = EPT % 2 == 0;
+template <int EPT>
+__device__ __forceinline__ void chunk_map(uint32_t b, uint32_t n, uint32_t (&ix)[EPT], bool (&ok)[EPT]) {
+    if constexpr (kPair<EPT>) {
+#pragma unroll
+        for (int k = 0; k < EPT / 2; ++k) {
+            const uint32_t i = b + 2u * (threadIdx.x + (uint32_t)(k * kSB));
+            const uint32_t c = i < n ? i : ((n - 1u) & ~1u);
+            ix[2 * k] = c;
+            ix[2 * k + 1] = c + 1u;
+            ok[2 * k] = i < n;
+            ok[2 * k + 1] = i + 1u < n;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const uint32_t i = b + threadIdx.x + (uint32_t)(j * kSB);
+            ok[j] = i < n;
+            ix[j] = ok[j] ? i : n - 1u;
+        }
+    }
+}
+#define CHUNK_PAIRS(n)                                                 \
+    uint32_t ix[EPT];                                                  \
+    bool ok[EPT];                                                      \
+    chunk_map<EPT>(_b, (n), ix, ok);
+
+template <typename T> struct PairOf;
+template <> struct PairOf<double> { using type = double2; };
+template <> struct PairOf<int64_t> { using type = longlong2; };
+template <> struct PairOf<float> { using type = float2; };
+template <> struct PairOf<int32_t> { using type = int2; };
+
+// Loads of one chunk's entries of a vector, as pairs when PAIR.
+template <bool PAIR, int EPT, typename T>
+__device__ __forceinline__ void ld_chunk(const UVec<T> &v, const uint32_t (&ix)[EPT],
+                                         typename std::remove_const<T>::type (&o)[EPT]) {
+    using E = typename std::remove_const<T>::type;
+    if constexpr (PAIR && kPair<EPT> && (sizeof(E) == 8 || sizeof(E) == 4)) {
+        using V = typename PairOf<E>::type;
+#pragma unroll
+        for (int k = 0; k < EPT / 2; ++k) {
+            const V a = v.template pair<const V>(ix[2 * k]);
+            o[2 * k] = a.x;
+            o[2 * k + 1] = a.y;
+        }
+    } else {
+        FOR_J o[_j] = v[ix[_j]];
+    }
+}
+// Stores of one chunk's real entries, as pairs when PAIR.
+template <bool PAIR, int EPT, typename T>
+__device__ __forceinline__ void st_chunk(const UVec<T> &v, const uint32_t (&ix)[EPT], const bool (&ok)[EPT],
+                                         const T (&val)[EPT]) {
+    if constexpr (PAIR && kPair<EPT> && (sizeof(T) == 8 || sizeof(T) == 4)) {
+        using V = typename PairOf<T>::type;
+#pragma unroll
+        for (int k = 0; k < EPT / 2; ++k)
+            if (ok[2 * k]) {
+                V a;
+                a.x = val[2 * k];
+                a.y = ok[2 * k + 1] ? val[2 * k + 1] : T(0);
+                v.template pair<V>(ix[2 * k]) = a;
+            }
+    } else {
+        FOR_J if (ok[_j]) v[ix[_j]] = val[_j];
+    }
+}
+
 template <typename OpT> constexpr bool kDigits = std::is_same<OpT, int8_t>::value;
 
 // The products of one chunk (elements ix[j]) for a subproblem column: every
@@ -95,15 +182,17 @@ template <typename OpT> constexpr bool kDigits = std::is_same<OpT, int8_t>::valu
 // grid 2^-27, exact, in one buffer that the product's K slices add into;
 // each real element is cleared once read when the next product adds into
 // it (w.clear_main).
-template <typename UT, int EPT>
+template <typename UT, int EPT, bool PAIR = false>
 __device__ __forceinline__ void uval_chunk(const Work &w, const ColView &cv, const uint32_t (&ix)[EPT],
                                            const bool (&ok)[EPT], double (&u)[EPT]) {
     if constexpr (std::is_same<UT, int64_t>::value) {
         const UVec<int64_t> U = uvec((int64_t *)w.U, cv.off);
         int64_t s[EPT];
-        FOR_J s[_j] = U[ix[_j]];
+        ld_chunk<PAIR>(U, ix, s);
         if (w.clear_main) {
-            FOR_J if (ok[_j]) U[ix[_j]] = 0;
+            int64_t z[EPT];
+            FOR_J z[_j] = 0;
+            st_chunk<PAIR>(U, ix, ok, z);
         }
         FOR_J u[_j] = (double)s[_j] / kMainScale;
     } else {
@@ -179,6 +268,47 @@ __device__ __forceinline__ void put_main(const Work &w, const Col &c, const ColV
         if (w.tw) uvec(w.tw, cv.off)[i] = (int32_t)T;
     } else {
         uvec((OpT *)w.op, cv.off)[i] = from_f64<OpT>(v);
+    }
+}
+
+// The four base-128 digits of T, as put_digits4 splits it.
+__device__ __forceinline__ void digits4_of(int32_t T, int32_t (&d)[4]) {
+    d[0] = (T + (1 << 20)) >> 21;
+    T -= d[0] << 21;
+    d[1] = (T + (1 << 13)) >> 14;
+    T -= d[1] << 14;
+    d[2] = (T + (1 << 6)) >> 7;
+    T -= d[2] << 7;
+    d[3] = T;
+}
+
+// put_main for one chunk's real entries; in pairs (PAIR and an even EPT) on
+// the integer path: two entries' digits per plane as one 2-byte store (a
+// second entry past n gets the digits of 0).
+template <typename OpT, int EPT, bool PAIR>
+__device__ __forceinline__ void put_main_chunk(const Work &w, const Col &c, const ColView &cv,
+                                               const uint32_t (&ix)[EPT], const bool (&ok)[EPT],
+                                               const double (&v)[EPT]) {
+    if constexpr (kDigits<OpT> && PAIR && kPair<EPT>) {
+        int8_t *pl = main_planes(w, c);
+        const int64_t ld = uni(c.ld);
+        const UVec<int32_t> tw{w.tw ? w.tw + cv.off : nullptr};
+#pragma unroll
+        for (int k = 0; k < EPT / 2; ++k) {
+            if (!ok[2 * k]) continue;
+            const uint32_t i = ix[2 * k];
+            const int32_t T0 = (int32_t)__double2ll_rn(v[2 * k] * kMainScale);
+            const int32_t T1 = ok[2 * k + 1] ? (int32_t)__double2ll_rn(v[2 * k + 1] * kMainScale) : 0;
+            int32_t a[4], b[4];
+            digits4_of(T0, a);
+            digits4_of(T1, b);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                *reinterpret_cast<uint16_t *>(pl + t * ld + i) = (uint16_t)((a[t] & 0xff) | ((b[t] & 0xff) << 8));
+            if (w.tw) tw.template pair<int2>(i) = make_int2(T0, T1);
+        }
+    } else {
+        FOR_J if (ok[_j]) put_main<OpT>(w, c, cv, ix[_j], v[_j]);
     }
 }
 
@@ -429,18 +559,15 @@ __device__ bool inner_step(const Work &w, Col &c, const ColView &cv, double *red
     double sl[3] = {0.0, 0.0, 0.0};
     double xr[EPT], gr[EPT];         // register copies when one pass covers the column
     CHUNKS(n) {
-        CHUNK_INDEX(n)
+        CHUNK_PAIRS(n)
         double xv[EPT], pv[EPT], Av[EPT], bv[EPT], xpv[EPT], gpv[EPT], u[EPT];
-        FOR_J {
-            const uint32_t i = ix[_j];
-            xv[_j] = x[i];
-            pv[_j] = p[i];
-            Av[_j] = dgi[i];
-            bv[_j] = lni[i];
-            xpv[_j] = xp[i];  // stale but unused when k == 0
-            gpv[_j] = gp[i];
-        }
-        uval_chunk<UT, EPT>(w, cv, ix, ok, u);
+        ld_chunk<true>(x, ix, xv);
+        ld_chunk<true>(p, ix, pv);
+        ld_chunk<true>(dgi, ix, Av);
+        ld_chunk<true>(lni, ix, bv);
+        ld_chunk<true>(xp, ix, xpv);  // stale but unused when k == 0
+        ld_chunk<true>(gp, ix, gpv);
+        uval_chunk<UT, EPT, true>(w, cv, ix, ok, u);
         FOR_J {
             Av[_j] = Av[_j] - pv[_j];  // diagonal of Q_r - Diag p
             bv[_j] = bv[_j] + pv[_j];  // b_r + p
@@ -499,26 +626,32 @@ __device__ bool inner_step(const Work &w, Col &c, const ColView &cv, double *red
     }
     const bool pabb = w.inner == PSDP_INNER_PABB;
     CHUNKS(n) {
-        CHUNK_INDEX(n)
-        double xv[EPT], gv[EPT], hp[EPT];
-        FOR_J {
-            const uint32_t i = ix[_j];
-            xv[_j] = CACHE ? xr[_j] : x[i];
-            gv[_j] = CACHE ? gr[_j] : g[i];
-            if (!pabb) hp[_j] = fmax((R[i] + fabs(dq[i] + gam[i])) - p[i], w.eps_hp);
+        CHUNK_PAIRS(n)
+        double xv[EPT], gv[EPT], hp[EPT], xn[EPT];
+        if (CACHE) {
+            FOR_J {
+                xv[_j] = xr[_j];
+                gv[_j] = gr[_j];
+            }
+        } else {
+            ld_chunk<true>(x, ix, xv);
+            ld_chunk<true>(g, ix, gv);
+        }
+        if (!pabb) {
+            FOR_J {
+                const uint32_t i = ix[_j];
+                hp[_j] = fmax((R[i] + fabs(dq[i] + gam[i])) - p[i], w.eps_hp);
+            }
         }
         FOR_J {
-            if (!ok[_j]) continue;
-            const uint32_t i = ix[_j];
             const double xi = xv[_j], gi = gv[_j];
-            double xn;
-            if (pabb) xn = fmin(fmax(xi - alpha * gi, 0.0), 1.0);
-            else xn = fmin(fmax(xi + (-gi / (2.0 * hp[_j])), 0.0), 1.0);
-            xp[i] = xi;
-            gp[i] = gi;
-            x[i] = xn;
-            put_main<OpT>(w, c, cv, i, xn);
+            if (pabb) xn[_j] = fmin(fmax(xi - alpha * gi, 0.0), 1.0);
+            else xn[_j] = fmin(fmax(xi + (-gi / (2.0 * hp[_j])), 0.0), 1.0);
         }
+        st_chunk<true>(xp, ix, ok, xv);
+        st_chunk<true>(gp, ix, ok, gv);
+        st_chunk<true>(x, ix, ok, xn);
+        put_main_chunk<OpT, EPT, true>(w, c, cv, ix, ok, xn);
     }
     if (k + 1 >= w.max_inner) {
         __syncthreads();
