@@ -426,3 +426,53 @@ def test_input_checks_on_device(P):
     # a valid instance still solves, with the same result as before the checks moved
     r = P.solve(_t(Q), _t(b))
     assert int(r.obj[0]) == O.solve(Q, b).obj
+
+
+def _degenerate_cases():
+    """(name, Q, b, ties): ties marks an instance whose objective is the same
+    at every binary point, so that only the objective is unique."""
+    z = lambda n: np.zeros((n, n), dtype=np.int32)
+    return [
+        ("n=1, Q < 0", np.array([[-3]], dtype=np.int32), np.array([1], dtype=np.int32), False),
+        ("n=1, Q > 0", np.array([[5]], dtype=np.int32), np.array([-2], dtype=np.int32), False),
+        ("Q = 0, b = 0", z(2), np.zeros(2, dtype=np.int32), True),
+        ("Q = 0, b > 0", z(3), np.array([4, 1, 7], dtype=np.int32), False),
+        ("Q = 0, b < 0", z(3), np.array([-4, -1, -7], dtype=np.int32), False),
+        ("diagonal Q", np.diag([3, -2, 5, -1]).astype(np.int32), np.zeros(4, dtype=np.int32), False),
+        ("positive off-diagonal", np.array([[0, 2, 2], [2, 0, 2], [2, 2, 0]], dtype=np.int32),
+         np.array([-1, -1, -1], dtype=np.int32), False),
+    ]
+
+
+def _objective(Q, b, x):
+    x = np.asarray(x, dtype=np.int64)
+    return int(x @ Q.astype(np.int64) @ x + b.astype(np.int64) @ x)
+
+
+@pytest.mark.parametrize("qdt", ["f64", "i8"])
+def test_degenerate_instances_equal_oracle(P, qdt):
+    """The method's degenerate cases: n = 1, Q = 0 (the subproblem is
+    linear), b of one sign (the optimum at a corner), a diagonal Q (the
+    coordinates decouple), a start that is already binary (no penalty update
+    runs), and the same instances as columns of one batched launch: objective
+    equal to the oracle's, and the rounded point too unless every binary point
+    has the same objective (Q = 0, b = 0: there the iterates end at the tie
+    x = 1/2, which ulps decide); every rounded point's exact objective is the
+    one reported."""
+    for name, Q, b, ties in _degenerate_cases():
+        ref = O.solve(Q, b)
+        r = P.solve(_t(Q), _t(b), qx_dtype=qdt)
+        xr = r.xhat.cpu().numpy().ravel()
+        assert int(r.obj[0]) == ref.obj == _objective(Q, b, xr), name
+        assert ties or np.array_equal(xr, ref.xhat), name
+        n = len(b)
+        X0 = gen.random_box_points(n, 3, 5)
+        X0[2] = (np.arange(n) % 2).astype(np.float64)  # binary: ends before any update
+        rb = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype=qdt)
+        for j in range(3):
+            rj = O.solve(Q, b, x0=X0[j])
+            xj = rb.xhat.cpu().numpy()[j]
+            assert int(rb.obj[j]) == rj.obj == _objective(Q, b, xj), (name, j)
+            assert ties or np.array_equal(xj, rj.xhat), (name, j)
+        assert np.array_equal(rb.xhat.cpu().numpy()[2], X0[2].astype(np.uint8)), name
+        assert rb.stats[2]["outer_iters"] == 0 and rb.stats[2]["inner_iters"] == 0, name
