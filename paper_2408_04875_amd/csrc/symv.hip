@@ -84,14 +84,18 @@ template <> struct RawRow<__hip_bfloat16, 8> {
 // thread, in G = T / R row groups of L = T / CW lanes. FP32 and BF16 threads
 // hold 8 columns of 4 rows (32 or 16 bytes of a row per load), FP64 threads
 // 4 columns of 8 rows (32 bytes), so that the loads of a tile are issued at
-// once from few registers; the BF16 kernel is held to 5 waves per SIMD
-// (measured at n = 16384: 8 x 4 per thread read 1.3x faster than 4 x 8 in
-// both FP32 and BF16).
+// once from few registers (measured at n = 16384: 8 x 4 per thread read 1.3x
+// faster than 4 x 8 in both FP32 and BF16). LDS: FP32 and BF16 tiles take
+// the tile's x entries from LDS and hand their row sums to LDS at once
+// instead of keeping them for a butterfly, which holds them to 80 registers:
+// six waves per SIMD, three 512-thread blocks per CU instead of two (BF16
+// 1.29x faster at n = 16384).
 template <typename QT> struct SymShape {
     static constexpr int CW = sizeof(QT) == 8 ? 4 : 8;
     static constexpr int R = sizeof(QT) == 8 ? 8 : 4;
     static constexpr int L = kSymT / CW, G = kSymT / R, threads = L * G;
-    static constexpr int waves = sizeof(QT) == 2 ? 5 : 4;  // minimum per SIMD
+    static constexpr bool LDS = sizeof(QT) != 8;
+    static constexpr int waves = LDS ? 6 : 4;  // minimum per SIMD
 };
 
 // The products of one tile tp = (bi, bj) by one block: lane l of row group g
@@ -106,9 +110,61 @@ __device__ __forceinline__ void sym_tile_body(const QT *tp, int bi, int bj, cons
     static_assert(R >= 2 && R <= L && (R & (R - 1)) == 0 && L <= 64 && (L & (L - 1)) == 0, "tile kernel shape");
     static_assert(S::threads >= 2 * kSymT, "one thread per output of the tile");
     __shared__ double part[G][kSymT];
-    __shared__ double dpart[kSymT];
     const int tid = threadIdx.x, l = tid % L, rg = tid / L;
     const int c0 = l * CW;
+    if constexpr (S::LDS) {
+        // x of the tile's rows and columns staged in LDS; the partial row sum
+        // of every (row, lane) goes to dl, and a row's direct sum adds its L
+        // lanes in lane order
+        __shared__ double xs[kSymT], xsj[kSymT];
+        __shared__ double dl[R][G][L];
+        RawRow<QT, CW> q[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) q[k].load(tp + (rg + G * k) * kSymT + c0);
+        if (tid < kSymT) {
+            const int64_t i = (int64_t)bi * kSymT + tid;
+            xs[tid] = i < ld ? x[i] : 0.0;
+        } else if (tid < 2 * kSymT) {
+            const int64_t j = (int64_t)bj * kSymT + (tid - kSymT);
+            xsj[tid - kSymT] = j < ld ? x[j] : 0.0;
+        }
+        __syncthreads();
+        const double *xj = &xsj[c0];
+        double tc[CW];
+#pragma unroll
+        for (int u = 0; u < CW; ++u) tc[u] = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const double xi = xs[rg + G * k];
+            double s = q[k][0] * xj[0];
+#pragma unroll
+            for (int u = 1; u < CW; ++u) s = fma(q[k][u], xj[u], s);
+            dl[k][rg][l] = s;
+#pragma unroll
+            for (int u = 0; u < CW; ++u) tc[u] = fma(q[k][u], xi, tc[u]);
+        }
+        if (bi != bj) {
+#pragma unroll
+            for (int u = 0; u < CW; ++u) part[rg][c0 + u] = tc[u];
+        }
+        __syncthreads();
+        if (tid < kSymT) {
+            // row tid = g + G k
+            const int g = tid % G, k = tid / G;
+            double sm = dl[k][g][0];
+#pragma unroll
+            for (int u = 1; u < L; ++u) sm += dl[k][g][u];
+            Do[tid] = sm;
+        } else if (tid < 2 * kSymT && bi != bj) {
+            const int c = tid - kSymT;
+            double sm = part[0][c];
+#pragma unroll
+            for (int g = 1; g < G; ++g) sm += part[g][c];
+            To[c] = sm;
+        }
+        return;
+    }
+    __shared__ double dpart[kSymT];
     // the thread's rows of the tile: every load is issued first
     RawRow<QT, CW> q[R];
 #pragma unroll
