@@ -279,19 +279,19 @@ __device__ __forceinline__ void sym_reduce_body(const double *Dp, const double *
     __shared__ double ps[8][kSymReduceRows];
     const int r = part * kSymReduceRows + (threadIdx.x & (kSymReduceRows - 1));
     const int q = threadIdx.x / kSymReduceRows;
-    // a quarter's parts in increasing tile order, eight loads in flight at a
-    // time (the additions keep that order)
+    // a quarter's parts in increasing tile order, 32 loads in flight at a
+    // time (a whole quarter up to n = 16384; the additions keep that order)
     auto quarter = [&](const double *S, int lo, int hi, bool direct) {
         double s = 0.0;
-        for (int b0 = lo; b0 < hi; b0 += 8) {
-            double v[8];
+        for (int b0 = lo; b0 < hi; b0 += 32) {
+            double v[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 32; ++u) {
                 const int b = b0 + u;
                 v[u] = b < hi ? S[(base + (direct ? sym_tile(bi, b, nb) : sym_tile(b, bi, nb))) * kSymT + r] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < 32; ++u)
                 if (b0 + u < hi) s += v[u];
         }
         return s;
