@@ -882,6 +882,9 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         bool dirty_m = false, dirty_a = false;
         hipStream_t st = nullptr;
         QxTimer tm, ta, ts;
+        // staging of the sparse products' operands (lanes run concurrently)
+        int32_t *stg = nullptr, *stg_aux = nullptr;
+        int64_t stg_passes = 0, stg_passes_aux = 0;
     };
     const int want = prm.lanes == 0 ? (ncol >= kLaneAutoCols ? 2 : 1) : prm.lanes;
     const int nlanes = i8 ? std::max(1, std::min({want, kMaxLanes, ncol})) : 1;
@@ -910,6 +913,13 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
         lanes.emplace_back(new Lane());
         lanes[l]->S = l == 0 ? &S : extra.back().get();
         lanes[l]->ncols = cb[l + 1] - cb[l];
+        if (S.rowptr) {
+            Lane &L = *lanes[l];
+            L.stg_passes = sparse_stage_passes(L.ncols, 1);
+            L.stg_passes_aux = sparse_stage_passes(L.ncols, 2);
+            HIPCHK(S.ar.get((void **)&L.stg, L.stg_passes * ld * 16 * (int64_t)sizeof(int32_t)));
+            HIPCHK(S.ar.get((void **)&L.stg_aux, L.stg_passes_aux * ld * 16 * (int64_t)sizeof(int32_t)));
+        }
     }
     auto pick8 = [&](Lane &L, int cm, int ca) {
         L.p8m.est = std::min({L.ncols, cm + 16, cm + ca});
@@ -1075,9 +1085,10 @@ psdp_status solve_impl(const T *Q, const T *b, int64_t n, const double *X0, cons
                 const Work &lw = LS.w;
                 if (LS.sparse_now) {
                     const SparseJob sm{L->p8m.est > 0, LS.rowptr, LS.pk, n, lw.tw, nullptr, ld, lw.active, lw.nactive,
-                                       ncol, (int64_t *)lw.U, nullptr, ld};
+                                       ncol, (int64_t *)lw.U, nullptr, ld, L->stg, L->stg_passes, L->ncols};
                     const SparseJob sa{L->p8a.est > 0, LS.rowptr, LS.pk, n, lw.tw_hi, lw.tw_lo, ld, lw.active_aux,
-                                       lw.nactive_aux, ncol, (int64_t *)lw.U_aux, lw.U_lo, ld};
+                                       lw.nactive_aux, ncol, (int64_t *)lw.U_aux, lw.U_lo, ld,
+                                       L->stg_aux, L->stg_passes_aux, L->ncols};
                     return launch_sparse(&sm, &sa, L->st);
                 }
                 const DigitJob jm{lw.dig, lw.active, lw.nactive, (int64_t *)lw.U, nullptr, ncol,
@@ -1975,7 +1986,10 @@ psdp_status psdp_qx_sparse(const int32_t *Q, int64_t n, const double *X, int32_t
     iota[B] = B;  // live count
     HIPCHK(ar.get((void **)&act, (size_t)plan.list_len * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(act, iota.data(), (size_t)plan.list_len * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    const SparseJob job{1, rowptr, pk, n, w0, w1, ld, act, act + B, B, U0, U1, ld};
+    int32_t *stage;
+    const int64_t passes = sparse_stage_passes(B, D == 4 ? 1 : 2);
+    HIPCHK(ar.get((void **)&stage, passes * ld * 16 * (int64_t)sizeof(int32_t)));
+    const SparseJob job{1, rowptr, pk, n, w0, w1, ld, act, act + B, B, U0, U1, ld, stage, passes, B};
     HIPCHK(launch_sparse(D == 4 ? &job : nullptr, D == 8 ? &job : nullptr, st));
     HIPCHK(launch_digit_combine(U0, U1, n, ld, B, D, esc, Y, st));
     HIPCHK(hipStreamSynchronize(st));

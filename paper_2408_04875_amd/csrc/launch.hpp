@@ -114,7 +114,12 @@ struct SparseJob {
     int zero_col;            // an all-zero operand column
     int64_t *U0, *U1;        // outputs (U1 for the low half), column c at c * ldu
     int64_t ldu;
+    int32_t *stage;          // staging of the live operands: passes x ldw x 16 words, no initial contents
+    int64_t passes;          // at least sparse_stage_passes(max_live, H), H = 1 (main) or 2 (aux)
+    int max_live;            // largest live count the list may hold (at most zero_col)
 };
+// Passes of 16 operand halves that cols live columns of H halves need.
+int64_t sparse_stage_passes(int cols, int H);
 hipError_t launch_csr_fill(const int8_t *Q8, int64_t ldq, int64_t n, const int32_t *rowptr, uint32_t *pk,
                            hipStream_t st);
 hipError_t launch_sparse(const SparseJob *main4, const SparseJob *aux8, hipStream_t st);
