@@ -267,53 +267,65 @@ __device__ __forceinline__ int64_t sym_tile(int bi, int bj, int nb) {
     return (int64_t)bi * nb - (int64_t)bi * (bi - 1) / 2 + (bj - bi);
 }
 
-// Four blocks per tile row bi, 256 threads each: row r of the block's 32
-// is summed by 8 threads, four over quarters of its direct parts (bj = bi ..
-// nb - 1) and four over quarters of its transposed parts (bk = 0 .. bi - 1),
-// each in increasing tile order; the eight sums are then added in that
-// order (direct quarters, then transposed quarters). part: which of the four
-// 32-row parts of the tile row; tile indices start at base.
+// A block of 256 threads sums 32 RPT rows of tile row bi: row r is summed
+// by 8 threads, four over quarters of its direct parts (bj = bi .. nb - 1)
+// and four over quarters of its transposed parts (bk = 0 .. bi - 1), each in
+// increasing tile order, and the eight sums are then added in that order
+// (direct quarters, then transposed quarters), whatever RPT is and however
+// many loads (UB per row) are in flight. part: which block of 32 RPT rows of
+// the tile row; tile indices start at base.
 constexpr int kSymReduceRows = 32;
+static_assert(kBlock == 8 * kSymReduceRows, "eight summing threads per row");
+template <int RPT, int UB>
 __device__ __forceinline__ void sym_reduce_body(const double *Dp, const double *Tp, int64_t base, int bi, int part,
                                                 int nb, int64_t n, double *y) {
-    __shared__ double ps[8][kSymReduceRows];
-    const int r = part * kSymReduceRows + (threadIdx.x & (kSymReduceRows - 1));
+    constexpr int RB = kSymReduceRows * RPT;
+    __shared__ double ps[8][RB];
+    const int rl = threadIdx.x & (kSymReduceRows - 1);
     const int q = threadIdx.x / kSymReduceRows;
-    // a quarter's parts in increasing tile order, 32 loads in flight at a
-    // time (a whole quarter up to n = 16384; the additions keep that order)
-    auto quarter = [&](const double *S, int lo, int hi, bool direct) {
-        double s = 0.0;
-        for (int b0 = lo; b0 < hi; b0 += 32) {
-            double v[32];
+    // a quarter's parts in increasing tile order, for each of the thread's
+    // rows (rows (part RPT + m) 32 + rl; the additions keep that order)
+    auto quarter = [&](const double *S, int lo, int hi, bool direct, double (&s)[RPT]) {
 #pragma unroll
-            for (int u = 0; u < 32; ++u) {
+        for (int m = 0; m < RPT; ++m) s[m] = 0.0;
+        for (int b0 = lo; b0 < hi; b0 += UB) {
+            double v[UB][RPT];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
                 const int b = b0 + u;
-                v[u] = b < hi ? S[(base + (direct ? sym_tile(bi, b, nb) : sym_tile(b, bi, nb))) * kSymT + r] : 0.0;
+                const int64_t t = b < hi ? base + (direct ? sym_tile(bi, b, nb) : sym_tile(b, bi, nb)) : 0;
+#pragma unroll
+                for (int m = 0; m < RPT; ++m)
+                    v[u][m] = b < hi ? S[t * kSymT + (part * RPT + m) * kSymReduceRows + rl] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 32; ++u)
-                if (b0 + u < hi) s += v[u];
+            for (int u = 0; u < UB; ++u)
+#pragma unroll
+                for (int m = 0; m < RPT; ++m)
+                    if (b0 + u < hi) s[m] += v[u][m];
         }
-        return s;
     };
-    double s;
+    double s[RPT];
     if (q < 4) {
         const int cnt = nb - bi, per = (cnt + 3) / 4;
         const int lo = bi + q * per;
-        s = quarter(Dp, lo, min(nb, lo + per), true);
+        quarter(Dp, lo, min(nb, lo + per), true, s);
     } else {
         const int per = (bi + 3) / 4;
         const int lo = (q - 4) * per;
-        s = quarter(Tp, lo, min(bi, lo + per), false);
+        quarter(Tp, lo, min(bi, lo + per), false, s);
     }
-    ps[q][threadIdx.x & (kSymReduceRows - 1)] = s;
-    __syncthreads();
-    const int64_t i = (int64_t)bi * kSymT + r;
-    if (threadIdx.x < kSymReduceRows && i < n) {
-        double v = ps[0][threadIdx.x];
 #pragma unroll
-        for (int g = 1; g < 8; ++g) v += ps[g][threadIdx.x];
-        y[i] = v;
+    for (int m = 0; m < RPT; ++m) ps[q][m * kSymReduceRows + rl] = s[m];
+    __syncthreads();
+    if (threadIdx.x < RB) {
+        const int64_t i = (int64_t)bi * kSymT + part * RB + threadIdx.x;
+        if (i < n) {
+            double v = ps[0][threadIdx.x];
+#pragma unroll
+            for (int g = 1; g < 8; ++g) v += ps[g][threadIdx.x];
+            y[i] = v;
+        }
     }
 }
 
@@ -321,20 +333,21 @@ __global__ void __launch_bounds__(kBlock) symv_reduce_kernel(const double *Dp, c
                                                              double *y, const int32_t *live) {
     if (live && *live == 0) return;
     constexpr int kParts = kSymT / kSymReduceRows;
-    sym_reduce_body(Dp, Tp, 0, blockIdx.x / kParts, blockIdx.x % kParts, nb, n, y);
+    sym_reduce_body<1, 32>(Dp, Tp, 0, blockIdx.x / kParts, blockIdx.x % kParts, nb, n, y);
 }
 
-// Group reduction: four blocks per entry of the list of the live instances'
-// tile rows (column, bi, vector offset, n, first tile index).
+// Group reduction: one block per entry of the list of the live instances'
+// tile rows (column, bi, vector offset, n, first tile index), each thread
+// taking its quarter of the parts for four rows 32 apart (the instances are
+// small: a quarter holds a few parts), with the single-instance order.
 __global__ void __launch_bounds__(kBlock) symv_group_reduce_kernel(const double *Dp, const double *Tp,
                                                                    const SymGroupRow *rows, int64_t nrows,
                                                                    const Col *col, double *U) {
-    constexpr int kParts = kSymT / kSymReduceRows;
-    const int64_t e = blockIdx.x / kParts;
+    const int64_t e = blockIdx.x;
     if (e >= nrows) return;
     const SymGroupRow d = rows[e];
     if (col[d.col].phase == PH_DONE) return;
-    sym_reduce_body(Dp, Tp, d.base, d.bi, blockIdx.x % kParts, symv_blocks(d.n), d.n, U + d.off);
+    sym_reduce_body<kSymT / kSymReduceRows, 8>(Dp, Tp, d.base, d.bi, 0, symv_blocks(d.n), d.n, U + d.off);
 }
 
 std::vector<int32_t> symv_tile_list(int nb) {
@@ -400,8 +413,8 @@ hipError_t launch_symv_group(int dtype, const SymGroup &g, const Work &w, hipStr
                            st, (const __hip_bfloat16 *)g.P, g.list, g.nlist, w.col, op, g.D, g.T);
     else
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(symv_group_reduce_kernel, dim3((unsigned)(g.nrows * (kSymT / kSymReduceRows))), dim3(kBlock), 0,
-                       st, g.D, g.T, g.rows, g.nrows, w.col, (double *)w.U);
+    hipLaunchKernelGGL(symv_group_reduce_kernel, dim3((unsigned)g.nrows), dim3(kBlock), 0, st, g.D, g.T, g.rows,
+                       g.nrows, w.col, (double *)w.U);
     return hipGetLastError();
 }
 
