@@ -37,7 +37,10 @@ def _sym(n, seed, density, lim=127):
 
 
 @pytest.mark.parametrize("n,B,density", [(1, 1, 1.0), (17, 3, 0.3), (64, 4, 1.0), (65, 5, 0.0),
-                                         (300, 9, 0.05), (777, 6, 0.001), (1000, 4, 0.1)])
+                                         (300, 9, 0.05), (777, 6, 0.001), (1000, 4, 0.1),
+                                         # rows of 65 nonzeros (two rounds of 64 per wave) and
+                                         # several passes of 16 operand halves (B > 16, B > 8)
+                                         (66, 20, 1.0), (300, 37, 0.05)])
 @pytest.mark.parametrize("digits", [4, 8])
 def test_sparse_product_bit_exact(P, n, B, density, digits):
     Q = _sym(n, n * 3 + B, density)
@@ -78,7 +81,7 @@ def _same_solve(a, b):
             assert sa[key] == sb[key], key
 
 
-@pytest.mark.parametrize("case", ["dense64", "sparse1000", "maxcut400"])
+@pytest.mark.parametrize("case", ["dense64", "sparse1000", "maxcut400", "maxcut400_b24_lanes2"])
 def test_solve_with_sparse_products_equals_dense(P, case):
     kw = {}
     if case == "dense64":
@@ -87,10 +90,14 @@ def test_solve_with_sparse_products_equals_dense(P, case):
     elif case == "sparse1000":
         Q, b, X0 = gen.sparse_2500_starts(n=1000, B=8)
     else:
+        # with 24 starts in two lanes of 12 columns: each lane's staging holds
+        # one pass of subproblem columns and two of lambda_min / CG columns
         W = gen.maxcut_graph(400, 9)
         Q, b = W, (-W.sum(axis=1)).astype(np.int32)
-        X0 = gen.random_box_points(400, 4, 5)
+        X0 = gen.random_box_points(400, 24 if case.endswith("lanes2") else 4, 5)
         kw = dict(perturb="diag", sigma=0.5, seed=3)
+        if case.endswith("lanes2"):
+            kw["lanes"] = 2
     on = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", sparse=1, **kw)
     off = P.solve(_t(Q), _t(b), X0=_t(X0), qx_dtype="i8", sparse=0, **kw)
     print(f"{case}: sparse sweeps {on.stats[0]['sparse_sweeps']} of {on.stats[0]['sweeps']}; "
