@@ -72,6 +72,23 @@ def test_sparse_product_rows_empty_and_full(P):
     assert np.array_equal(Y, F.qx_fixed_point(Q, X, 4))
 
 
+def test_sparse_product_benchmark_graph_sampled_rows(P):
+    """The sparse Max-Cut workload the benchmark times (n = 8000, G(n, 0.005)
+    with +-1 weights, 16 columns, the launch shape of its solves): exact
+    against the oracle on 96 sampled rows, subproblem (4-digit) and
+    lambda_min (8-digit) operands."""
+    n, B = 8000, 16
+    W = gen.maxcut_graph(n, 9, 0.005)
+    rng = np.random.default_rng(8000)
+    rows = np.sort(rng.choice(n, 96, replace=False))
+    X = gen.random_box_points(n, B, 5)
+    Y4 = P.qx_digits(_t(W), _t(X), digits=4, sparse=True).cpu().numpy()
+    assert np.array_equal(Y4[:, rows], F.qx_fixed_point(W, X, 4, rows=rows))
+    V = rng.standard_normal((B, n)) * (2.0 ** rng.integers(-20, 20, (B, 1)))
+    Y8 = P.qx_digits(_t(W), _t(V), digits=8, sparse=True).cpu().numpy()
+    assert np.array_equal(Y8[:, rows], F.qx_fixed_point(W, V, 8, rows=rows))
+
+
 def _same_solve(a, b):
     assert np.array_equal(a.X.cpu().numpy(), b.X.cpu().numpy())
     assert np.array_equal(a.obj.cpu().numpy(), b.obj.cpu().numpy())
